@@ -1,0 +1,699 @@
+"""FP64 CPU oracle for the Lyman-alpha forest pair sums.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library may import, call or link
+this module; only the tests, the smoke check and the benchmark's CPU-baseline
+leg use it.  It shares no code, constants or helpers with the HIP path; the
+only thing both sides read is the seeded input generator (``synth``), which
+contains none of the method's arithmetic.
+
+Everything here is plain NumPy in float64, written from the paper:
+
+* the two-point estimator xi_A = sum_A d_i w_i d_j w_j / sum_A w_i w_j over
+  pixel pairs from different forests whose (r_par, r_perp) falls in the
+  rectangular bin A (Sec. 2.1, eq. estimator_two);
+* the distortion matrix D_AB = w_A^-1 sum_{ij in A} w_i w_j
+  sum_{i'j' in B} eta_ii' eta_jj' with eta the per-forest continuum
+  projection built from w and Lambda = log(lambda) (Sec. 2.2, eq. distortion
+  and the eta definition that follows it);
+* the gradient of xi with respect to delta and w, obtained by differentiating
+  the estimator directly.
+
+Where the paper is silent the oracle takes these readings:
+
+* separations: r_par = |D_i - D_j| cos(theta/2), r_perp = (D_i + D_j)
+  sin(theta/2), with sin(theta/2) = |n_f - n_g| / 2 from unit vectors
+  (the decomposition of the pair separation about the mid line of sight; it
+  satisfies r_par^2 + r_perp^2 = |x_i - x_j|^2);
+* bins are half-open [e_k, e_{k+1}); the cut is rectangular; pairs are
+  unordered (each pixel pair once);
+* xi_A = 0 where sum w_i w_j = 0;
+* eta uses the w-weighted mean of Lambda; the slope term is dropped when the
+  weighted spread of Lambda vanishes (S <= 1e-24 W Lambda_bar^2); a forest
+  with zero total weight keeps its deltas (it contributes nothing anyway);
+* D uses a deterministic subset of forest pairs: (f, g) with f < g is kept iff
+  splitmix64(seed XOR (f * 2^32 + g)) < floor(p * 2^64) (p = 1 keeps all);
+  its normalisation w_A sums over the same kept pairs.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+IDENTITY, MEAN, MEAN_SLOPE = 0, 1, 2
+
+# ---------------------------------------------------------------------------
+# geometry (Sec. 2.1: separations parallel and perpendicular to the line of
+# sight, in comoving coordinates)
+# ---------------------------------------------------------------------------
+
+
+def unit_vectors(ra, dec):
+    """Unit vectors (cos dec cos ra, cos dec sin ra, sin dec), shape (N, 3)."""
+    ra = np.asarray(ra, np.float64)
+    dec = np.asarray(dec, np.float64)
+    cd = np.cos(dec)
+    return np.stack([cd * np.cos(ra), cd * np.sin(ra), np.sin(dec)], -1)
+
+
+def pair_sc(nf, ng):
+    """s = sin(theta/2) = |n_f - n_g| / 2 and c = cos(theta/2) = sqrt(1 - s^2).
+
+    The chord form keeps full relative precision at small angles.
+    """
+    nf = np.asarray(nf, np.float64)
+    ng = np.asarray(ng, np.float64)
+    dx = nf[..., 0] - ng[..., 0]
+    dy = nf[..., 1] - ng[..., 1]
+    dz = nf[..., 2] - ng[..., 2]
+    s = 0.5 * np.sqrt((dx * dx + dy * dy) + dz * dz)
+    c = np.sqrt(1.0 - s * s)
+    return s, c
+
+
+def separations(Di, Dj, s, c):
+    """(r_par, r_perp) of pixels at comoving distances Di, Dj (broadcasting)."""
+    Di = np.asarray(Di, np.float64)
+    Dj = np.asarray(Dj, np.float64)
+    return np.abs(Di - Dj) * c, (Di + Dj) * s
+
+
+def bin_index_1d(r, edges):
+    """k with edges[k] <= r < edges[k+1]; -1 outside [edges[0], edges[-1])."""
+    edges = np.asarray(edges, np.float64)
+    k = np.searchsorted(edges, r, side="right") - 1
+    k = np.where((k >= 0) & (k < edges.shape[0] - 1), k, -1)
+    return k
+
+
+def bin_index(rpar, rperp, grid):
+    """Flat bin A = k_par * n_perp + k_perp, or -1 if outside the grid."""
+    kp = bin_index_1d(rpar, grid.edges_par)
+    kt = bin_index_1d(rperp, grid.edges_perp)
+    return np.where((kp >= 0) & (kt >= 0), kp * grid.n_perp + kt, -1)
+
+
+def near_edge(r, edges, tau):
+    """True where r lies within tau of an edge other than a zero lower edge.
+
+    Such pairs may legitimately bin differently under a different but equally
+    valid rounding of the geometry; tests use this to recognise ties.
+    """
+    edges = np.asarray(edges, np.float64)
+    e = edges[1:] if edges[0] == 0.0 else edges
+    k = np.searchsorted(e, r)
+    lo = np.abs(r - e[np.clip(k - 1, 0, e.shape[0] - 1)])
+    hi = np.abs(e[np.clip(k, 0, e.shape[0] - 1)] - r)
+    return np.minimum(lo, hi) <= tau
+
+
+# ---------------------------------------------------------------------------
+# forest pairs (Sec. 2.1: only pairs from different forests; the neighbour
+# pre-ordering only decides which forests are visited, never the result)
+# ---------------------------------------------------------------------------
+
+
+def forest_extents(F):
+    n = F.n_forests
+    dmin = np.empty(n)
+    dmax = np.empty(n)
+    for f in range(n):
+        sl = F.forest_slice(f)
+        if sl.stop > sl.start:
+            dmin[f] = F.dist[sl].min()
+            dmax[f] = F.dist[sl].max()
+        else:
+            dmin[f] = np.inf
+            dmax[f] = -np.inf
+    return dmin, dmax
+
+
+def forest_pairs(F, grid, prune=True):
+    """All unordered (f, g), f < g, of one realisation; optionally pruned.
+
+    The prune drops a pair only when no pixel pair can be in the grid: every
+    r_perp >= (Dmin_f + Dmin_g) s and every r_par >= gap(f, g) c, evaluated
+    with the same floating-point operations as the separations themselves, so
+    the rounding is monotone and the cut is exact.
+    """
+    N = F.n_forests
+    real = F.real_of()
+    n = unit_vectors(F.ra, F.dec)
+    dmin, dmax = forest_extents(F)
+    out = []
+    for f in range(N):
+        g = np.arange(f + 1, N)
+        g = g[real[g] == real[f]]
+        g = g[(F.offsets[g + 1] > F.offsets[g])]
+        if F.offsets[f + 1] == F.offsets[f] or g.size == 0:
+            continue
+        if prune:
+            s, c = pair_sc(n[f][None, :], n[g])
+            rperp_min = (dmin[f] + dmin[g]) * s
+            gap = np.maximum(0.0, np.maximum(dmin[g] - dmax[f], dmin[f] - dmax[g]))
+            rpar_min = gap * c
+            keep = (rperp_min < grid.edges_perp[-1]) & (rpar_min < grid.edges_par[-1])
+            g = g[keep]
+        out.append(np.stack([np.full(g.shape[0], f, np.int64), g.astype(np.int64)], -1))
+    if not out:
+        return np.zeros((0, 2), np.int64)
+    return np.concatenate(out, 0)
+
+
+# ---------------------------------------------------------------------------
+# eta: per-forest continuum projection (Sec. 2.2, the eta_ii' definition)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class EtaParams:
+    W: float
+    lbar: float
+    S: float
+    a: np.ndarray      # Lambda_i - Lambda_bar
+    u: np.ndarray      # w_i / W
+    b: np.ndarray      # w_i a_i / S (0 when the slope term is dropped)
+    slope: bool
+
+
+def eta_params(w, loglam, mode=MEAN_SLOPE) -> EtaParams:
+    """Weighted sums that define eta_ii' = delta_ii' - u_i' - a_i b_i'."""
+    w = np.asarray(w, np.float64)
+    L = np.asarray(loglam, np.float64)
+    n = w.shape[0]
+    W = float(np.sum(w))
+    if mode == IDENTITY or W == 0.0 or n == 0:
+        z = np.zeros(n)
+        return EtaParams(W, 0.0, 0.0, z, z.copy(), z.copy(), False)
+    lbar = float(np.sum(w * L) / W)
+    a = L - lbar
+    S = float(np.sum(w * a * a))
+    u = w / W
+    slope = mode == MEAN_SLOPE and S > 1e-24 * W * lbar * lbar
+    b = w * a / S if slope else np.zeros(n)
+    return EtaParams(W, lbar, S, a, u, b, slope)
+
+
+def eta_matrix(w, loglam, mode=MEAN_SLOPE):
+    """Dense eta for one forest (brute-force reference)."""
+    w = np.asarray(w, np.float64)
+    n = w.shape[0]
+    if mode == IDENTITY or n == 0 or np.sum(w) == 0.0:
+        return np.eye(n)
+    P = eta_params(w, loglam, mode)
+    eta = np.eye(n) - P.u[None, :]
+    if P.slope:
+        eta = eta - P.a[:, None] * P.b[None, :]
+    return eta
+
+
+def project_forest(delta, w, loglam, mode=MEAN_SLOPE):
+    """(eta delta)_i = delta_i - sum_i' u_i' delta_i' - a_i sum_i' b_i' delta_i'."""
+    delta = np.asarray(delta, np.float64)
+    if mode == IDENTITY:
+        return delta.copy()
+    P = eta_params(w, loglam, mode)
+    if P.W == 0.0:
+        return delta.copy()
+    out = delta - np.sum(P.u * delta)
+    if P.slope:
+        out = out - P.a * np.sum(P.b * delta)
+    return out
+
+
+def projected_deltas(F, mode=MEAN_SLOPE):
+    out = np.empty_like(F.delta)
+    for f in range(F.n_forests):
+        sl = F.forest_slice(f)
+        out[sl] = project_forest(F.delta[sl], F.weight[sl], F.loglam[sl], mode)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# compensated accumulation of per-forest partial histograms
+# ---------------------------------------------------------------------------
+
+
+class _Neumaier:
+    """Element-wise Neumaier (improved Kahan) summation of arrays."""
+
+    def __init__(self, shape):
+        self.s = np.zeros(shape)
+        self.c = np.zeros(shape)
+
+    def add(self, x, where=None):
+        if where is not None:
+            s = self.s[where]
+            t = s + x
+            self.c[where] += np.where(np.abs(s) >= np.abs(x), (s - t) + x, (x - t) + s)
+            self.s[where] = t
+            return
+        t = self.s + x
+        self.c += np.where(np.abs(self.s) >= np.abs(x), (self.s - t) + x, (x - t) + self.s)
+        self.s = t
+
+    def value(self):
+        return self.s + self.c
+
+
+# ---------------------------------------------------------------------------
+# xi sums (Sec. 2.1, eq. estimator_two)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class XiSums:
+    num: np.ndarray      # [R, n_bins]  sum w_i d_i w_j d_j
+    wsum: np.ndarray     # [R, n_bins]  sum w_i w_j
+    npairs: np.ndarray   # [R, n_bins]  pair counts (int64)
+    absnum: np.ndarray   # [R, n_bins]  sum |w_i d_i w_j d_j| (conditioning)
+    n_near_edge: int     # pairs within tau of an interior or upper edge
+
+    @property
+    def xi(self):
+        return xi_from_sums(self.num, self.wsum)
+
+
+def xi_from_sums(num, wsum):
+    num = np.asarray(num, np.float64)
+    wsum = np.asarray(wsum, np.float64)
+    out = np.zeros_like(num)
+    nz = wsum != 0.0
+    out[nz] = num[nz] / wsum[nz]
+    return out
+
+
+def _partner_arrays(F, g_list, n_vec, nf_vec):
+    """Concatenate the pixels of forests g_list with their per-pair (s, c)."""
+    starts = F.offsets[g_list]
+    counts = F.offsets[g_list + 1] - starts
+    idx = np.concatenate([np.arange(a, a + k) for a, k in zip(starts, counts)])
+    s, c = pair_sc(nf_vec[None, :], n_vec[g_list])
+    return idx, np.repeat(s, counts), np.repeat(c, counts)
+
+
+def _chunks_by_pixels(F, g_list, budget):
+    out, cur, tot = [], [], 0
+    for g in g_list:
+        k = int(F.offsets[g + 1] - F.offsets[g])
+        if cur and tot + k > budget:
+            out.append(np.array(cur, np.int64))
+            cur, tot = [], 0
+        cur.append(g)
+        tot += k
+    if cur:
+        out.append(np.array(cur, np.int64))
+    return out
+
+
+def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
+            edge_tau=1e-9, pairs=None, chunk_elems=2_000_000) -> XiSums:
+    """Pair sums of eq. estimator_two for every realisation.
+
+    For each forest f the pixels of all its partners g > f are concatenated
+    and the n_f x sum(n_g) separations are binned at once; the per-forest
+    partial histograms are combined with Neumaier summation so the result is
+    accurate to a few ulps of sum |terms| per bin.
+    """
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    delta = projected_deltas(F, eta_mode) if project else F.delta
+    wd = F.weight * delta
+    n_vec = unit_vectors(F.ra, F.dec)
+    real = F.real_of()
+    num = _Neumaier((R, nb))
+    wsum = _Neumaier((R, nb))
+    absn = _Neumaier((R, nb))
+    npairs = np.zeros((R, nb), np.int64)
+    n_near = 0
+    if pairs is None:
+        pairs = forest_pairs(F, grid, prune)
+    if pairs.shape[0] == 0:
+        return XiSums(num.value(), wsum.value(), npairs, absn.value(), 0)
+    order = np.argsort(pairs[:, 0], kind="stable")
+    pairs = pairs[order]
+    firsts, starts = np.unique(pairs[:, 0], return_index=True)
+    ends = np.append(starts[1:], pairs.shape[0])
+    for f, a, b in zip(firsts, starts, ends):
+        sl = F.forest_slice(int(f))
+        nf = sl.stop - sl.start
+        r = int(real[f])
+        budget = max(1, chunk_elems // max(nf, 1))
+        for gch in _chunks_by_pixels(F, pairs[a:b, 1], budget):
+            idx, s, c = _partner_arrays(F, gch, n_vec, n_vec[f])
+            rpar, rperp = separations(F.dist[sl][:, None], F.dist[idx][None, :], s[None, :], c[None, :])
+            A = bin_index(rpar, rperp, grid)
+            m = A >= 0
+            if edge_tau > 0:
+                near = (near_edge(rpar, grid.edges_par, edge_tau * np.maximum(1.0, rpar))
+                        | near_edge(rperp, grid.edges_perp, edge_tau * np.maximum(1.0, rperp)))
+                inside = (rpar < grid.edges_par[-1] + 1.0) & (rperp < grid.edges_perp[-1] + 1.0)
+                n_near += int(np.count_nonzero(near & inside))
+            Am = A[m]
+            prod = (wd[sl][:, None] * wd[idx][None, :])[m]
+            ww = (F.weight[sl][:, None] * F.weight[idx][None, :])[m]
+            num.add(np.bincount(Am, weights=prod, minlength=nb), where=(r,))
+            wsum.add(np.bincount(Am, weights=ww, minlength=nb), where=(r,))
+            absn.add(np.bincount(Am, weights=np.abs(prod), minlength=nb), where=(r,))
+            npairs[r] += np.bincount(Am, minlength=nb)
+    return XiSums(num.value(), wsum.value(), npairs, absn.value(), n_near)
+
+
+def xi_pairs_brute(F, grid, delta=None):
+    """Pure-Python triple loop over pixel pairs of different forests (tiny inputs)."""
+    import math
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    if delta is None:
+        delta = F.delta
+    real = F.real_of()
+    n = unit_vectors(F.ra, F.dec)
+    num = [[[] for _ in range(nb)] for _ in range(R)]
+    ws = [[[] for _ in range(nb)] for _ in range(R)]
+    cnt = np.zeros((R, nb), np.int64)
+    N = F.n_forests
+    for f in range(N):
+        for g in range(f + 1, N):
+            if real[f] != real[g]:
+                continue
+            s, c = pair_sc(n[f], n[g])
+            s, c = float(s), float(c)
+            for i in range(F.offsets[f], F.offsets[f + 1]):
+                for j in range(F.offsets[g], F.offsets[g + 1]):
+                    rpar = abs(float(F.dist[i]) - float(F.dist[j])) * c
+                    rperp = (float(F.dist[i]) + float(F.dist[j])) * s
+                    kp = int(bin_index_1d(np.array([rpar]), grid.edges_par)[0])
+                    kt = int(bin_index_1d(np.array([rperp]), grid.edges_perp)[0])
+                    if kp < 0 or kt < 0:
+                        continue
+                    A = kp * grid.n_perp + kt
+                    rr = int(real[f])
+                    num[rr][A].append(float(F.weight[i]) * float(delta[i]) * float(F.weight[j]) * float(delta[j]))
+                    ws[rr][A].append(float(F.weight[i]) * float(F.weight[j]))
+                    cnt[rr, A] += 1
+    N_ = np.array([[math.fsum(v) for v in row] for row in num])
+    W_ = np.array([[math.fsum(v) for v in row] for row in ws])
+    return N_, W_, cnt
+
+
+# ---------------------------------------------------------------------------
+# distortion matrix (Sec. 2.2, eq. distortion)
+# ---------------------------------------------------------------------------
+
+
+def splitmix64(x):
+    """SplitMix64 output for state x (Steele, Lea & Flood 2014; Vigna's
+    reference form): z = x + 0x9E3779B97F4A7C15, then two xor-shift-multiply
+    rounds and a final xor-shift.  uint64 arrays, wrapping arithmetic."""
+    x = np.asarray(x, np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def keep_threshold(p):
+    """floor(p * 2^64) as a Python int (None means keep every pair)."""
+    if p >= 1.0:
+        return None
+    return int(np.ldexp(np.float64(p), 64))
+
+
+def keep_pair_mask(f, g, p, seed):
+    thr = keep_threshold(p)
+    f = np.asarray(f, np.uint64)
+    g = np.asarray(g, np.uint64)
+    if thr is None:
+        return np.ones(np.broadcast(f, g).shape, bool)
+    key = (f << np.uint64(32)) | g
+    h = splitmix64(np.uint64(seed) ^ key)
+    return h < np.uint64(thr)
+
+
+def dmat_pairs(F, grid, keep_fraction=1.0, seed=0, prune=True):
+    pairs = forest_pairs(F, grid, prune)
+    if pairs.shape[0] == 0:
+        return pairs
+    return pairs[keep_pair_mask(pairs[:, 0], pairs[:, 1], keep_fraction, seed)]
+
+
+def _pair_bins(F, grid, f, g, n_vec):
+    sf, sg = F.forest_slice(f), F.forest_slice(g)
+    s, c = pair_sc(n_vec[f], n_vec[g])
+    rpar, rperp = separations(F.dist[sf][:, None], F.dist[sg][None, :], s, c)
+    return bin_index(rpar, rperp, grid)
+
+
+@dataclass
+class DmatResult:
+    num: np.ndarray   # [R, nb, nb]
+    wd: np.ndarray    # [R, nb]
+
+    @property
+    def D(self):
+        out = np.zeros_like(self.num)
+        nz = self.wd != 0.0
+        for r in range(self.num.shape[0]):
+            out[r][nz[r]] = self.num[r][nz[r]] / self.wd[r][nz[r]][:, None]
+        return out
+
+
+def dmat_brute(F, grid, pairs, eta_mode=MEAN_SLOPE):
+    """Eq. distortion written out as four nested sums (tiny inputs only)."""
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    num = np.zeros((R, nb, nb))
+    wd = np.zeros((R, nb))
+    real = F.real_of()
+    n_vec = unit_vectors(F.ra, F.dec)
+    for f, g in pairs:
+        f, g = int(f), int(g)
+        r = int(real[f])
+        sf, sg = F.forest_slice(f), F.forest_slice(g)
+        A = _pair_bins(F, grid, f, g, n_vec)
+        ef = eta_matrix(F.weight[sf], F.loglam[sf], eta_mode)
+        eg = eta_matrix(F.weight[sg], F.loglam[sg], eta_mode)
+        wf, wg = F.weight[sf], F.weight[sg]
+        nf, ng = wf.shape[0], wg.shape[0]
+        for i in range(nf):
+            for j in range(ng):
+                a = A[i, j]
+                if a < 0:
+                    continue
+                wd[r, a] += wf[i] * wg[j]
+                for ip in range(nf):
+                    for jp in range(ng):
+                        b = A[ip, jp]
+                        if b < 0:
+                            continue
+                        num[r, a, b] += wf[i] * wg[j] * ef[i, ip] * eg[j, jp]
+    return DmatResult(num, wd)
+
+
+def dmat_definition(F, grid, pairs, eta_mode=MEAN_SLOPE):
+    """Eq. distortion with the inner double sum done as eta_f M^B eta_g^T.
+
+    M^B[i', j'] = 1 when pixel pair (i', j') falls in bin B, so
+    sum_{i'j' in B} eta_ii' eta_jj' = (eta_f M^B eta_g^T)[i, j]; the outer
+    sum over (i, j) in A is then a weighted histogram.  Small inputs only.
+    """
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    num = np.zeros((R, nb, nb))
+    wd = np.zeros((R, nb))
+    real = F.real_of()
+    n_vec = unit_vectors(F.ra, F.dec)
+    for f, g in pairs:
+        f, g = int(f), int(g)
+        r = int(real[f])
+        sf, sg = F.forest_slice(f), F.forest_slice(g)
+        A = _pair_bins(F, grid, f, g, n_vec)
+        m = A >= 0
+        if not m.any():
+            continue
+        ef = eta_matrix(F.weight[sf], F.loglam[sf], eta_mode)
+        eg = eta_matrix(F.weight[sg], F.loglam[sg], eta_mode)
+        ww = F.weight[sf][:, None] * F.weight[sg][None, :]
+        wd[r] += np.bincount(A[m], weights=ww[m], minlength=nb)
+        for B in np.unique(A[m]):
+            MB = (A == B).astype(np.float64)
+            PB = ef @ MB @ eg.T
+            num[r, :, B] += np.bincount(A[m], weights=(ww * PB)[m], minlength=nb)
+    return DmatResult(num, wd)
+
+
+def dmat(F, grid, pairs, eta_mode=MEAN_SLOPE):
+    """Eq. distortion in factorised form (pinned against the two above).
+
+    With eta_ii' = delta_ii' - p_i . q_i', p_i = (1, a_i), q_i' = (u_i', b_i'):
+      num_AB = w_A^{fg} delta_AB
+             - sum_i w_i sum_l R^l_i[A] G^l_i[B]     (i fixed, j and j' vary)
+             - sum_j w_j sum_k C^k_j[A] F^k_j[B]     (j fixed, i and i' vary)
+             + sum_kl H^kl_A Q^kl_B
+    R^l_i[A] = sum_{j: beta(i,j)=A} w_j p_j^l, G^l_i[B] = sum_{j': beta(i,j')=B} q_j'^l,
+    C, F likewise over i, H^kl_A = sum_{beta=A} w_i p_i^k w_j p_j^l,
+    Q^kl_B = sum_{beta=B} q_i^k q_j^l.
+    """
+    R_ = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    num = np.zeros((R_, nb, nb))
+    wd = np.zeros((R_, nb))
+    real = F.real_of()
+    n_vec = unit_vectors(F.ra, F.dec)
+    cache = {}
+
+    def params(f):
+        if f not in cache:
+            sl = F.forest_slice(f)
+            P = eta_params(F.weight[sl], F.loglam[sl], eta_mode)
+            w = F.weight[sl]
+            if eta_mode == IDENTITY or P.W == 0.0:
+                p = np.zeros((w.shape[0], 2))
+                q = np.zeros((w.shape[0], 2))
+            else:
+                p = np.stack([np.ones(w.shape[0]), P.a], -1)
+                q = np.stack([P.u, P.b], -1)
+            cache[f] = (w, p, q)
+        return cache[f]
+
+    for f, g in pairs:
+        f, g = int(f), int(g)
+        r = int(real[f])
+        A = _pair_bins(F, grid, f, g, n_vec)
+        m = A >= 0
+        if not m.any():
+            continue
+        wf, pf, qf = params(f)
+        wg, pg, qg = params(g)
+        nf, ng = wf.shape[0], wg.shape[0]
+        touched = np.unique(A[m])
+        T = touched.shape[0]
+        loc = np.full(nb, -1, np.int64)
+        loc[touched] = np.arange(T)
+        ii, jj = np.nonzero(m)
+        la = loc[A[ii, jj]]
+        row_key = ii * T + la
+        col_key = jj * T + la
+        blk = np.zeros((T, T))
+        for l in range(2):
+            Rl = np.bincount(row_key, weights=wg[jj] * pg[jj, l], minlength=nf * T).reshape(nf, T)
+            Gl = np.bincount(row_key, weights=qg[jj, l], minlength=nf * T).reshape(nf, T)
+            blk -= (Rl * wf[:, None]).T @ Gl
+            Cl = np.bincount(col_key, weights=wf[ii] * pf[ii, l], minlength=ng * T).reshape(ng, T)
+            Fl = np.bincount(col_key, weights=qf[ii, l], minlength=ng * T).reshape(ng, T)
+            blk -= (Cl * wg[:, None]).T @ Fl
+        H00 = None
+        for k in range(2):
+            for l in range(2):
+                H = np.bincount(la, weights=wf[ii] * pf[ii, k] * wg[jj] * pg[jj, l], minlength=T)
+                Q = np.bincount(la, weights=qf[ii, k] * qg[jj, l], minlength=T)
+                blk += np.outer(H, Q)
+        H00 = np.bincount(la, weights=wf[ii] * wg[jj], minlength=T)
+        blk[np.arange(T), np.arange(T)] += H00
+        num[r][np.ix_(touched, touched)] += blk
+        wd[r, touched] += H00
+    return DmatResult(num, wd)
+
+
+# ---------------------------------------------------------------------------
+# gradient of xi (differentiating eq. estimator_two)
+# ---------------------------------------------------------------------------
+
+
+def xi_grad(F, grid, grad_xi, xi, wsum, pairs=None, prune=True):
+    """Back-propagate dL/dxi_A to delta and w (deltas taken as given).
+
+    With gamma_A = (dL/dxi_A) / W_A (0 where W_A = 0):
+      dL/d delta_i = w_i sum_j gamma_{beta(i,j)} w_j delta_j
+      dL/d w_i     = sum_j gamma_{beta(i,j)} w_j (delta_i delta_j - xi_{beta(i,j)})
+    summed over every partner pixel j of every other forest (both orders).
+    """
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    grad_xi = np.asarray(grad_xi, np.float64).reshape(R, nb)
+    xi = np.asarray(xi, np.float64).reshape(R, nb)
+    wsum = np.asarray(wsum, np.float64).reshape(R, nb)
+    gamma = np.zeros((R, nb))
+    nz = wsum != 0.0
+    gamma[nz] = grad_xi[nz] / wsum[nz]
+    gx = gamma * xi
+    gd = np.zeros(F.n_pix)
+    gw = np.zeros(F.n_pix)
+    real = F.real_of()
+    n_vec = unit_vectors(F.ra, F.dec)
+    if pairs is None:
+        pairs = forest_pairs(F, grid, prune)
+    wdel = F.weight * F.delta
+    for f, g in pairs:
+        f, g = int(f), int(g)
+        r = int(real[f])
+        sf, sg = F.forest_slice(f), F.forest_slice(g)
+        A = _pair_bins(F, grid, f, g, n_vec)
+        m = A >= 0
+        if not m.any():
+            continue
+        Ac = np.where(m, A, 0)
+        Gm = np.where(m, gamma[r][Ac], 0.0)
+        GXm = np.where(m, gx[r][Ac], 0.0)
+        t_f = Gm @ wdel[sg]
+        t_g = Gm.T @ wdel[sf]
+        gd[sf] += F.weight[sf] * t_f
+        gd[sg] += F.weight[sg] * t_g
+        gw[sf] += F.delta[sf] * t_f - GXm @ F.weight[sg]
+        gw[sg] += F.delta[sg] * t_g - GXm.T @ F.weight[sf]
+    return gd, gw
+
+
+def loss(xi, target):
+    """L = sum_A (xi_A - m_A)^2."""
+    d = np.asarray(xi, np.float64).ravel() - np.asarray(target, np.float64).ravel()
+    return float(np.sum(d * d))
+
+
+def loss_grad_xi(xi, target):
+    return 2.0 * (np.asarray(xi, np.float64) - np.asarray(target, np.float64).reshape(np.shape(xi)))
+
+
+# ---------------------------------------------------------------------------
+# error metrics used by the parity tests
+# ---------------------------------------------------------------------------
+
+
+def err_xi(xi_test, xi_ref, wsum_ref, absnum_ref):
+    """max_A |dxi_A| W_A / sum_A |w d w d| (relative to the bin's condition)."""
+    xi_test = np.asarray(xi_test, np.float64)
+    m = np.asarray(absnum_ref) > 0
+    if not m.any():
+        return 0.0
+    return float(np.max(np.abs(xi_test - xi_ref)[m] * np.asarray(wsum_ref)[m] / np.asarray(absnum_ref)[m]))
+
+
+def err_rel(test, ref):
+    """max |d| / |ref| over entries with ref != 0 (and test must be 0 elsewhere)."""
+    test = np.asarray(test, np.float64)
+    ref = np.asarray(ref, np.float64)
+    m = ref != 0
+    e = 0.0
+    if m.any():
+        e = float(np.max(np.abs(test[m] - ref[m]) / np.abs(ref[m])))
+    if (~m).any():
+        e = max(e, float(np.max(np.abs(test[~m]))) if np.any(test[~m]) else 0.0)
+    return e
+
+
+def err_rows(test, ref):
+    """max_A max_B |dD_AB| / max_B |D_AB| (row-normwise)."""
+    test = np.asarray(test, np.float64)
+    ref = np.asarray(ref, np.float64)
+    scale = np.max(np.abs(ref), axis=-1, keepdims=True)
+    scale = np.where(scale == 0, 1.0, scale)
+    return float(np.max(np.abs(test - ref) / scale))
+
+
+def err_norm(test, ref):
+    """max |d| / max |ref| (normwise)."""
+    ref = np.asarray(ref, np.float64)
+    s = float(np.max(np.abs(ref)))
+    return float(np.max(np.abs(np.asarray(test, np.float64) - ref)) / (s if s else 1.0))
