@@ -1,0 +1,184 @@
+/*
+ * lya.h -- C ABI of the MI355X Lyman-alpha pair-accumulation library.
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950):
+ *   - the weighted pixel-pair sums behind the two-point estimator
+ *       xi_A = sum_A delta_i w_i delta_j w_j / sum_A w_i w_j
+ *     over every pair of pixels (i, j) from different forests whose
+ *     separation (r_par, r_perp) lies in the rectangular bin A
+ *     (arXiv:2507.00129, Sec. 2.1, eq. estimator_two);
+ *   - the distortion matrix D_AB = w_A^-1 sum_{ij in A} w_i w_j
+ *       sum_{i'j' in B} eta_ii' eta_jj'
+ *     with eta the per-forest continuum projection built from w and
+ *     Lambda = log(lambda) (Sec. 2.2, eq. distortion and the eta definition);
+ *   - the gradient of xi with respect to delta and w for a caller-supplied
+ *     dL/dxi.
+ *
+ * Geometry.  Forest f has a sky direction n_f (from ra, dec).  With
+ * s = |n_f - n_g| / 2 = sin(theta/2) and c = sqrt(1 - s^2), a pixel pair at
+ * comoving distances D_i, D_j has r_par = |D_i - D_j| c and
+ * r_perp = (D_i + D_j) s.  Bins are half-open, [e_k, e_{k+1}) on both axes;
+ * a pair is in the grid iff both axes are.  The flat bin index is
+ * A = k_par * n_perp + k_perp.  Pairs are unordered: each pixel pair from two
+ * different forests of the same realisation is counted once.
+ *
+ * Memory.  Every pointer in lya_forests and every output pointer is a DEVICE
+ * pointer on the device the context was created for; the grid edges are HOST
+ * pointers.  All memory is owned by the caller; the library never frees
+ * caller memory and keeps no caller pointer after the call returns.  Work is
+ * enqueued on the caller's stream (a hipStream_t passed as void*, NULL = the
+ * default stream); each call synchronises that stream a few times to size
+ * its work lists, and returns once all of its work has been enqueued.
+ * Outputs are fully overwritten (the library zeroes them first).
+ *
+ * Errors.  Every call returns a status; nothing aborts and nothing throws.
+ * Arguments are checked before any work is enqueued; with
+ * lya_options.validate set, array contents are checked on the device too
+ * (offsets, finiteness, signs, realisation ids).  lya_last_error() returns a
+ * human-readable message for the last failure on a context.
+ *
+ * Threading.  A context may be used by one host thread at a time.  Two
+ * contexts may run concurrently.
+ */
+#ifndef LYA_H
+#define LYA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LYA_OK = 0,
+  LYA_E_INVALID = 1,     /* bad argument or bad array contents */
+  LYA_E_NOMEM = 2,       /* device workspace allocation failed */
+  LYA_E_DEVICE = 3,      /* a HIP call failed */
+  LYA_E_UNSUPPORTED = 4  /* valid input this build cannot handle (see message) */
+} lya_status;
+
+typedef enum {
+  /* Pair geometry and products in FP32 (distances re-centred so that
+     FP32 keeps ~1e-4 Mpc/h); pairs within rounding of a bin edge are re-binned
+     in FP64, so binning equals the FP64 decision; sums are accumulated with
+     error compensation into FP64 totals.  Per-forest projection sums and the
+     final normalisation are FP64. */
+  LYA_FP32_COMP = 0,
+  /* Everything in FP64. */
+  LYA_FP64 = 1
+} lya_precision;
+
+typedef enum {
+  LYA_ETA_IDENTITY = 0,   /* eta = I */
+  LYA_ETA_MEAN = 1,       /* eta_ii' = delta_ii' - w_i'/W_f */
+  LYA_ETA_MEAN_SLOPE = 2  /* ... - (L_i - Lbar) w_i' (L_i' - Lbar) / S_f   (Sec. 2.2) */
+} lya_eta;
+
+/* Forests in CSR layout (Sec. 3.1: one sky position and a variable-length
+   table of delta, w and lambda per forest).  Pixels of forest f are
+   offsets[f] .. offsets[f+1]-1. */
+typedef struct {
+  int64_t n_forests;          /* >= 0 */
+  int64_t n_pix;              /* == offsets[n_forests] (checked when validating) */
+  const int64_t *offsets;     /* [n_forests + 1], offsets[0] == 0, non-decreasing */
+  const double *ra;           /* [n_forests] right ascension, radians */
+  const double *dec;          /* [n_forests] declination, radians */
+  const double *dist;         /* [n_pix] comoving distance, Mpc/h, > 0 */
+  const double *delta;        /* [n_pix] flux fluctuation */
+  const double *weight;       /* [n_pix] >= 0; w = 0 masks a pixel out */
+  const double *loglam;       /* [n_pix] log(lambda), any base (eta only) */
+  const int32_t *realisation; /* [n_forests] in [0, n_realisations), or NULL (all 0) */
+  int32_t n_realisations;     /* >= 1; outputs are stacked per realisation */
+} lya_forests;
+
+/* Bin edges (HOST pointers), strictly increasing, finite, edges[0] >= 0.
+   This build requires uniformly spaced edges on each axis (to 1e-9 of a
+   bin); other grids return LYA_E_UNSUPPORTED.  n_par * n_perp <= 4096. */
+typedef struct {
+  int32_t n_par;
+  int32_t n_perp;
+  const double *edges_par;   /* [n_par + 1] */
+  const double *edges_perp;  /* [n_perp + 1] */
+} lya_grid;
+
+typedef struct {
+  int32_t precision;          /* lya_precision */
+  int32_t eta;                /* lya_eta: projection used by lya_dmat and project_deltas */
+  int32_t project_deltas;     /* lya_xi: replace delta by eta delta per forest first */
+  int32_t autotune;           /* pick kernel variants by timing them on this input */
+  int32_t validate;           /* check array contents on the device (one extra sync) */
+  int32_t timing;             /* record per-stage device times (see lya_stats) */
+  int32_t variant;            /* >= 0 forces that kernel variant; -1 lets the
+                                 autotuner (or the default) choose */
+  int32_t reserved;           /* must be 0 */
+  double dmat_keep_fraction;  /* lya_dmat: keep forest pair (f<g) iff
+                                 splitmix64(seed ^ (f<<32 | g)) < floor(p * 2^64);
+                                 p in (0, 1], p = 1 keeps all (Sec. 2.2: D on a
+                                 subset of forest pairs) */
+  uint64_t seed;
+} lya_options;
+
+/* What the last call on a context did. */
+typedef struct {
+  int64_t forest_pairs;       /* unordered forest pairs in the work list */
+  int64_t work_items;         /* persistent-kernel work items */
+  int64_t candidate_pairs;    /* pixel pairs evaluated (sum n_f n_g over the list) */
+  int32_t variant;            /* kernel variant index used for the main kernel */
+  int32_t grid_blocks;        /* persistent workgroups launched */
+  /* device milliseconds per stage, filled when options.timing != 0 */
+  float ms_precompute, ms_worklist, ms_main, ms_finalize;
+} lya_stats;
+
+typedef struct lya_context lya_context;
+
+/* Fills *opts with defaults: FP32_COMP, MEAN_SLOPE, no projection,
+   autotune on, validate on, timing off, variant -1, keep fraction 1, seed 0. */
+void lya_options_default(lya_options *opts);
+
+/* Creates a context bound to HIP device `device`.  The context owns a
+   grow-only device workspace and the autotuner's cache. */
+lya_status lya_create(lya_context **ctx, int device);
+void lya_destroy(lya_context *ctx);
+const char *lya_last_error(const lya_context *ctx);
+lya_status lya_last_stats(const lya_context *ctx, lya_stats *out);
+
+/* Pair sums and xi (Sec. 2.1, eq. estimator_two).  Outputs, each
+   [n_realisations * n_bins] row-major by realisation, device:
+     num[A]    = sum_A w_i delta_i w_j delta_j
+     wsum[A]   = sum_A w_i w_j
+     npairs[A] = number of pixel pairs in A (any weight)
+     xi[A]     = num[A] / wsum[A], 0 where wsum[A] == 0   (may be NULL)
+   With project_deltas, delta is first replaced per forest by eta delta
+   (eta of options.eta). */
+lya_status lya_xi(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                  const lya_options *opts, void *stream,
+                  double *num, double *wsum, int64_t *npairs, double *xi);
+
+/* Distortion matrix (Sec. 2.2, eq. distortion) over the forest pairs kept by
+   options.dmat_keep_fraction / seed, with eta of options.eta.  Outputs,
+   device:
+     dmat[r][A][B] = D_AB of realisation r, [n_realisations * n_bins * n_bins]
+     wsum_d[r][A]  = w_A over the kept pairs, [n_realisations * n_bins]
+   Rows with wsum_d == 0 are zero.  delta is not read. */
+lya_status lya_dmat(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                    const lya_options *opts, void *stream,
+                    double *dmat, double *wsum_d);
+
+/* Gradient of a scalar L(xi) with respect to delta and w (deltas taken as
+   given: project_deltas must be 0).  Inputs grad_xi = dL/dxi, xi and wsum
+   as produced by lya_xi, each [n_realisations * n_bins], device.  Outputs
+   [n_pix], device:
+     grad_delta[i]  = w_i sum_j gamma_{A(i,j)} w_j delta_j
+     grad_weight[i] = sum_j gamma_{A(i,j)} w_j (delta_i delta_j - xi_{A(i,j)})
+   with gamma_A = grad_xi[A] / wsum[A] (0 where wsum[A] == 0) and j over every
+   pixel of every other forest of the same realisation. */
+lya_status lya_xi_backward(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                           const lya_options *opts, void *stream,
+                           const double *grad_xi, const double *xi, const double *wsum,
+                           double *grad_delta, double *grad_weight);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LYA_H */

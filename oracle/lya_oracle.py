@@ -268,7 +268,7 @@ class XiSums:
     wsum: np.ndarray     # [R, n_bins]  sum w_i w_j
     npairs: np.ndarray   # [R, n_bins]  pair counts (int64)
     absnum: np.ndarray   # [R, n_bins]  sum |w_i d_i w_j d_j| (conditioning)
-    n_near_edge: int     # pairs within tau of an interior or upper edge
+    n_near_edge: int     # pairs within edge_tau * max(1, r) of an interior or upper edge
 
     @property
     def xi(self):
@@ -308,7 +308,7 @@ def _chunks_by_pixels(F, g_list, budget):
 
 
 def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
-            edge_tau=1e-9, pairs=None, chunk_elems=2_000_000) -> XiSums:
+            edge_tau=1e-12, pairs=None, chunk_elems=2_000_000) -> XiSums:
     """Pair sums of eq. estimator_two for every realisation.
 
     For each forest f the pixels of all its partners g > f are concatenated

@@ -1,0 +1,182 @@
+// Forest-pair work list (the neighbourhood pre-ordering of Sec. 2.1).
+//
+// Forests are sorted by (realisation, declination strip, right ascension).
+// The strip height is at least the largest angle theta_max at which any pixel
+// pair can still have r_perp inside the grid, so every neighbour of a forest
+// lies in its own strip or the two adjacent ones.  For the forest at sorted
+// position p the candidates form one contiguous range of sorted positions;
+// each candidate is kept by the exact conservative cut pair_may_bin.
+#include <hipcub/hipcub.hpp>
+
+#include "lya_common.h"
+
+namespace lya {
+
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+
+__global__ void keys_kernel(WorklistArgs a) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.n_forests) return;
+  const double dec = a.dec[f];
+  int strip = (int)floor((dec + 0.5 * kPi) / a.strip_h);
+  strip = strip < 0 ? 0 : (strip >= a.n_strips ? a.n_strips - 1 : strip);
+  double t = a.ra[f] / (2.0 * kPi);
+  t -= floor(t);
+  uint32_t raq = (uint32_t)fmin(t * 4294967296.0, 4294967295.0);
+  const uint64_t real = (uint64_t)a.finfo[f].real;
+  a.keys[f] = (real << 44) | ((uint64_t)strip << 32) | raq;
+  a.ids[f] = (int32_t)f;
+}
+
+__device__ __forceinline__ int cell_of(uint64_t key, int n_strips) {
+  return (int)(key >> 44) * n_strips + (int)((key >> 32) & 0xFFF);
+}
+
+__global__ void cells_kernel(WorklistArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_forests) return;
+  const int c = cell_of(a.keys_sorted[p], a.n_strips);
+  if (p == 0 || cell_of(a.keys_sorted[p - 1], a.n_strips) != c) a.cell_begin[c] = (int32_t)p;
+  if (p == a.n_forests - 1 || cell_of(a.keys_sorted[p + 1], a.n_strips) != c) a.cell_end[c] = (int32_t)(p + 1);
+}
+
+// Candidate range of sorted positions for position p.
+__device__ __forceinline__ void candidate_range(const WorklistArgs& a, int64_t p, int64_t& lo,
+                                                int64_t& hi) {
+  const uint64_t key = a.keys_sorted[p];
+  const int strip = (int)((key >> 32) & 0xFFF);
+  const int c = cell_of(key, a.n_strips);
+  hi = a.cell_end[c];
+  if (strip + 1 < a.n_strips && a.cell_end[c + 1] > hi) hi = a.cell_end[c + 1];
+  if (a.symmetric) {
+    lo = a.cell_begin[c];
+    if (strip > 0 && a.cell_begin[c - 1] >= 0 && a.cell_begin[c - 1] < lo) lo = a.cell_begin[c - 1];
+  } else {
+    lo = p + 1;
+  }
+}
+
+__device__ __forceinline__ bool keep_pair(const WorklistArgs& a, int f, int g) {
+  if (!a.use_keep) return true;
+  const uint64_t lo = (uint64_t)(f < g ? f : g), hi = (uint64_t)(f < g ? g : f);
+  return splitmix64(a.seed ^ ((lo << 32) | hi)) < a.keep_thr;
+}
+
+// One wave per sorted position; lanes stride over the candidate range.
+template <bool kFill>
+__global__ __launch_bounds__(256) void neighbours_kernel(WorklistArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= a.n_forests) return;
+  const int f = a.sorted[p];
+  const ForestInfo fi = a.finfo[f];
+  int64_t lo, hi;
+  candidate_range(a, p, lo, hi);
+  int64_t count = 0;
+  int64_t out = kFill ? a.nb_off[p] : 0;
+  if (fi.npix > 0) {
+    for (int64_t q0 = lo; q0 < hi; q0 += 64) {
+      const int64_t q = q0 + lane;
+      bool ok = false;
+      if (q < hi && q != p) {
+        const int g = a.sorted[q];
+        const ForestInfo gi = a.finfo[g];
+        ok = gi.npix > 0 && pair_may_bin(fi, gi, a.eperp_max, a.epar_max) && keep_pair(a, f, g);
+      }
+      const uint64_t m = __ballot(ok);
+      if (kFill && ok) {
+        const int r = __popcll(m & ((1ull << lane) - 1ull));
+        a.nbr[out + r] = (int32_t)q;
+        if (a.pair_p) a.pair_p[out + r] = (int32_t)p;
+      }
+      const int c = __popcll(m);
+      out += c;
+      count += c;
+    }
+  }
+  if (!kFill && lane == 0) a.cnt[p] = count;
+}
+
+__global__ void count_items_kernel(WorklistArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_forests) return;
+  a.item_cnt[p] = (a.cnt[p] + a.chunk - 1) / a.chunk;
+}
+
+__global__ void fill_items_kernel(WorklistArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n_forests) return;
+  const int64_t n = a.cnt[p], base = a.nb_off[p], o = a.item_off[p];
+  for (int64_t k = 0; k * a.chunk < n; ++k) {
+    Item it;
+    it.nb_begin = base + k * a.chunk;
+    it.p = (int32_t)p;
+    const int64_t left = n - k * a.chunk;
+    it.nb_count = (int32_t)(left < a.chunk ? left : a.chunk);
+    a.items[o + k] = it;
+  }
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+size_t worklist_cub_bytes(int64_t n) {
+  size_t b1 = 0, b2 = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, b1, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                     (int32_t*)nullptr, (int32_t*)nullptr, (int)n);
+  hipcub::DeviceScan::ExclusiveSum(nullptr, b2, (int64_t*)nullptr, (int64_t*)nullptr, (int)n);
+  return (b1 > b2 ? b1 : b2) + 256;
+}
+
+hipError_t launch_sort_forests(WorklistArgs& a, hipStream_t st) {
+  if (a.n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t bytes = a.cub_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(a.cub_tmp, bytes, a.keys, a.keys_sorted, a.ids, a.sorted,
+                                         (int)a.n_forests, 0, 64, st);
+  if (e != hipSuccess) return e;
+  const size_t ncell = (size_t)a.n_real * a.n_strips;
+  e = hipMemsetAsync(a.cell_begin, 0xFF, ncell * sizeof(int32_t), st);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(a.cell_end, 0xFF, ncell * sizeof(int32_t), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cells_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_neighbours(const WorklistArgs& a, hipStream_t st) {
+  if (a.n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(neighbours_kernel<false>, dim3(nblk(a.n_forests, 4)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_neighbours(const WorklistArgs& a, hipStream_t st) {
+  if (a.n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(neighbours_kernel<true>, dim3(nblk(a.n_forests, 4)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t bytes,
+                       hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, st);
+}
+
+hipError_t launch_count_items(const WorklistArgs& a, hipStream_t st) {
+  if (a.n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(count_items_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_items(const WorklistArgs& a, hipStream_t st) {
+  if (a.n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_items_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace lya

@@ -1,0 +1,394 @@
+// The xi pair kernel: weighted pixel-pair histograms of Sec. 2.1,
+// eq. estimator_two (numerator sum w_i d_i w_j d_j, denominator sum w_i w_j,
+// pair count), over every work item of the forest-pair list.
+//
+// Layout of the work.  A work item is one forest f (at sorted position p)
+// against up to kChunkMax neighbour forests g.  The neighbours' pixels form
+// one concatenated stream; each wave takes 64 consecutive stream pixels, one
+// per lane (coalesced loads, every lane busy except at the stream's end), and
+// loops over the pixels of f, which are identical for all lanes and are read
+// through the scalar cache.  Each lane thus evaluates one pixel pair per
+// iteration: r_par = |D_i - D_j| c, r_perp = (D_i + D_j) s with the lane's own
+// (s, c), then the bin and the two products.
+//
+// Histograms live in LDS, one copy per workgroup (FP64 sums, u32 counts), and
+// are added to the global FP64 outputs when the workgroup finishes, when the
+// realisation changes, or before a count could overflow.
+//
+// FP32 form.  Distances are re-centred on dc so FP32 keeps ~1e-4 Mpc/h.  A pair
+// whose FP32 bin coordinate lies within the proven error bound (tau) of a bin
+// edge is re-evaluated in FP64 with the same operations as the FP64 form and
+// binned by comparison with the FP64 edges, so the FP32 and FP64 forms bin
+// every pair identically.  Products are FP32 and are accumulated in FP64 in
+// LDS (ds_add_f64 is native on gfx950 and moves the same bytes as a hi/lo
+// pair of FP32 accumulators); with run-length accumulation, up to 32
+// consecutive products of the same bin are first summed in FP32 registers.
+#include "lya_common.h"
+
+namespace lya {
+
+namespace {
+
+constexpr unsigned kRunMax = 32;
+
+struct NbTable {
+  int64_t pix0[kChunkMax];
+  int32_t pref[kChunkMax + 1];
+  float s32[kChunkMax], c32[kChunkMax], b32[kChunkMax];
+  double s64[kChunkMax], c64[kChunkMax];
+};
+
+// Loads through the constant address space: with a wave-uniform address the
+// compiler emits scalar (SMEM) loads.  Native vector types are used because
+// class copies cannot bind to address-space-qualified objects.
+typedef float lya_f4 __attribute__((ext_vector_type(4)));
+typedef double lya_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Rec32 load_uniform(const Rec32* p) {
+  const lya_f4 v = *(const __attribute__((address_space(4))) lya_f4*)p;
+  return Rec32{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Rec64 load_uniform(const Rec64* p) {
+  const lya_d4 v = *(const __attribute__((address_space(4))) lya_d4*)p;
+  return Rec64{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ double load_uniform(const double* p) {
+  return *(const __attribute__((address_space(4))) double*)p;
+}
+
+template <typename T> struct RecOf;
+template <> struct RecOf<float> { using type = Rec32; };
+template <> struct RecOf<double> { using type = Rec64; };
+
+template <int BLOCK>
+__device__ void flush_hist(const XiArgs& a, double* hN, double* hW, unsigned* hn, int real) {
+  const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
+  const int64_t base = (int64_t)real * nb;
+  for (int L = threadIdx.x; L < nb; L += BLOCK) {
+    const unsigned c = hn[L];
+    if (c) {
+      const int kp = L % NP, kt = L / NP;
+      const int64_t A = base + (int64_t)kp * NT + kt;
+      atomicAdd(&a.num[A], hN[L]);
+      atomicAdd(&a.wsum[A], hW[L]);
+      atomicAdd(&a.npairs[A], (unsigned long long)c);
+    }
+    hN[L] = 0.0;
+    hW[L] = 0.0;
+    hn[L] = 0u;
+  }
+}
+
+template <typename T, int BLOCK, bool RLE>
+__global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
+  using Rec = typename RecOf<T>::type;
+  extern __shared__ double smem[];
+  __shared__ NbTable tb;
+  __shared__ int64_t s_item;
+
+  const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
+  double* hN = smem;
+  double* hW = smem + nb;
+  unsigned* hn = (unsigned*)(smem + 2 * nb);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  for (int L = threadIdx.x; L < nb; L += BLOCK) {
+    hN[L] = 0.0;
+    hW[L] = 0.0;
+    hn[L] = 0u;
+  }
+
+  const Rec* __restrict__ recs;
+  if constexpr (sizeof(T) == 4) recs = a.rec32; else recs = a.rec64;
+
+  // bin-coordinate constants
+  const T e0p = (T)a.g.e0_par, e0t = (T)a.g.e0_perp;
+  const T invp = (T)a.g.inv_par, invt = (T)a.g.inv_perp;
+  T taup, taut;
+  if constexpr (sizeof(T) == 4) {
+    taup = a.glob->tau_par;
+    taut = a.glob->tau_perp;
+  } else {
+    taup = 1e-8;
+    taut = 1e-8;
+  }
+  const T np_hi = (T)NP + taup, nt_hi = (T)NT + taut;
+  const T lo_p = a.g.zero_lo_par ? (T)-1 : -taup;
+  const T lo_t = a.g.zero_lo_perp ? (T)-1 : -taut;
+  const bool zlp = a.g.zero_lo_par, zlt = a.g.zero_lo_perp;
+  const double dc2 = 2.0 * a.glob->dc;
+
+  int cur_real = -1;
+  double pending = 0.0;  // upper bound on pairs added to any bin since the last flush
+  __syncthreads();
+
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= a.n_items) break;
+    const Item item = a.items[it];
+    const int f = a.sorted[item.p];
+    const ForestInfo fi = a.finfo[f];
+    const int nbc = item.nb_count;
+
+    // neighbour table: geometry per forest pair, prefix of pixel counts
+    if (threadIdx.x < 64) {
+      int n = 0;
+      if (lane < nbc) {
+        const int g = a.sorted[a.nbr[item.nb_begin + lane]];
+        const ForestInfo gi = a.finfo[g];
+        double s, c;
+        pair_sc(fi, gi, s, c);
+        tb.pix0[lane] = gi.pix0;
+        tb.s64[lane] = s;
+        tb.c64[lane] = c;
+        tb.s32[lane] = (float)s;
+        tb.c32[lane] = (float)c;
+        tb.b32[lane] = (float)(dc2 * s);
+        n = gi.npix;
+      }
+      int incl = n;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      if (lane < nbc) tb.pref[lane + 1] = incl;
+      if (lane == 0) tb.pref[0] = 0;
+    }
+    __syncthreads();
+    const int total = tb.pref[nbc];
+
+    if (fi.real != cur_real || pending + (double)total * fi.npix > 4.0e9) {
+      if (cur_real >= 0) {
+        flush_hist<BLOCK>(a, hN, hW, hn, cur_real);
+        __syncthreads();
+      }
+      cur_real = fi.real;
+      pending = 0.0;
+    }
+    pending += (double)total * fi.npix;
+
+    const Rec* __restrict__ rf = recs + fi.pix0;
+    const int nf = fi.npix;
+
+    for (int base = wave * 64; base < total; base += BLOCK) {
+      const int q = base + lane;
+      int k = 0;
+      {
+        int lo = 0, hi = nbc;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (tb.pref[mid] <= q) lo = mid; else hi = mid;
+        }
+        k = lo;
+      }
+      T dj, wdj, wj, sj, cj, bj;
+      double Dj64 = 0.0, s64 = 0.0, c64 = 1.0;
+      if (q < total) {
+        const int64_t j = tb.pix0[k] + (q - tb.pref[k]);
+        const Rec rj = recs[j];
+        dj = rj.d;
+        wdj = rj.wd;
+        wj = rj.w;
+        if constexpr (sizeof(T) == 4) {
+          sj = tb.s32[k];
+          cj = tb.c32[k];
+          bj = tb.b32[k];
+          Dj64 = a.dist[j];
+          s64 = tb.s64[k];
+          c64 = tb.c64[k];
+        } else {
+          sj = tb.s64[k];
+          cj = tb.c64[k];
+          bj = 0;
+        }
+      } else {
+        // out-of-range lane: a far-away pixel, never in the grid
+        dj = (T)1e30;
+        wdj = 0;
+        wj = 0;
+        sj = 0;
+        cj = 1;
+        bj = 0;
+      }
+
+      int curA = -1;
+      T accN = 0, accW = 0;
+      unsigned cnt = 0;
+
+#pragma unroll 2
+      for (int i = 0; i < nf; ++i) {
+        const Rec ri = load_uniform(rf + i);
+        T rp, rt;
+        if constexpr (sizeof(T) == 4) {
+          rp = fabsf(ri.d - dj) * cj;
+          rt = fmaf(ri.d + dj, sj, bj);
+        } else {
+          rp = __dmul_rn(fabs(__dsub_rn(ri.d, dj)), cj);
+          rt = __dmul_rn(__dadd_rn(ri.d, dj), sj);
+        }
+        const T xp = (rp - e0p) * invp;
+        const T xt = (rt - e0t) * invt;
+        int A = -1;
+        if ((xp < np_hi) & (xt < nt_hi) & (xp > lo_p) & (xt > lo_t)) {
+          const T rxp = rint(xp), rxt = rint(xt);
+          const bool gp = (fabs(xp - rxp) < taup) & !(zlp & (rxp == (T)0));
+          const bool gt = (fabs(xt - rxt) < taut) & !(zlt & (rxt == (T)0));
+          if (gp | gt) {
+            double rp64, rt64;
+            if constexpr (sizeof(T) == 4) {
+              const double Di = load_uniform(a.dist + fi.pix0 + i);
+              rp64 = __dmul_rn(fabs(__dsub_rn(Di, Dj64)), c64);
+              rt64 = __dmul_rn(__dadd_rn(Di, Dj64), s64);
+            } else {
+              rp64 = rp;
+              rt64 = rt;
+            }
+            const int kp = bin_exact(rp64, a.edges_par, NP, (int)floor((double)xp));
+            const int kt = bin_exact(rt64, a.edges_perp, NT, (int)floor((double)xt));
+            A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
+          } else if ((xp >= (T)0) & (xt >= (T)0) & (xp < (T)NP) & (xt < (T)NT)) {
+            A = (int)xt * NP + (int)xp;
+          }
+        }
+        if constexpr (RLE) {
+          // a run ends when the bin changes or after kRunMax pairs, which keeps
+          // the FP32 rounding of a run sum below kRunMax units in the last place
+          if (A != curA || cnt == kRunMax) {
+            if (curA >= 0) {
+              atomicAdd(&hN[curA], (double)accN);
+              atomicAdd(&hW[curA], (double)accW);
+              atomicAdd(&hn[curA], cnt);
+            }
+            curA = A;
+            accN = 0;
+            accW = 0;
+            cnt = 0;
+          }
+          if (A >= 0) {
+            accN += ri.wd * wdj;
+            accW += ri.w * wj;
+            ++cnt;
+          }
+        } else {
+          if (A >= 0) {
+            atomicAdd(&hN[A], (double)(ri.wd * wdj));
+            atomicAdd(&hW[A], (double)(ri.w * wj));
+            atomicAdd(&hn[A], 1u);
+          }
+        }
+      }
+      if constexpr (RLE) {
+        if (curA >= 0) {
+          atomicAdd(&hN[curA], (double)accN);
+          atomicAdd(&hW[curA], (double)accW);
+          atomicAdd(&hn[curA], cnt);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (cur_real >= 0) flush_hist<BLOCK>(a, hN, hW, hn, cur_real);
+}
+
+struct Variant {
+  const char* name;
+  int block;
+  bool rle;
+};
+constexpr Variant kVariants[] = {
+    {"b256", 256, false},
+    {"b512", 512, false},
+    {"b256-rle", 256, true},
+    {"b512-rle", 512, true},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <typename T, int BLOCK, bool RLE>
+hipError_t launch_one(const XiArgs& a, int blocks, hipStream_t st) {
+  const size_t smem = (size_t)a.g.n_par * a.g.n_perp * (2 * sizeof(double) + sizeof(unsigned));
+  auto kern = xi_kernel<T, BLOCK, RLE>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(int v, const XiArgs& a, int blocks, hipStream_t st) {
+  switch (v) {
+    case 0: return launch_one<T, 256, false>(a, blocks, st);
+    case 1: return launch_one<T, 512, false>(a, blocks, st);
+    case 2: return launch_one<T, 256, true>(a, blocks, st);
+    case 3: return launch_one<T, 512, true>(a, blocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int BLOCK, bool RLE>
+int occupancy(int n_bins) {
+  const size_t smem = (size_t)n_bins * (2 * sizeof(double) + sizeof(unsigned));
+  auto kern = xi_kernel<T, BLOCK, RLE>;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
+  int nblk = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, BLOCK, smem) != hipSuccess) return 1;
+  return nblk > 0 ? nblk : 1;
+}
+
+template <typename T>
+int occ_t(int v, int n_bins) {
+  switch (v) {
+    case 0: return occupancy<T, 256, false>(n_bins);
+    case 1: return occupancy<T, 512, false>(n_bins);
+    case 2: return occupancy<T, 256, true>(n_bins);
+    case 3: return occupancy<T, 512, true>(n_bins);
+  }
+  return 1;
+}
+
+__global__ void zero_kernel(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void finalize_xi_kernel(const double* num, const double* wsum, double* xi, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double w = wsum[i];
+  xi[i] = w != 0.0 ? num[i] / w : 0.0;
+}
+
+}  // namespace
+
+int xi_num_variants() { return kNumVariants; }
+const char* xi_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
+
+hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  return precision == LYA_FP64 ? launch_t<double>(variant, a, blocks, st)
+                               : launch_t<float>(variant, a, blocks, st);
+}
+
+int xi_blocks_per_cu(int variant, int precision, int n_bins) {
+  return precision == LYA_FP64 ? occ_t<double>(variant, n_bins) : occ_t<float>(variant, n_bins);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n = bytes / 4;
+  const unsigned blocks = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_xi(const double* num, const double* wsum, double* xi, int64_t n,
+                              hipStream_t st) {
+  if (n == 0 || xi == nullptr) return hipSuccess;
+  hipLaunchKernelGGL(finalize_xi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, num, wsum, xi, n);
+  return hipGetLastError();
+}
+
+}  // namespace lya

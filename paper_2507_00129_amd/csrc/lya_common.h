@@ -1,0 +1,227 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// MI355X Lyman-alpha pair library.  Not part of the public ABI (see lya.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lya.h"
+
+namespace lya {
+
+constexpr int kMaxBins = 4096;     // n_par * n_perp limit (LDS histograms)
+constexpr int kMaxStrips = 4096;   // declination strips of the sky index
+constexpr int kMaxRealisations = 1 << 20;
+constexpr int kChunkMax = 64;      // neighbour forests per xi / backward work item
+
+// Per-forest geometry and layout, FP64 (64 bytes).
+struct ForestInfo {
+  double nx, ny, nz;   // unit vector (cos dec cos ra, cos dec sin ra, sin dec)
+  double dmin, dmax;   // extent along the line of sight (+inf/-inf when empty)
+  int64_t pix0;        // first pixel
+  int32_t npix;
+  int32_t real;        // realisation id
+};
+
+// Per-forest eta sums (Sec. 2.2), FP64.
+struct EtaInfo {
+  double W;      // sum w
+  double lbar;   // sum w L / W
+  double S;      // sum w (L - lbar)^2
+  int32_t slope; // slope term kept
+  int32_t pad;
+};
+
+// Device-side scalars produced by the precompute stage.
+struct Globals {
+  unsigned long long dmin_bits;  // atomics on the bit patterns of positive doubles
+  unsigned long long dmax_bits;
+  double dc;        // re-centring distance (exactly representable in FP32)
+  double m;         // max |D - dc|
+  float tau_par;    // FP32 edge-guard half width, in bins
+  float tau_perp;
+  int32_t flag;     // validation error bits
+  int32_t pad;
+};
+
+// Pixel records for the xi and backward kernels.
+struct __align__(16) Rec32 { float d, wd, w, del; };   // d = D - dc
+struct __align__(32) Rec64 { double d, wd, w, del; };  // d = D
+
+// Pixel records for the distortion kernel: D, w and the eta factors
+// p = (1, a), q = (u, b) with a = L - lbar, u = w / W, b = w a / S.
+struct __align__(16) DRec32 { float d, w, a, u; float b, pad0, pad1, pad2; };
+struct __align__(16) DRec64 { double d, w, a, u, b, pad; };
+
+// One persistent-kernel work item: forest at sorted position p against the
+// neighbour list entries [nb_begin, nb_begin + nb_count).
+struct Item {
+  int64_t nb_begin;
+  int32_t p;
+  int32_t nb_count;
+};
+
+// Uniform grid description passed by value to the pair kernels.
+struct GridDev {
+  int32_t n_par, n_perp;
+  double e0_par, e0_perp;       // first edges
+  double inv_par, inv_perp;     // 1 / bin width
+  double emax_par, emax_perp;   // last edges
+  int32_t zero_lo_par, zero_lo_perp;  // first edge is exactly 0
+};
+
+// Validation error bits (Globals::flag).
+enum : int32_t {
+  kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32
+};
+
+// ---------------------------------------------------------------- geometry
+// s = |n_f - n_g| / 2 and c = sqrt(1 - s^2) (chord form of the half angle).
+// Written with explicit operation order and no contraction so that every
+// kernel gets bit-identical values.
+__device__ __forceinline__ void pair_sc(const ForestInfo& a, const ForestInfo& b, double& s,
+                                        double& c) {
+  const double dx = a.nx - b.nx, dy = a.ny - b.ny, dz = a.nz - b.nz;
+  const double q = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  s = __dmul_rn(0.5, __dsqrt_rn(q));
+  c = __dsqrt_rn(__dsub_rn(1.0, __dmul_rn(s, s)));
+}
+
+// Conservative forest-pair cut: false only if no pixel pair can be in the
+// grid.  r_perp >= (Dmin_f + Dmin_g) s and r_par >= gap c, with the same
+// rounded operations as the separations, so monotone rounding keeps it exact.
+__device__ __forceinline__ bool pair_may_bin(const ForestInfo& a, const ForestInfo& b,
+                                             double eperp_max, double epar_max) {
+  double s, c;
+  pair_sc(a, b, s, c);
+  const double rperp_min = __dmul_rn(__dadd_rn(a.dmin, b.dmin), s);
+  const double gap = fmax(0.0, fmax(__dsub_rn(b.dmin, a.dmax), __dsub_rn(a.dmin, b.dmax)));
+  const double rpar_min = __dmul_rn(gap, c);
+  return rperp_min < eperp_max && rpar_min < epar_max;
+}
+
+// Exact bin of r against FP64 edges[0..n]; k0 is a guess within a few bins.
+// Returns -1 outside [edges[0], edges[n]).
+__device__ __forceinline__ int bin_exact(double r, const double* __restrict__ edges, int n, int k0) {
+  if (!(r >= edges[0]) || !(r < edges[n])) return -1;
+  int k = k0 < 0 ? 0 : (k0 > n - 1 ? n - 1 : k0);
+  while (r < edges[k]) --k;
+  while (r >= edges[k + 1]) ++k;
+  return k;
+}
+
+// SplitMix64 output function (Steele, Lea & Flood 2014): mix(x + golden gamma).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------- host launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+
+struct PrecomputeArgs {
+  const lya_forests* F;
+  int eta_mode;
+  int project;
+  int want_xi32, want_xi64, want_d32, want_d64;
+  ForestInfo* finfo;
+  EtaInfo* einfo;
+  double* delta_proj;   // [n_pix] when project
+  Rec32* rec32;
+  Rec64* rec64;
+  DRec32* drec32;
+  DRec64* drec64;
+  Globals* glob;
+  double eperp_max, epar_max, e0_par, e0_perp, inv_par, inv_perp;
+};
+hipError_t launch_validate(const lya_forests* F, Globals* glob, hipStream_t st);
+hipError_t launch_forest_stats(const PrecomputeArgs& a, hipStream_t st);
+hipError_t launch_globals(const PrecomputeArgs& a, hipStream_t st);
+hipError_t launch_pack(const PrecomputeArgs& a, hipStream_t st);
+
+struct WorklistArgs {
+  int64_t n_forests;
+  int32_t n_real;
+  const ForestInfo* finfo;
+  const double* ra;
+  const double* dec;
+  int n_strips;
+  double strip_h;
+  double eperp_max, epar_max;
+  int symmetric;          // neighbours on both sides (backward)
+  int use_keep;           // distortion subset
+  uint64_t keep_thr, seed;
+  // outputs / scratch
+  uint64_t* keys;
+  uint64_t* keys_sorted;
+  int32_t* ids;
+  int32_t* sorted;        // sorted position -> forest
+  int32_t* cell_begin;    // [n_real * n_strips]
+  int32_t* cell_end;
+  int64_t* cnt;           // [n_forests]
+  int64_t* nb_off;        // [n_forests]
+  int32_t* nbr;           // neighbour sorted positions
+  int32_t* pair_p;        // optional: sorted position of the first forest per entry
+  int64_t* item_cnt;      // [n_forests]
+  int64_t* item_off;
+  Item* items;
+  int chunk;
+  void* cub_tmp;
+  size_t cub_bytes;
+};
+size_t worklist_cub_bytes(int64_t n);
+hipError_t launch_sort_forests(WorklistArgs& a, hipStream_t st);
+hipError_t launch_count_neighbours(const WorklistArgs& a, hipStream_t st);
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t bytes,
+                       hipStream_t st);
+hipError_t launch_fill_neighbours(const WorklistArgs& a, hipStream_t st);
+hipError_t launch_count_items(const WorklistArgs& a, hipStream_t st);
+hipError_t launch_fill_items(const WorklistArgs& a, hipStream_t st);
+
+struct XiArgs {
+  const ForestInfo* finfo;
+  const int32_t* sorted;
+  const int32_t* nbr;
+  const Item* items;
+  int64_t n_items;
+  unsigned int* counter;
+  const Rec32* rec32;
+  const Rec64* rec64;
+  const double* dist;
+  const double* edges_par;
+  const double* edges_perp;
+  const Globals* glob;
+  GridDev g;
+  double* num;
+  double* wsum;
+  unsigned long long* npairs;
+};
+int xi_num_variants();
+const char* xi_variant_name(int v);
+hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hipStream_t st);
+int xi_blocks_per_cu(int variant, int precision, int n_bins);
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_finalize_xi(const double* num, const double* wsum, double* xi, int64_t n,
+                              hipStream_t st);
+
+}  // namespace lya

@@ -1,0 +1,558 @@
+// Host runtime of the C ABI declared in lya.h: argument checks, the
+// grow-only device workspace, stage orchestration on the caller's stream,
+// and the autotuner that picks kernel variants by timing them on the input.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "lya_common.h"
+
+using namespace lya;
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct lya_context {
+  int device = 0;
+  int n_cu = 1;
+  std::string err;
+  lya_stats stats{};
+  std::map<std::string, Buf> bufs;
+  std::map<std::string, int> tuned;
+  hipEvent_t ev[8]{};
+  void* pinned = nullptr;  // small pinned host staging area
+};
+
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+
+lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, LYA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+#define LYA_TRY(expr)               \
+  do {                              \
+    lya_status s_ = (expr);         \
+    if (s_ != LYA_OK) return s_;    \
+  } while (0)
+
+// Grow-only named workspace buffer (256-byte aligned by hipMalloc).
+lya_status ws(lya_context* ctx, const char* name, size_t bytes, void** out) {
+  Buf& b = ctx->bufs[name];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes < bytes) {
+    if (b.p) {
+      hipDeviceSynchronize();
+      hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      hipGetLastError();
+      b.p = nullptr;
+      return fail(ctx, LYA_E_NOMEM, "device allocation of %zu bytes for %s failed", want, name);
+    }
+    b.bytes = want;
+  }
+  *out = b.p;
+  return LYA_OK;
+}
+
+template <typename T>
+lya_status wst(lya_context* ctx, const char* name, size_t count, T** out) {
+  void* p = nullptr;
+  lya_status s = ws(ctx, name, count * sizeof(T), &p);
+  *out = (T*)p;
+  return s;
+}
+
+lya_status check_axis(lya_context* ctx, const double* e, int n, const char* axis, double& e0,
+                      double& inv, double& emax) {
+  if (!e) return fail(ctx, LYA_E_INVALID, "edges_%s is NULL", axis);
+  if (n < 1) return fail(ctx, LYA_E_INVALID, "n_%s = %d must be >= 1", axis, n);
+  for (int k = 0; k <= n; ++k)
+    if (!isfinite(e[k])) return fail(ctx, LYA_E_INVALID, "edges_%s[%d] is not finite", axis, k);
+  if (e[0] < 0.0) return fail(ctx, LYA_E_INVALID, "edges_%s[0] = %g is negative", axis, e[0]);
+  for (int k = 0; k < n; ++k)
+    if (!(e[k + 1] > e[k]))
+      return fail(ctx, LYA_E_INVALID, "edges_%s not strictly increasing at %d", axis, k);
+  const double d = (e[n] - e[0]) / n;
+  for (int k = 0; k <= n; ++k)
+    if (fabs(e[k] - (e[0] + k * d)) > 1e-9 * d)
+      return fail(ctx, LYA_E_UNSUPPORTED, "edges_%s are not uniformly spaced (edge %d); this build bins uniform grids only", axis, k);
+  e0 = e[0];
+  inv = 1.0 / d;
+  emax = e[n];
+  return LYA_OK;
+}
+
+lya_status check_common(lya_context* ctx, const lya_forests* F, const lya_grid* G,
+                        const lya_options* o, GridDev& gd) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!F || !G || !o) return fail(ctx, LYA_E_INVALID, "NULL forests, grid or options");
+  if (F->n_forests < 0 || F->n_pix < 0) return fail(ctx, LYA_E_INVALID, "negative n_forests or n_pix");
+  if (F->n_forests > INT32_MAX - 1 || F->n_pix > ((int64_t)1 << 40))
+    return fail(ctx, LYA_E_UNSUPPORTED, "too many forests or pixels");
+  if (F->n_realisations < 1 || F->n_realisations > kMaxRealisations)
+    return fail(ctx, LYA_E_INVALID, "n_realisations = %d out of range", F->n_realisations);
+  if (F->n_forests > 0 && (!F->offsets || !F->ra || !F->dec))
+    return fail(ctx, LYA_E_INVALID, "NULL offsets, ra or dec");
+  if (F->n_pix > 0 && (!F->dist || !F->delta || !F->weight || !F->loglam))
+    return fail(ctx, LYA_E_INVALID, "NULL dist, delta, weight or loglam");
+  if (o->precision != LYA_FP32_COMP && o->precision != LYA_FP64)
+    return fail(ctx, LYA_E_INVALID, "unknown precision %d", o->precision);
+  if (o->eta < LYA_ETA_IDENTITY || o->eta > LYA_ETA_MEAN_SLOPE)
+    return fail(ctx, LYA_E_INVALID, "unknown eta mode %d", o->eta);
+  if (!(o->dmat_keep_fraction > 0.0 && o->dmat_keep_fraction <= 1.0))
+    return fail(ctx, LYA_E_INVALID, "dmat_keep_fraction = %g outside (0, 1]", o->dmat_keep_fraction);
+  if ((int64_t)G->n_par * G->n_perp > kMaxBins)
+    return fail(ctx, LYA_E_UNSUPPORTED, "n_par * n_perp = %lld exceeds %d bins",
+                (long long)G->n_par * G->n_perp, kMaxBins);
+  double e0p, ip, ep, e0t, it, et;
+  LYA_TRY(check_axis(ctx, G->edges_par, G->n_par, "par", e0p, ip, ep));
+  LYA_TRY(check_axis(ctx, G->edges_perp, G->n_perp, "perp", e0t, it, et));
+  gd.n_par = G->n_par;
+  gd.n_perp = G->n_perp;
+  gd.e0_par = e0p;
+  gd.e0_perp = e0t;
+  gd.inv_par = ip;
+  gd.inv_perp = it;
+  gd.emax_par = ep;
+  gd.emax_perp = et;
+  gd.zero_lo_par = e0p == 0.0;
+  gd.zero_lo_perp = e0t == 0.0;
+  return LYA_OK;
+}
+
+__global__ void init_globals_kernel(Globals* g) {
+  g->dmin_bits = 0x7FF0000000000000ull;  // +inf
+  g->dmax_bits = 0ull;
+  g->dc = 0.0;
+  g->m = 0.0;
+  g->tau_par = 0.f;
+  g->tau_perp = 0.f;
+  g->flag = 0;
+  g->pad = 0;
+}
+
+struct Prepared {
+  Globals* glob = nullptr;
+  ForestInfo* finfo = nullptr;
+  Rec32* rec32 = nullptr;
+  Rec64* rec64 = nullptr;
+  DRec32* drec32 = nullptr;
+  DRec64* drec64 = nullptr;
+  double* edges_par = nullptr;
+  double* edges_perp = nullptr;
+  Globals host{};
+};
+
+// Validation, per-forest sums and record packing.
+lya_status prepare(lya_context* ctx, const lya_forests* F, const lya_grid* G, const GridDev& gd,
+                   const lya_options* o, hipStream_t st, bool xi_rec, bool d_rec, bool project,
+                   Prepared& P) {
+  const int64_t N = F->n_forests, npix = F->n_pix;
+  LYA_TRY(wst(ctx, "globals", 1, &P.glob));
+  LYA_TRY(wst(ctx, "finfo", (size_t)N, &P.finfo));
+  EtaInfo* einfo;
+  LYA_TRY(wst(ctx, "einfo", (size_t)N, &einfo));
+  LYA_TRY(wst(ctx, "edges_par", (size_t)gd.n_par + 1, &P.edges_par));
+  LYA_TRY(wst(ctx, "edges_perp", (size_t)gd.n_perp + 1, &P.edges_perp));
+  HIP_TRY(hipMemcpyAsync(P.edges_par, G->edges_par, sizeof(double) * (gd.n_par + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.edges_perp, G->edges_perp, sizeof(double) * (gd.n_perp + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(init_globals_kernel, dim3(1), dim3(1), 0, st, P.glob);
+  HIP_TRY(hipGetLastError());
+  if (o->validate) {
+    HIP_TRY(launch_validate(F, P.glob, st));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int32_t flag = *(int32_t*)ctx->pinned;
+    if (flag) {
+      return fail(ctx, LYA_E_INVALID, "invalid forest arrays:%s%s%s%s%s%s",
+                  flag & kBadOffsets ? " offsets not non-decreasing from 0" : "",
+                  flag & kBadNpix ? " offsets[n_forests] != n_pix" : "",
+                  flag & kBadFinite ? " non-finite values" : "",
+                  flag & kBadWeight ? " negative weights" : "",
+                  flag & kBadDist ? " non-positive distances" : "",
+                  flag & kBadReal ? " realisation id out of range" : "");
+    }
+  }
+  PrecomputeArgs a{};
+  a.F = F;
+  a.eta_mode = o->eta;
+  a.project = project;
+  a.want_xi32 = xi_rec && o->precision == LYA_FP32_COMP;
+  a.want_xi64 = xi_rec && o->precision == LYA_FP64;
+  a.want_d32 = d_rec && o->precision == LYA_FP32_COMP;
+  a.want_d64 = d_rec && o->precision == LYA_FP64;
+  a.finfo = P.finfo;
+  a.einfo = einfo;
+  a.glob = P.glob;
+  a.eperp_max = gd.emax_perp;
+  a.epar_max = gd.emax_par;
+  a.e0_par = gd.e0_par;
+  a.e0_perp = gd.e0_perp;
+  a.inv_par = gd.inv_par;
+  a.inv_perp = gd.inv_perp;
+  if (project) LYA_TRY(wst(ctx, "delta_proj", (size_t)npix, &a.delta_proj));
+  if (a.want_xi32) LYA_TRY(wst(ctx, "rec32", (size_t)npix, &a.rec32));
+  if (a.want_xi64) LYA_TRY(wst(ctx, "rec64", (size_t)npix, &a.rec64));
+  if (a.want_d32) LYA_TRY(wst(ctx, "drec32", (size_t)npix, &a.drec32));
+  if (a.want_d64) LYA_TRY(wst(ctx, "drec64", (size_t)npix, &a.drec64));
+  HIP_TRY(launch_forest_stats(a, st));
+  HIP_TRY(launch_globals(a, st));
+  HIP_TRY(launch_pack(a, st));
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  memcpy(&P.host, ctx->pinned, sizeof(Globals));
+  P.rec32 = a.rec32;
+  P.rec64 = a.rec64;
+  P.drec32 = a.drec32;
+  P.drec64 = a.drec64;
+  return LYA_OK;
+}
+
+struct Worklist {
+  int32_t* sorted = nullptr;
+  int32_t* nbr = nullptr;
+  int32_t* pair_p = nullptr;
+  Item* items = nullptr;
+  int64_t n_pairs = 0;
+  int64_t n_items = 0;
+};
+
+lya_status read_i64(lya_context* ctx, const int64_t* dev, int64_t* host, int count, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(ctx->pinned, dev, sizeof(int64_t) * count, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  memcpy(host, ctx->pinned, sizeof(int64_t) * count);
+  return LYA_OK;
+}
+
+// Sky index, neighbour lists and work items (Sec. 2.1 pre-ordering).
+lya_status build_worklist(lya_context* ctx, const lya_forests* F, const GridDev& gd,
+                          const Prepared& P, hipStream_t st, bool symmetric, bool use_keep,
+                          uint64_t keep_thr, uint64_t seed, bool want_pairs, int chunk,
+                          const char* tag, Worklist& W) {
+  const int64_t N = F->n_forests;
+  const int R = F->n_realisations;
+  const double dmin = __builtin_bit_cast(double, P.host.dmin_bits);
+  double arg = (dmin > 0.0 && isfinite(dmin)) ? gd.emax_perp / (2.0 * dmin) : 2.0;
+  double theta = arg >= 1.0 ? kPi : 2.0 * asin(arg);
+  theta = theta * (1.0 + 1e-9) + 1e-12;
+  int n_strips = (int)floor(kPi / theta);
+  if (n_strips < 1) n_strips = 1;
+  if (n_strips > kMaxStrips) n_strips = kMaxStrips;
+  const int max_by_real = (int)((1u << 12) - 1);
+  if (n_strips > max_by_real) n_strips = max_by_real;
+
+  WorklistArgs a{};
+  a.n_forests = N;
+  a.n_real = R;
+  a.finfo = P.finfo;
+  a.ra = F->ra;
+  a.dec = F->dec;
+  a.n_strips = n_strips;
+  a.strip_h = kPi / n_strips;
+  a.eperp_max = gd.emax_perp;
+  a.epar_max = gd.emax_par;
+  a.symmetric = symmetric;
+  a.use_keep = use_keep;
+  a.keep_thr = keep_thr;
+  a.seed = seed;
+  a.chunk = chunk;
+  std::string t(tag);
+  LYA_TRY(wst(ctx, "wl_keys", (size_t)N, &a.keys));
+  LYA_TRY(wst(ctx, "wl_keys_sorted", (size_t)N, &a.keys_sorted));
+  LYA_TRY(wst(ctx, "wl_ids", (size_t)N, &a.ids));
+  LYA_TRY(wst(ctx, (t + "_sorted").c_str(), (size_t)N, &a.sorted));
+  LYA_TRY(wst(ctx, "wl_cell_begin", (size_t)R * n_strips, &a.cell_begin));
+  LYA_TRY(wst(ctx, "wl_cell_end", (size_t)R * n_strips, &a.cell_end));
+  LYA_TRY(wst(ctx, "wl_cnt", (size_t)N, &a.cnt));
+  LYA_TRY(wst(ctx, "wl_nb_off", (size_t)N, &a.nb_off));
+  LYA_TRY(wst(ctx, "wl_item_cnt", (size_t)N, &a.item_cnt));
+  LYA_TRY(wst(ctx, "wl_item_off", (size_t)N, &a.item_off));
+  a.cub_bytes = worklist_cub_bytes(N);
+  LYA_TRY(ws(ctx, "wl_cub", a.cub_bytes, &a.cub_tmp));
+
+  HIP_TRY(launch_sort_forests(a, st));
+  HIP_TRY(launch_count_neighbours(a, st));
+  HIP_TRY(launch_scan(a.cnt, a.nb_off, N, a.cub_tmp, a.cub_bytes, st));
+  int64_t last[2];
+  HIP_TRY(hipMemcpyAsync((char*)ctx->pinned, a.cnt + (N - 1), 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 8, a.nb_off + (N - 1), 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  memcpy(last, ctx->pinned, 16);
+  const int64_t total = last[0] + last[1];
+  LYA_TRY(wst(ctx, (t + "_nbr").c_str(), (size_t)total, &a.nbr));
+  if (want_pairs) LYA_TRY(wst(ctx, (t + "_pair_p").c_str(), (size_t)total, &a.pair_p));
+  HIP_TRY(launch_fill_neighbours(a, st));
+  W.sorted = a.sorted;
+  W.nbr = a.nbr;
+  W.pair_p = a.pair_p;
+  W.n_pairs = total;
+  if (chunk > 0) {
+    HIP_TRY(launch_count_items(a, st));
+    HIP_TRY(launch_scan(a.item_cnt, a.item_off, N, a.cub_tmp, a.cub_bytes, st));
+    HIP_TRY(hipMemcpyAsync((char*)ctx->pinned, a.item_cnt + (N - 1), 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 8, a.item_off + (N - 1), 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memcpy(last, ctx->pinned, 16);
+    W.n_items = last[0] + last[1];
+    LYA_TRY(wst(ctx, (t + "_items").c_str(), (size_t)W.n_items, &a.items));
+    HIP_TRY(launch_fill_items(a, st));
+    W.items = a.items;
+  }
+  return LYA_OK;
+}
+
+int xi_chunk(const lya_forests* F, int target_stream) {
+  const double mean = F->n_forests ? (double)F->n_pix / (double)F->n_forests : 1.0;
+  int c = (int)llround(target_stream / (mean > 1.0 ? mean : 1.0));
+  if (c < 1) c = 1;
+  if (c > kChunkMax) c = kChunkMax;
+  return c;
+}
+
+// Optional per-stage device timing: events 0..5 bracket the stages.
+struct Timer {
+  lya_context* ctx;
+  hipStream_t st;
+  bool on;
+  void at(int i) {
+    if (on) hipEventRecord(ctx->ev[i], st);
+  }
+  float ms(int a, int b) {
+    float t = 0.f;
+    if (on) hipEventElapsedTime(&t, ctx->ev[a], ctx->ev[b]);
+    return t;
+  }
+  lya_status finish(lya_context* c) {
+    if (!on) return LYA_OK;
+    if (hipEventSynchronize(c->ev[5]) != hipSuccess) return fail(c, LYA_E_DEVICE, "event sync failed");
+    c->stats.ms_precompute = ms(0, 1);
+    c->stats.ms_worklist = ms(1, 2);
+    c->stats.ms_main = ms(3, 4);
+    c->stats.ms_finalize = ms(4, 5);
+    return LYA_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void lya_options_default(lya_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->precision = LYA_FP32_COMP;
+  o->eta = LYA_ETA_MEAN_SLOPE;
+  o->project_deltas = 0;
+  o->autotune = 1;
+  o->validate = 1;
+  o->timing = 0;
+  o->variant = -1;
+  o->reserved = 0;
+  o->dmat_keep_fraction = 1.0;
+  o->seed = 0;
+}
+
+lya_status lya_create(lya_context** out, int device) {
+  if (!out) return LYA_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    hipGetLastError();
+    return LYA_E_DEVICE;
+  }
+  lya_context* ctx = new lya_context();
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return LYA_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+  for (auto& e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete ctx;
+      return LYA_E_DEVICE;
+    }
+  if (hipHostMalloc(&ctx->pinned, 4096) != hipSuccess) {
+    delete ctx;
+    return LYA_E_NOMEM;
+  }
+  *out = ctx;
+  return LYA_OK;
+}
+
+void lya_destroy(lya_context* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& kv : ctx->bufs)
+    if (kv.second.p) hipFree(kv.second.p);
+  for (auto& e : ctx->ev)
+    if (e) hipEventDestroy(e);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
+  delete ctx;
+}
+
+const char* lya_last_error(const lya_context* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+lya_status lya_last_stats(const lya_context* ctx, lya_stats* out) {
+  if (!ctx || !out) return LYA_E_INVALID;
+  *out = ctx->stats;
+  return LYA_OK;
+}
+
+lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
+                  void* stream, double* num, double* wsum, int64_t* npairs, double* xi) {
+  GridDev gd{};
+  LYA_TRY(check_common(ctx, F, G, o, gd));
+  if (!num || !wsum || !npairs) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or npairs");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->err.clear();
+  ctx->stats = lya_stats{};
+  const int nb = gd.n_par * gd.n_perp;
+  const int64_t nout = (int64_t)F->n_realisations * nb;
+  Timer tm{ctx, st, o->timing != 0};
+  tm.at(0);
+  HIP_TRY(launch_zero(num, nout * sizeof(double), st));
+  HIP_TRY(launch_zero(wsum, nout * sizeof(double), st));
+  HIP_TRY(launch_zero(npairs, nout * sizeof(int64_t), st));
+  if (F->n_forests > 0 && F->n_pix > 0) {
+    Prepared P;
+    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, o->project_deltas != 0, P));
+    tm.at(1);
+    Worklist W;
+    const int chunk = xi_chunk(F, 4096);
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, false, 0, 0, false, chunk, "xi", W));
+    tm.at(2);
+    ctx->stats.forest_pairs = W.n_pairs;
+    ctx->stats.work_items = W.n_items;
+    unsigned int* counter;
+    LYA_TRY(wst(ctx, "xi_counter", 1, &counter));
+    XiArgs a{};
+    a.finfo = P.finfo;
+    a.sorted = W.sorted;
+    a.nbr = W.nbr;
+    a.items = W.items;
+    a.n_items = W.n_items;
+    a.counter = counter;
+    a.rec32 = P.rec32;
+    a.rec64 = P.rec64;
+    a.dist = F->dist;
+    a.edges_par = P.edges_par;
+    a.edges_perp = P.edges_perp;
+    a.glob = P.glob;
+    a.g = gd;
+    a.num = num;
+    a.wsum = wsum;
+    a.npairs = (unsigned long long*)npairs;
+
+    // autotune: time each variant on a prefix of the work list, into scratch outputs
+    char key[128];
+    snprintf(key, sizeof key, "xi/%d/%d/%d", o->precision, nb,
+             (int)(F->n_pix / (F->n_forests ? F->n_forests : 1) / 64));
+    int variant = 0;
+    auto found = ctx->tuned.find(key);
+    if (o->variant >= 0) {
+      if (o->variant >= xi_num_variants())
+        return fail(ctx, LYA_E_INVALID, "variant %d out of range (xi has %d)", o->variant, xi_num_variants());
+      variant = o->variant;
+    } else if (found != ctx->tuned.end()) {
+      variant = found->second;
+    } else if (o->autotune && W.n_items > 0) {
+      double* sn;
+      double* sw;
+      unsigned long long* sc;
+      LYA_TRY(wst(ctx, "tune_num", (size_t)nout, &sn));
+      LYA_TRY(wst(ctx, "tune_wsum", (size_t)nout, &sw));
+      LYA_TRY(wst(ctx, "tune_cnt", (size_t)nout, &sc));
+      XiArgs t = a;
+      t.num = sn;
+      t.wsum = sw;
+      t.npairs = sc;
+      int64_t sample = W.n_items / 8;
+      if (sample < 4 * ctx->n_cu) sample = W.n_items < 4 * ctx->n_cu ? W.n_items : 4 * ctx->n_cu;
+      t.n_items = sample;
+      float best = 1e30f;
+      for (int v = 0; v < xi_num_variants(); ++v) {
+        const int blocks = xi_blocks_per_cu(v, o->precision, nb) * ctx->n_cu;
+        float ms_v = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(launch_zero(counter, 4, st));
+          HIP_TRY(hipEventRecord(ctx->ev[6], st));
+          HIP_TRY(launch_xi(v, o->precision, t, blocks, st));
+          HIP_TRY(hipEventRecord(ctx->ev[7], st));
+          HIP_TRY(hipEventSynchronize(ctx->ev[7]));
+          HIP_TRY(hipEventElapsedTime(&ms_v, ctx->ev[6], ctx->ev[7]));
+        }
+        if (ms_v < best) {
+          best = ms_v;
+          variant = v;
+        }
+      }
+      ctx->tuned[key] = variant;
+    }
+    const int blocks = xi_blocks_per_cu(variant, o->precision, nb) * ctx->n_cu;
+    ctx->stats.variant = variant;
+    ctx->stats.grid_blocks = blocks;
+    HIP_TRY(launch_zero(counter, 4, st));
+    tm.at(3);
+    HIP_TRY(launch_xi(variant, o->precision, a, blocks, st));
+    tm.at(4);
+  } else {
+    tm.at(1);
+    tm.at(2);
+    tm.at(3);
+    tm.at(4);
+  }
+  HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
+  tm.at(5);
+  return tm.finish(ctx);
+}
+
+lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
+                    void* stream, double* dmat, double* wsum_d) {
+  (void)stream; (void)dmat; (void)wsum_d;
+  GridDev gd{};
+  LYA_TRY(check_common(ctx, F, G, o, gd));
+  return fail(ctx, LYA_E_UNSUPPORTED, "lya_dmat not built yet");
+}
+
+lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_grid* G,
+                           const lya_options* o, void* stream, const double* grad_xi,
+                           const double* xi, const double* wsum, double* grad_delta,
+                           double* grad_weight) {
+  (void)stream; (void)grad_xi; (void)xi; (void)wsum; (void)grad_delta; (void)grad_weight;
+  GridDev gd{};
+  LYA_TRY(check_common(ctx, F, G, o, gd));
+  return fail(ctx, LYA_E_UNSUPPORTED, "lya_xi_backward not built yet");
+}
+
+}  // extern "C"

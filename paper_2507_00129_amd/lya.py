@@ -1,0 +1,263 @@
+"""ctypes binding of the C ABI in include/lya.h.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device arrays are torch CUDA tensors (used for memory and streams);
+grid edges stay on the host.  Importing works without a GPU; calls need one.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "liblya.so")
+
+LYA_OK, LYA_E_INVALID, LYA_E_NOMEM, LYA_E_DEVICE, LYA_E_UNSUPPORTED = 0, 1, 2, 3, 4
+FP32_COMP, FP64 = 0, 1
+ETA_IDENTITY, ETA_MEAN, ETA_MEAN_SLOPE = 0, 1, 2
+
+_PRECISION = {"fp32": FP32_COMP, "fp32_comp": FP32_COMP, "fp64": FP64, FP32_COMP: FP32_COMP, FP64: FP64}
+_ETA = {"identity": ETA_IDENTITY, "mean": ETA_MEAN, "mean_slope": ETA_MEAN_SLOPE,
+        ETA_IDENTITY: ETA_IDENTITY, ETA_MEAN: ETA_MEAN, ETA_MEAN_SLOPE: ETA_MEAN_SLOPE}
+
+
+class LyaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lya status {status}: {msg}")
+        self.status = status
+
+
+class lya_forests(ctypes.Structure):
+    _fields_ = [
+        ("n_forests", ctypes.c_int64), ("n_pix", ctypes.c_int64),
+        ("offsets", ctypes.c_void_p), ("ra", ctypes.c_void_p), ("dec", ctypes.c_void_p),
+        ("dist", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+        ("loglam", ctypes.c_void_p), ("realisation", ctypes.c_void_p),
+        ("n_realisations", ctypes.c_int32),
+    ]
+
+
+class lya_grid(ctypes.Structure):
+    _fields_ = [("n_par", ctypes.c_int32), ("n_perp", ctypes.c_int32),
+                ("edges_par", ctypes.c_void_p), ("edges_perp", ctypes.c_void_p)]
+
+
+class lya_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32), ("eta", ctypes.c_int32), ("project_deltas", ctypes.c_int32),
+        ("autotune", ctypes.c_int32), ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("dmat_keep_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
+    ]
+
+
+class lya_stats(ctypes.Structure):
+    _fields_ = [
+        ("forest_pairs", ctypes.c_int64), ("work_items", ctypes.c_int64),
+        ("candidate_pairs", ctypes.c_int64), ("variant", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("ms_precompute", ctypes.c_float),
+        ("ms_worklist", ctypes.c_float), ("ms_main", ctypes.c_float), ("ms_finalize", ctypes.c_float),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblya.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run paper_2507_00129_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.lya_options_default.argtypes = [ctypes.POINTER(lya_options)]
+    lib.lya_options_default.restype = None
+    lib.lya_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.lya_create.restype = I32
+    lib.lya_destroy.argtypes = [P]
+    lib.lya_destroy.restype = None
+    lib.lya_last_error.argtypes = [P]
+    lib.lya_last_error.restype = ctypes.c_char_p
+    lib.lya_last_stats.argtypes = [P, ctypes.POINTER(lya_stats)]
+    lib.lya_last_stats.restype = I32
+    FP, GP, OP = ctypes.POINTER(lya_forests), ctypes.POINTER(lya_grid), ctypes.POINTER(lya_options)
+    lib.lya_xi.argtypes = [P, FP, GP, OP, P, P, P, P, P]
+    lib.lya_xi.restype = I32
+    lib.lya_dmat.argtypes = [P, FP, GP, OP, P, P, P]
+    lib.lya_dmat.restype = I32
+    lib.lya_xi_backward.argtypes = [P, FP, GP, OP, P, P, P, P, P, P]
+    lib.lya_xi_backward.restype = I32
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+@dataclass
+class DeviceForests:
+    """Forests resident on the GPU as torch tensors (CSR layout of lya.h)."""
+    offsets: "object"
+    ra: "object"
+    dec: "object"
+    dist: "object"
+    delta: "object"
+    weight: "object"
+    loglam: "object"
+    realisation: "object" = None
+    n_realisations: int = 1
+    offsets_host: Optional[np.ndarray] = None
+
+    @property
+    def n_forests(self):
+        return int(self.ra.shape[0])
+
+    @property
+    def n_pix(self):
+        return int(self.dist.shape[0])
+
+    @classmethod
+    def from_host(cls, F, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+        real = None if getattr(F, "realisation", None) is None else t(F.realisation, torch.int32)
+        return cls(t(F.offsets, torch.int64), t(F.ra, torch.float64), t(F.dec, torch.float64),
+                   t(F.dist, torch.float64), t(F.delta, torch.float64), t(F.weight, torch.float64),
+                   t(F.loglam, torch.float64), real, int(getattr(F, "n_realisations", 1)),
+                   np.asarray(F.offsets, np.int64).copy())
+
+    def with_values(self, delta=None, weight=None):
+        return DeviceForests(self.offsets, self.ra, self.dec, self.dist,
+                             self.delta if delta is None else delta,
+                             self.weight if weight is None else weight,
+                             self.loglam, self.realisation, self.n_realisations, self.offsets_host)
+
+    def c_struct(self) -> lya_forests:
+        for name in ("ra", "dec", "dist", "delta", "weight", "loglam"):
+            v = getattr(self, name)
+            if not v.is_contiguous() or str(v.dtype) != "torch.float64":
+                raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+        return lya_forests(self.n_forests, self.n_pix, _ptr(self.offsets), _ptr(self.ra), _ptr(self.dec),
+                           _ptr(self.dist), _ptr(self.delta), _ptr(self.weight), _ptr(self.loglam),
+                           _ptr(self.realisation), int(self.n_realisations))
+
+
+class HostGrid:
+    """Keeps the edge arrays alive for the duration of a call."""
+
+    def __init__(self, grid):
+        self.ep = np.ascontiguousarray(grid.edges_par, np.float64)
+        self.et = np.ascontiguousarray(grid.edges_perp, np.float64)
+        self.n_bins = (self.ep.shape[0] - 1) * (self.et.shape[0] - 1)
+
+    def c_struct(self) -> lya_grid:
+        return lya_grid(self.ep.shape[0] - 1, self.et.shape[0] - 1,
+                        self.ep.ctypes.data, self.et.ctypes.data)
+
+
+class Library:
+    """One lya_context bound to a CUDA device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        import torch
+        self.device = int(device)
+        torch.cuda.init()
+        self.ctx = ctypes.c_void_p()
+        s = self.lib.lya_create(ctypes.byref(self.ctx), self.device)
+        if s != LYA_OK:
+            raise LyaError(s, f"lya_create(device={device}) failed")
+
+    def close(self):
+        if self.ctx:
+            self.lib.lya_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def options(self, precision="fp32", eta="mean_slope", project_deltas=False, autotune=True,
+                validate=True, timing=False, keep_fraction=1.0, seed=0, variant=-1) -> lya_options:
+        o = lya_options()
+        self.lib.lya_options_default(ctypes.byref(o))
+        o.precision = _PRECISION[precision]
+        o.eta = _ETA[eta]
+        o.project_deltas = int(bool(project_deltas))
+        o.autotune = int(bool(autotune))
+        o.validate = int(bool(validate))
+        o.timing = int(bool(timing))
+        o.dmat_keep_fraction = float(keep_fraction)
+        o.seed = int(seed)
+        o.variant = int(variant)
+        return o
+
+    def _check(self, status):
+        if status != LYA_OK:
+            raise LyaError(status, self.lib.lya_last_error(self.ctx).decode())
+
+    def _stream(self, stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(int(stream.cuda_stream))
+
+    def last_stats(self) -> dict:
+        st = lya_stats()
+        self._check(self.lib.lya_last_stats(self.ctx, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in lya_stats._fields_}
+
+    def xi(self, forests: DeviceForests, grid, stream=None, out=None, **opts):
+        """Pair sums and xi; returns dict of [n_realisations, n_bins] tensors."""
+        import torch
+        g = HostGrid(grid)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        if out is None:
+            out = dict(num=torch.empty((R, g.n_bins), dtype=torch.float64, device=dev),
+                       wsum=torch.empty((R, g.n_bins), dtype=torch.float64, device=dev),
+                       npairs=torch.empty((R, g.n_bins), dtype=torch.int64, device=dev),
+                       xi=torch.empty((R, g.n_bins), dtype=torch.float64, device=dev))
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                    self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
+                                    _ptr(out["npairs"]), _ptr(out.get("xi"))))
+        return out
+
+    def dmat(self, forests: DeviceForests, grid, stream=None, out=None, **opts):
+        """Distortion matrix; returns dict(dmat [R, nb, nb], wsum_d [R, nb])."""
+        import torch
+        g = HostGrid(grid)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        if out is None:
+            out = dict(dmat=torch.empty((R, g.n_bins, g.n_bins), dtype=torch.float64, device=dev),
+                       wsum_d=torch.empty((R, g.n_bins), dtype=torch.float64, device=dev))
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_dmat(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                      self._stream(stream), _ptr(out["dmat"]), _ptr(out["wsum_d"])))
+        return out
+
+    def xi_backward(self, forests: DeviceForests, grid, grad_xi, xi, wsum, stream=None, out=None, **opts):
+        """dL/ddelta and dL/dw for dL/dxi = grad_xi; returns (grad_delta, grad_weight)."""
+        import torch
+        g = HostGrid(grid)
+        dev = forests.dist.device
+        if out is None:
+            out = (torch.empty(forests.n_pix, dtype=torch.float64, device=dev),
+                   torch.empty(forests.n_pix, dtype=torch.float64, device=dev))
+        gx, x, w = (t.contiguous().to(torch.float64) for t in (grad_xi, xi, wsum))
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi_backward(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                             self._stream(stream), _ptr(gx), _ptr(x), _ptr(w),
+                                             _ptr(out[0]), _ptr(out[1])))
+        return out
