@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PrecomputeArgs a, lya_forests
       const double uu = act ? w / e.W : 0.0;
       const double bb = e.slope ? w * am / e.S : 0.0;
       const double aa = e.slope ? am : 0.0;
-      if (a.want_d32) a.drec32[i] = DRec32{(float)(D - dc), (float)w, (float)aa, (float)uu, (float)bb, 0.f, 0.f, 0.f};
+      if (a.want_d32) a.drec32[i] = DRec32{(float)(D - dc), (float)w, (float)aa, (float)uu, (float)bb, 0.f, D};
       if (a.want_d64) a.drec64[i] = DRec64{D, w, aa, uu, bb, 0.0};
     }
   }

@@ -23,6 +23,7 @@
 // LDS (ds_add_f64 is native on gfx950 and moves the same bytes as a hi/lo
 // pair of FP32 accumulators); with run-length accumulation, up to 32
 // consecutive products of the same bin are first summed in FP32 registers.
+#include "lya_bin.h"
 #include "lya_common.h"
 
 namespace lya {
@@ -101,21 +102,8 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   const Rec* __restrict__ recs;
   if constexpr (sizeof(T) == 4) recs = a.rec32; else recs = a.rec64;
 
-  // bin-coordinate constants
-  const T e0p = (T)a.g.e0_par, e0t = (T)a.g.e0_perp;
-  const T invp = (T)a.g.inv_par, invt = (T)a.g.inv_perp;
-  T taup, taut;
-  if constexpr (sizeof(T) == 4) {
-    taup = a.glob->tau_par;
-    taut = a.glob->tau_perp;
-  } else {
-    taup = 1e-8;
-    taut = 1e-8;
-  }
-  const T np_hi = (T)NP + taup, nt_hi = (T)NT + taut;
-  const T lo_p = a.g.zero_lo_par ? (T)-1 : -taup;
-  const T lo_t = a.g.zero_lo_perp ? (T)-1 : -taut;
-  const bool zlp = a.g.zero_lo_par, zlt = a.g.zero_lo_perp;
+  BinK<T> K;
+  K.init(a.g, a.glob, a.edges_par, a.edges_perp);
   const double dc2 = 2.0 * a.glob->dc;
 
   int cur_real = -1;
@@ -222,37 +210,15 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
       for (int i = 0; i < nf; ++i) {
         const Rec ri = load_uniform(rf + i);
         T rp, rt;
-        if constexpr (sizeof(T) == 4) {
-          rp = fabsf(ri.d - dj) * cj;
-          rt = fmaf(ri.d + dj, sj, bj);
-        } else {
-          rp = __dmul_rn(fabs(__dsub_rn(ri.d, dj)), cj);
-          rt = __dmul_rn(__dadd_rn(ri.d, dj), sj);
-        }
-        const T xp = (rp - e0p) * invp;
-        const T xt = (rt - e0t) * invt;
-        int A = -1;
-        if ((xp < np_hi) & (xt < nt_hi) & (xp > lo_p) & (xt > lo_t)) {
-          const T rxp = rint(xp), rxt = rint(xt);
-          const bool gp = (fabs(xp - rxp) < taup) & !(zlp & (rxp == (T)0));
-          const bool gt = (fabs(xt - rxt) < taut) & !(zlt & (rxt == (T)0));
-          if (gp | gt) {
-            double rp64, rt64;
-            if constexpr (sizeof(T) == 4) {
-              const double Di = load_uniform(a.dist + fi.pix0 + i);
-              rp64 = __dmul_rn(fabs(__dsub_rn(Di, Dj64)), c64);
-              rt64 = __dmul_rn(__dadd_rn(Di, Dj64), s64);
-            } else {
-              rp64 = rp;
-              rt64 = rt;
-            }
-            const int kp = bin_exact(rp64, a.edges_par, NP, (int)floor((double)xp));
-            const int kt = bin_exact(rt64, a.edges_perp, NT, (int)floor((double)xt));
-            A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
-          } else if ((xp >= (T)0) & (xt >= (T)0) & (xp < (T)NP) & (xt < (T)NT)) {
-            A = (int)xt * NP + (int)xp;
+        separations(ri.d, dj, cj, sj, bj, rp, rt);
+        const int A = K.bin(rp, rt, [&](double& rp64, double& rt64) {
+          if constexpr (sizeof(T) == 4) {
+            separations64(load_uniform(a.dist + fi.pix0 + i), Dj64, c64, s64, rp64, rt64);
+          } else {
+            rp64 = rp;
+            rt64 = rt;
           }
-        }
+        });
         if constexpr (RLE) {
           // a run ends when the bin changes or after kRunMax pairs, which keeps
           // the FP32 rounding of a run sum below kRunMax units in the last place

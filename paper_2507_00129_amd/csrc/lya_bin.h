@@ -1,0 +1,103 @@
+// Pair binning shared by the xi, distortion and backward kernels.
+//
+// A pair's bin coordinates are x = (r - e0) / dr on each axis.  In FP32 the
+// separations carry a bounded rounding error (tau bins, computed per call from
+// the data, see globals_kernel); a pair whose coordinate lies within tau of an
+// integer (a bin edge) is re-evaluated in FP64 with exactly the operations of
+// the FP64 form and binned by comparison with the FP64 edge array, so FP32 and
+// FP64 give the same bin for every pair.  The FP64 form uses the same scheme
+// with a tau of 1e-8 bins to settle ties against the edge array.  A zero lower
+// edge needs no guard because separations are never negative.
+#pragma once
+
+#include "lya_common.h"
+
+namespace lya {
+
+template <typename T>
+struct BinK {
+  T e0p, e0t, invp, invt;
+  T np_hi, nt_hi, lo_p, lo_t;
+  T taup, taut;
+  int NP, NT;
+  bool zlp, zlt;
+  const double* ep;
+  const double* et;
+
+  __device__ __forceinline__ void init(const GridDev& g, const Globals* glob, const double* edges_par,
+                                       const double* edges_perp) {
+    NP = g.n_par;
+    NT = g.n_perp;
+    e0p = (T)g.e0_par;
+    e0t = (T)g.e0_perp;
+    invp = (T)g.inv_par;
+    invt = (T)g.inv_perp;
+    if constexpr (sizeof(T) == 4) {
+      taup = glob->tau_par;
+      taut = glob->tau_perp;
+    } else {
+      taup = 1e-8;
+      taut = 1e-8;
+    }
+    np_hi = (T)NP + taup;
+    nt_hi = (T)NT + taut;
+    zlp = g.zero_lo_par;
+    zlt = g.zero_lo_perp;
+    lo_p = zlp ? (T)-1 : -taup;
+    lo_t = zlt ? (T)-1 : -taut;
+    ep = edges_par;
+    et = edges_perp;
+  }
+
+  // Local (LDS) bin index kt * NP + kp of a pair with separations (rp, rt),
+  // or -1 outside the grid.  exact() returns the FP64 separations; it is
+  // called only for pairs within tau of an edge.
+  template <typename Exact>
+  __device__ __forceinline__ int bin(T rp, T rt, Exact&& exact) const {
+    const T xp = (rp - e0p) * invp;
+    const T xt = (rt - e0t) * invt;
+    int A = -1;
+    if ((xp < np_hi) & (xt < nt_hi) & (xp > lo_p) & (xt > lo_t)) {
+      const T rxp = rint(xp), rxt = rint(xt);
+      const bool gp = (fabs(xp - rxp) < taup) & !(zlp & (rxp == (T)0));
+      const bool gt = (fabs(xt - rxt) < taut) & !(zlt & (rxt == (T)0));
+      if (gp | gt) {
+        double rp64, rt64;
+        exact(rp64, rt64);
+        const int kp = bin_exact(rp64, ep, NP, (int)floor((double)xp));
+        const int kt = bin_exact(rt64, et, NT, (int)floor((double)xt));
+        A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
+      } else if ((xp >= (T)0) & (xt >= (T)0) & (xp < (T)NP) & (xt < (T)NT)) {
+        A = (int)xt * NP + (int)xp;
+      }
+    }
+    return A;
+  }
+};
+
+// Separations of a pixel pair in the working precision.  FP32: distances are
+// re-centred (d = D - dc) and b = fl32(2 dc s), so r_perp = (d_i + d_j) s + b.
+__device__ __forceinline__ void separations(float di, float dj, float c, float s, float b, float& rp,
+                                            float& rt) {
+  rp = fabsf(di - dj) * c;
+  rt = fmaf(di + dj, s, b);
+}
+__device__ __forceinline__ void separations(double di, double dj, double c, double s, double,
+                                            double& rp, double& rt) {
+  rp = __dmul_rn(fabs(__dsub_rn(di, dj)), c);
+  rt = __dmul_rn(__dadd_rn(di, dj), s);
+}
+// FP64 separations exactly as defined (used by the FP32 edge guard too).
+__device__ __forceinline__ void separations64(double Di, double Dj, double c, double s, double& rp,
+                                              double& rt) {
+  rp = __dmul_rn(fabs(__dsub_rn(Di, Dj)), c);
+  rt = __dmul_rn(__dadd_rn(Di, Dj), s);
+}
+
+// Global output index A = kp * NT + kt of a local index L = kt * NP + kp.
+__device__ __forceinline__ int out_index(int L, int NP, int NT) {
+  const int kt = L / NP, kp = L - kt * NP;
+  return kp * NT + kt;
+}
+
+}  // namespace lya

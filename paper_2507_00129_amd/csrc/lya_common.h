@@ -50,7 +50,8 @@ struct __align__(32) Rec64 { double d, wd, w, del; };  // d = D
 
 // Pixel records for the distortion kernel: D, w and the eta factors
 // p = (1, a), q = (u, b) with a = L - lbar, u = w / W, b = w a / S.
-struct __align__(16) DRec32 { float d, w, a, u; float b, pad0, pad1, pad2; };
+// DRec32 also keeps the FP64 distance D for the FP32 edge guard.
+struct __align__(16) DRec32 { float d, w, a, u; float b, pad; double D; };
 struct __align__(16) DRec64 { double d, w, a, u, b, pad; };
 
 // One persistent-kernel work item: forest at sorted position p against the
@@ -219,6 +220,28 @@ int xi_num_variants();
 const char* xi_variant_name(int v);
 hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hipStream_t st);
 int xi_blocks_per_cu(int variant, int precision, int n_bins);
+
+struct DmatArgs {
+  const ForestInfo* finfo;
+  const int32_t* sorted;
+  const int32_t* nbr;      // second forest (sorted position) of each kept pair
+  const int32_t* pair_p;   // first forest (sorted position) of each kept pair
+  int64_t n_pairs;
+  unsigned int* counter;
+  const DRec32* drec32;
+  const DRec64* drec64;
+  const double* edges_par;
+  const double* edges_perp;
+  const Globals* glob;
+  GridDev g;
+  double* dnum;    // [R][nb][nb] numerator of D
+  double* wd;      // [R][nb] sum w_i w_j over the kept pairs
+};
+int dmat_num_variants();
+const char* dmat_variant_name(int v);
+hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
+int dmat_blocks_per_cu(int variant, int precision);
+hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_finalize_xi(const double* num, const double* wsum, double* xi, int64_t n,

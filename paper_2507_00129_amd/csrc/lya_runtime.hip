@@ -539,10 +539,104 @@ lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, con
 
 lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                     void* stream, double* dmat, double* wsum_d) {
-  (void)stream; (void)dmat; (void)wsum_d;
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
-  return fail(ctx, LYA_E_UNSUPPORTED, "lya_dmat not built yet");
+  if (!dmat || !wsum_d) return fail(ctx, LYA_E_INVALID, "NULL output dmat or wsum_d");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->err.clear();
+  ctx->stats = lya_stats{};
+  const int nb = gd.n_par * gd.n_perp;
+  const int64_t R = F->n_realisations;
+  Timer tm{ctx, st, o->timing != 0};
+  tm.at(0);
+  HIP_TRY(launch_zero(dmat, (size_t)R * nb * nb * sizeof(double), st));
+  HIP_TRY(launch_zero(wsum_d, (size_t)R * nb * sizeof(double), st));
+  if (F->n_forests > 0 && F->n_pix > 0) {
+    Prepared P;
+    LYA_TRY(prepare(ctx, F, G, gd, o, st, false, true, false, P));
+    tm.at(1);
+    const bool use_keep = o->dmat_keep_fraction < 1.0;
+    const uint64_t thr = use_keep ? (uint64_t)ldexp(o->dmat_keep_fraction, 64) : ~0ull;
+    Worklist W;
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, use_keep, thr, o->seed, true, 0, "dm", W));
+    tm.at(2);
+    ctx->stats.forest_pairs = W.n_pairs;
+    ctx->stats.work_items = W.n_pairs;
+    unsigned int* counter;
+    LYA_TRY(wst(ctx, "dm_counter", 1, &counter));
+    DmatArgs a{};
+    a.finfo = P.finfo;
+    a.sorted = W.sorted;
+    a.nbr = W.nbr;
+    a.pair_p = W.pair_p;
+    a.n_pairs = W.n_pairs;
+    a.counter = counter;
+    a.drec32 = P.drec32;
+    a.drec64 = P.drec64;
+    a.edges_par = P.edges_par;
+    a.edges_perp = P.edges_perp;
+    a.glob = P.glob;
+    a.g = gd;
+    a.dnum = dmat;
+    a.wd = wsum_d;
+    int variant = 0;
+    if (o->variant >= 0) {
+      if (o->variant >= dmat_num_variants())
+        return fail(ctx, LYA_E_INVALID, "variant %d out of range (dmat has %d)", o->variant, dmat_num_variants());
+      variant = o->variant;
+    } else {
+      char key[96];
+      snprintf(key, sizeof key, "dmat/%d/%d", o->precision, nb);
+      auto found = ctx->tuned.find(key);
+      if (found != ctx->tuned.end()) {
+        variant = found->second;
+      } else if (o->autotune && W.n_pairs > 0) {
+        // time each variant on a prefix of the pair list into scratch outputs
+        double* sd;
+        double* sw;
+        LYA_TRY(wst(ctx, "tune_dnum", (size_t)R * nb * nb, &sd));
+        LYA_TRY(wst(ctx, "tune_wd", (size_t)R * nb, &sw));
+        DmatArgs t = a;
+        t.dnum = sd;
+        t.wd = sw;
+        t.n_pairs = W.n_pairs < 16 * ctx->n_cu ? W.n_pairs : (W.n_pairs / 16 > 16 * ctx->n_cu ? W.n_pairs / 16 : 16 * ctx->n_cu);
+        float best = 1e30f;
+        for (int v = 0; v < dmat_num_variants(); ++v) {
+          const int blocks = dmat_blocks_per_cu(v, o->precision) * ctx->n_cu;
+          float ms_v = 0.f;
+          for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(launch_zero(counter, 4, st));
+            HIP_TRY(hipEventRecord(ctx->ev[6], st));
+            HIP_TRY(launch_dmat(v, o->precision, t, blocks, st));
+            HIP_TRY(hipEventRecord(ctx->ev[7], st));
+            HIP_TRY(hipEventSynchronize(ctx->ev[7]));
+            HIP_TRY(hipEventElapsedTime(&ms_v, ctx->ev[6], ctx->ev[7]));
+          }
+          if (ms_v < best) {
+            best = ms_v;
+            variant = v;
+          }
+        }
+        ctx->tuned[key] = variant;
+      }
+    }
+    const int blocks = dmat_blocks_per_cu(variant, o->precision) * ctx->n_cu;
+    ctx->stats.variant = variant;
+    ctx->stats.grid_blocks = blocks;
+    HIP_TRY(launch_zero(counter, 4, st));
+    tm.at(3);
+    HIP_TRY(launch_dmat(variant, o->precision, a, blocks, st));
+    tm.at(4);
+  } else {
+    tm.at(1);
+    tm.at(2);
+    tm.at(3);
+    tm.at(4);
+  }
+  HIP_TRY(launch_finalize_dmat(dmat, wsum_d, R * nb, nb, st));
+  tm.at(5);
+  return tm.finish(ctx);
 }
 
 lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_grid* G,

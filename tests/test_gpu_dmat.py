@@ -1,0 +1,133 @@
+"""GPU parity of lya_dmat against the FP64 oracle (Sec. 2.2, eq. distortion).
+Tolerances: e_D = max_A max_B |dD_AB| / max_B |D_AB| (row-normwise) and the
+max relative error of w_A, 1e-12 for the FP64 form and 1e-5 for FP32."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import Grid, concat_realisations, make_config, make_patch, subset_forests, uniform_grid
+from synth.survey import nearest_to_centre
+
+from helpers import tiny
+from test_gpu_xi import _ragged_forests
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+G60 = uniform_grid(15, 60.0)
+ETA = {"identity": O.IDENTITY, "mean": O.MEAN, "mean_slope": O.MEAN_SLOPE}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_00129_amd import Library
+    L = Library(0)
+    yield L
+    L.close()
+
+
+def run_dmat(lib, F, G, **kw):
+    from paper_2507_00129_amd import DeviceForests
+    dF = DeviceForests.from_host(F, "cuda:0")
+    out = lib.dmat(dF, G, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def check(out, ref, prec, what):
+    e_d = O.err_rows(out["dmat"], ref.D)
+    e_w = O.err_rel(out["wsum_d"], ref.wd)
+    print(f"[{what} {prec}] rows={int((ref.wd > 0).sum())} e_D={e_d:.3e} e_W={e_w:.3e}", flush=True)
+    assert e_d <= TOL[prec] and e_w <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("eta", ["mean", "mean_slope"])
+def test_tiny_against_four_nested_sums(lib, prec, eta):
+    F = tiny(0, n_forests=3, k=6)
+    G = uniform_grid(4, 24.0, 3, 30.0)
+    pairs = O.dmat_pairs(F, G)
+    ref = O.dmat_brute(F, G, pairs, ETA[eta])
+    out = run_dmat(lib, F, G, precision=prec, eta=eta)
+    check(out, ref, prec, f"tiny-{eta}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_config0(lib, prec, variant):
+    F, G, _ = make_config(0, seed=0)
+    ref = O.dmat(F, G, O.dmat_pairs(F, G))
+    out = run_dmat(lib, F, G, precision=prec, variant=variant, autotune=False)
+    check(out, ref, prec, f"config0-v{variant}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_identity_eta_gives_identity(lib, prec):
+    F, G, _ = make_config(0, seed=1, scale=0.5)
+    out = run_dmat(lib, F, G, precision=prec, eta="identity")
+    D, wd = out["dmat"][0], out["wsum_d"][0]
+    rows = wd > 0
+    assert rows.sum() > 50
+    sub = D[np.ix_(rows, rows)]
+    assert np.abs(np.diag(sub) - 1.0).max() < 1e-13
+    assert not (sub - np.diag(np.diag(sub))).any()
+    assert not D[~rows].any()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("eta", ["mean", "mean_slope"])
+def test_covering_grid_row_sums(lib, prec, eta):
+    """A uniform grid holding every pair of these compact forests (r < 400
+    Mpc/h): the eta rows sum to zero, so every row of D does too."""
+    F = tiny(4, n_forests=6, k=40)
+    G = uniform_grid(50, 400.0)
+    ref = O.xi_sums(F, G)
+    n = np.diff(F.offsets)
+    assert ref.npairs.sum() == (n.sum() ** 2 - np.sum(n ** 2)) // 2
+    out = run_dmat(lib, F, G, precision=prec, eta=eta)
+    D = out["dmat"][0]
+    assert np.abs(D).max() > 0.1
+    assert np.abs(D.sum(1)).max() <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_keep_fraction_subset(lib, prec):
+    F, G, _ = make_config(0, seed=2)
+    p, seed = 0.35, 11
+    ref = O.dmat(F, G, O.dmat_pairs(F, G, p, seed))
+    out = run_dmat(lib, F, G, precision=prec, keep_fraction=p, seed=seed)
+    check(out, ref, prec, "subset")
+    full = run_dmat(lib, F, G, precision=prec)
+    assert O.err_rows(full["dmat"], ref.D) > 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged(lib, prec):
+    F = _ragged_forests(7)
+    ref = O.dmat(F, G60, O.dmat_pairs(F, G60))
+    for v in (0, 1):
+        out = run_dmat(lib, F, G60, precision=prec, variant=v, autotune=False)
+        check(out, ref, prec, f"ragged-v{v}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_realisations(lib, prec):
+    parts = [make_patch(n, 2.0, 60 + r) for r, n in enumerate((20, 33, 27))]
+    F = concat_realisations(parts)
+    ref = O.dmat(F, G60, O.dmat_pairs(F, G60))
+    out = run_dmat(lib, F, G60, precision=prec)
+    assert out["dmat"].shape == (3, G60.n_bins, G60.n_bins)
+    check(out, ref, prec, "realisations")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config1_compact_subpatch(lib, prec):
+    """eBOSS-like forests on the 50x50 grid to 200 Mpc/h (pairs touching more
+    bins than one LDS tile holds)."""
+    F, G, _ = make_config(1, seed=0, scale=0.02)
+    S = subset_forests(F, nearest_to_centre(F, 60))
+    ref = O.dmat(S, G, O.dmat_pairs(S, G))
+    for v in (0, 1):
+        out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
+        check(out, ref, prec, f"config1-sub-v{v}")
