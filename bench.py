@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the Lyman-alpha pair accumulation on one MI355X.
+
+One step = one pass of the whole hot path over the eBOSS-like workload
+(30k forests over 400 deg^2, 50x50 bins to 200 Mpc/h): per-forest precompute,
+device work list, the xi pair kernel and its finalisation, then the
+distortion matrix over the kept forest pairs and its finalisation.  Inputs are
+synthetic (seeded), resident in HBM before the timed region.
+
+value = in-grid pixel pairs of the step (xi pairs + pairs of the kept D forest
+pairs) / step time, for the FP32 form.  The FP64 form is timed the same way
+and reported beside it, with the FP32 form's error against FP64 at full size
+and both forms' errors against the FP64 CPU oracle on a compact sub-patch.
+
+Prints ONE JSON line.  --gpus N > 1 is not supported by this build.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_ALU_OPS = 256 * 64 * 2.4e9          # one VALU op per lane per clock, non-packed
+PEAK_HBM = 8.0e12
+WORKLOADS = {
+    1: "eBOSS-like patch: 30k forests over 400 deg^2, log-lambda pixels (50-150 per forest), "
+       "GRF + unit-noise deltas; xi and D on 50x50 bins to 200 Mpc/h",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_step(lib, dF, G, prec, keep, seed, stream):
+    xo = lib.xi(dF, G, precision=prec, timing=True, stream=stream)
+    sx = lib.last_stats()
+    do = lib.dmat(dF, G, precision=prec, timing=True, keep_fraction=keep, seed=seed, stream=stream)
+    sd = lib.last_stats()
+    return xo, do, sx, sd
+
+
+def time_form(lib, dF, G, prec, keep, seed, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    for w in range(warmup):
+        run_step(lib, dF, G, prec, keep, seed, stream)
+        torch.cuda.synchronize()
+        log(f"[bench] {prec} warmup {w + 1}/{warmup} done")
+    sx_all, sd_all = [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for k in range(steps):
+        xo, do, sx, sd = run_step(lib, dF, G, prec, keep, seed, stream)
+        sx_all.append(sx)
+        sd_all.append(sd)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    log(f"[bench] {prec}: {steps} steps in {wall:.3f} s wall, {dev_ms:.1f} ms device")
+    return xo, do, sx_all, sd_all, wall
+
+
+def mean(xs):
+    return sum(xs) / max(1, len(xs))
+
+
+def cpu_baseline_and_sample_errors(lib, F, G, keep, seed, n_xi, n_d):
+    """The FP64 oracle on a compact sub-patch (timed on one host thread), and the
+    GPU forms' errors against it on the same sample."""
+    import numpy as np
+    import oracle
+    from paper_2507_00129_amd import DeviceForests
+    from synth import subset_forests
+    from synth.survey import nearest_to_centre
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    Sx = subset_forests(F, nearest_to_centre(F, n_xi))
+    Sd = subset_forests(F, nearest_to_centre(F, n_d))
+    t0 = time.perf_counter()
+    X = oracle.xi_sums(Sx, G)
+    t1 = time.perf_counter()
+    pairs = oracle.dmat_pairs(Sd, G, keep, seed)
+    Dr = oracle.dmat(Sd, G, pairs)
+    t2 = time.perf_counter()
+    d_pairs = int(oracle.xi_sums(Sd, G, pairs=pairs).npairs.sum())
+    if limiter is not None:
+        limiter.unregister()
+    xi_pairs = int(X.npairs.sum())
+    errs = {}
+    dSx, dSd = DeviceForests.from_host(Sx), DeviceForests.from_host(Sd)
+    for prec in ("fp32", "fp64"):
+        o = lib.xi(dSx, G, precision=prec)
+        xi = o["xi"].cpu().numpy()
+        same = bool(np.array_equal(o["npairs"].cpu().numpy(), X.npairs))
+        d = lib.dmat(dSd, G, precision=prec, keep_fraction=keep, seed=seed)
+        errs[prec] = dict(e_xi=oracle.err_xi(xi, X.xi, X.wsum, X.absnum),
+                          e_W=oracle.err_rel(o["wsum"].cpu().numpy(), X.wsum),
+                          e_D=oracle.err_rows(d["dmat"].cpu().numpy(), Dr.D),
+                          npairs_exact=same)
+    value = (xi_pairs + d_pairs) / ((t1 - t0) + (t2 - t1))
+    base = dict(value=value, unit="pixel pairs/s", cores=1, kind="oracle",
+                sample=f"FP64 NumPy oracle, one thread: xi on the {n_xi} forests nearest the patch centre "
+                       f"({xi_pairs} in-grid pairs, {t1 - t0:.2f} s) + D on the {n_d} nearest "
+                       f"({d_pairs} in-grid pairs of {len(pairs)} kept forest pairs, {t2 - t1:.2f} s)")
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--keep", type=float, default=1.0, help="distortion-matrix forest-pair keep fraction")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the full-size FP32-vs-FP64 comparison")
+    ap.add_argument("--cpu-xi-forests", type=int, default=150)
+    ap.add_argument("--cpu-d-forests", type=int, default=60)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs the hot path on one GPU only; --gpus N > 1 is not "
+              "supported (the work list would be sharded across GPUs with one all-reduce of the "
+              "sums, which is not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2507_00129_amd import DeviceForests, Library
+    from synth import make_config
+
+    log(f"[bench] generating config {args.config} (seed {args.seed})")
+    F, G, extras = make_config(args.config, seed=args.seed)
+    lib = Library(0)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    torch.cuda.synchronize()
+    log(f"[bench] {F.n_forests} forests, {F.n_pix} pixels resident on the GPU")
+
+    res = {}
+    forms = ["fp32"] if args.no_fp64 else ["fp32", "fp64"]
+    for prec in forms:
+        xo, do, sx, sd, wall = time_form(lib, dF, G, prec, args.keep, args.seed, args.steps, args.warmup)
+        xi_pairs = int(xo["npairs"].sum().item())
+        d_pairs = int(mean([s["ingrid_pairs"] for s in sd]))
+        res[prec] = dict(out_xi={k: v.cpu().numpy() for k, v in xo.items()},
+                         out_d={k: v.cpu().numpy() for k, v in do.items()},
+                         xi_pairs=xi_pairs, d_pairs=d_pairs, wall=wall,
+                         ms_step=1e3 * wall / args.steps,
+                         ms_xi_kernel=mean([s["ms_main"] for s in sx]),
+                         ms_d_kernel=mean([s["ms_main"] for s in sd]),
+                         ms_xi_total=mean([s["ms_precompute"] + s["ms_worklist"] + s["ms_main"] + s["ms_finalize"] for s in sx]),
+                         ms_d_total=mean([s["ms_precompute"] + s["ms_worklist"] + s["ms_main"] + s["ms_finalize"] for s in sd]),
+                         cand=int(sx[-1]["candidate_pairs"]), d_fmas=int(mean([s["outer_fmas"] for s in sd])),
+                         d_forest_pairs=int(sd[-1]["forest_pairs"]), xi_variant=int(sx[-1]["variant"]),
+                         d_variant=int(sd[-1]["variant"]))
+        r = res[prec]
+        r["value"] = (xi_pairs + d_pairs) / (r["ms_step"] / 1e3)
+        log(f"[bench] {prec}: {r['value']:.4e} pairs/s; xi kernel {r['ms_xi_kernel']:.2f} ms "
+            f"({xi_pairs / r['ms_xi_kernel'] * 1e3:.3e} pairs/s), D kernel {r['ms_d_kernel']:.2f} ms "
+            f"({d_pairs / max(r['ms_d_kernel'], 1e-9) * 1e3:.3e} pairs/s)")
+
+    r32 = res["fp32"]
+    # dominant kernel and its roofline (algorithmic work / measured kernel time)
+    if r32["ms_xi_kernel"] >= r32["ms_d_kernel"]:
+        ops = 6.0 * r32["cand"] + 7.0 * r32["xi_pairs"]
+        achieved = ops / (r32["ms_xi_kernel"] / 1e3) / 1e12
+        roof = dict(kernel="xi_kernel<float>", bound="alu", achieved=achieved, peak=PEAK_ALU_OPS / 1e12,
+                    unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12), traffic=None,
+                    work=f"6 ops x {r32['cand']} candidate pairs + 7 ops x {r32['xi_pairs']} in-grid pairs",
+                    ms=r32["ms_xi_kernel"])
+    else:
+        ops = 2.0 * r32["d_fmas"] + 16.0 * r32["d_pairs"]
+        achieved = ops / (r32["ms_d_kernel"] / 1e3) / 1e12
+        roof = dict(kernel="dmat_kernel<float>", bound="alu", achieved=achieved, peak=PEAK_ALU_OPS / 1e12,
+                    unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12), traffic=None,
+                    work=f"2 x {r32['d_fmas']} outer-product FMAs + 16 ops x {r32['d_pairs']} in-grid pairs",
+                    ms=r32["ms_d_kernel"])
+
+    line = dict(metric="pixel pairs/sec for xi + distortion matrix, FP32 vs FP64 at stated rel. error",
+                value=r32["value"], unit="pixel pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=r32["ms_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", data="synthetic",
+                config=dict(workload=WORKLOADS[args.config], forests=F.n_forests, pixels=F.n_pix,
+                            n_bins=G.n_bins, dmat_keep_fraction=args.keep, precision="FP32_COMP",
+                            xi_pairs=r32["xi_pairs"], d_pairs=r32["d_pairs"],
+                            d_forest_pairs=r32["d_forest_pairs"], candidate_pairs=r32["cand"]),
+                roofline=roof)
+    line["xi_pairs_per_s_kernel"] = r32["xi_pairs"] / (r32["ms_xi_kernel"] / 1e3)
+    line["d_pairs_per_s_kernel"] = r32["d_pairs"] / max(r32["ms_d_kernel"] / 1e3, 1e-12)
+    if "fp64" in res:
+        r64 = res["fp64"]
+        line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_step"],
+                            xi_pairs_per_s_kernel=r64["xi_pairs"] / (r64["ms_xi_kernel"] / 1e3),
+                            d_pairs_per_s_kernel=r64["d_pairs"] / max(r64["ms_d_kernel"] / 1e3, 1e-12))
+        line["fp32_over_fp64"] = r32["value"] / r64["value"]
+        if not args.no_check:
+            a32, a64 = r32["out_xi"], r64["out_xi"]
+            absn = lib.xi(dF.with_values(delta=dF.delta.abs()), G, precision="fp64")["num"].cpu().numpy()
+            m = absn > 0
+            d32, d64 = r32["out_d"]["dmat"], r64["out_d"]["dmat"]
+            scale = np.max(np.abs(d64), axis=-1, keepdims=True)
+            scale[scale == 0] = 1.0
+            line["fp32_vs_fp64_full"] = dict(
+                npairs_identical=bool(np.array_equal(a32["npairs"], a64["npairs"])),
+                e_xi=float(np.max(np.abs(a32["num"] - a64["num"])[m] / absn[m])),
+                e_W=float(np.max(np.abs(a32["wsum"] - a64["wsum"])[a64["wsum"] > 0] / a64["wsum"][a64["wsum"] > 0])),
+                e_D=float(np.max(np.abs(d32 - d64) / scale)))
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a compact sub-patch")
+        base, errs = cpu_baseline_and_sample_errors(lib, F, G, args.keep, args.seed,
+                                                    args.cpu_xi_forests, args.cpu_d_forests)
+        line["cpu_baseline"] = base
+        line["vs_oracle_sample"] = errs
+    print(json.dumps(line), flush=True)
+    lib.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -127,6 +127,11 @@ typedef struct {
   int32_t grid_blocks;        /* persistent workgroups launched */
   /* device milliseconds per stage, filled when options.timing != 0 */
   float ms_precompute, ms_worklist, ms_main, ms_finalize;
+  /* lya_dmat with options.timing != 0: pixel pairs inside the grid over the
+     kept forest pairs, and multiply-adds spent on the row outer products and
+     on the H (x) Q term (the algorithmic work of the factorised form) */
+  int64_t ingrid_pairs;
+  int64_t outer_fmas;
 } lya_stats;
 
 typedef struct lya_context lya_context;

@@ -11,3 +11,9 @@ from .lya import (  # noqa: F401
     load_library,
     LYA_OK, LYA_E_INVALID, LYA_E_NOMEM, LYA_E_DEVICE, LYA_E_UNSUPPORTED,
 )
+
+
+def differentiable_xi(*args, **kwargs):
+    """torch-differentiable xi (see paper_2507_00129_amd.autograd.xi)."""
+    from .autograd import xi
+    return xi(*args, **kwargs)

@@ -1,0 +1,208 @@
+// Backward pass of the xi estimator (Sec. 2.1, eq. estimator_two):
+// with gamma_A = (dL/dxi_A) / W_A,
+//   dL/d delta_i = w_i sum_j gamma_{A(i,j)} w_j delta_j
+//   dL/d w_i     = sum_j gamma_{A(i,j)} w_j (delta_i delta_j - xi_{A(i,j)})
+//                = delta_i S1_i - S2_i,  S1_i = sum_j gamma w_j delta_j,
+//                                        S2_i = sum_j gamma xi w_j
+// over every pixel j of every other forest of the same realisation.
+//
+// Work item = one forest f with all of its neighbours (a symmetric neighbour
+// list), so every contribution to f's pixels is summed inside one workgroup
+// and written with plain stores.  Lanes own pixels i of f; the neighbour's
+// pixels j are wave-uniform (scalar loads); the bin of each pair comes from
+// the shared binner and gamma, gamma*xi are gathered from an LDS table.  Waves
+// split the neighbours; each lane sums a neighbour's contributions in the
+// working precision, adds them to FP64 registers, and the waves combine their
+// FP64 sums through LDS.
+#include "lya_bin.h"
+#include "lya_common.h"
+
+namespace lya {
+
+namespace {
+
+constexpr int kGroup = 2048;  // pixels of f handled per pass (LDS accumulators)
+
+template <typename R>
+__device__ __forceinline__ R load_u(const R* p);
+typedef float bw_f4 __attribute__((ext_vector_type(4)));
+typedef double bw_d4 __attribute__((ext_vector_type(4)));
+template <>
+__device__ __forceinline__ Rec32 load_u(const Rec32* p) {
+  const bw_f4 v = *(const __attribute__((address_space(4))) bw_f4*)p;
+  return Rec32{v.x, v.y, v.z, v.w};
+}
+template <>
+__device__ __forceinline__ Rec64 load_u(const Rec64* p) {
+  const bw_d4 v = *(const __attribute__((address_space(4))) bw_d4*)p;
+  return Rec64{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ double load_ud(const double* p) {
+  return *(const __attribute__((address_space(4))) double*)p;
+}
+
+template <typename T> struct RecOfB;
+template <> struct RecOfB<float> { using type = Rec32; };
+template <> struct RecOfB<double> { using type = Rec64; };
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void xi_bwd_kernel(BwdArgs a) {
+  using Rec = typename RecOfB<T>::type;
+  constexpr int NW = BLOCK / 64;
+  extern __shared__ double smem[];
+  const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
+  double* acc1 = smem;                 // [kGroup]
+  double* acc2 = smem + kGroup;        // [kGroup]
+  T* tab = (T*)(smem + 2 * kGroup);    // [nb][2]: gamma, gamma * xi  (local layout)
+  __shared__ int64_t s_item;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  BinK<T> K;
+  K.init(a.g, a.glob, a.edges_par, a.edges_perp);
+  const double dc2 = 2.0 * a.glob->dc;
+  const Rec* __restrict__ recs;
+  if constexpr (sizeof(T) == 4) recs = a.rec32; else recs = a.rec64;
+
+  int cur_real = -1;
+  for (;;) {
+    if (tid == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const int64_t it = s_item;
+    if (it >= a.n_items) break;
+    const Item item = a.items[it];
+    const ForestInfo fi = a.finfo[a.sorted[item.p]];
+    if (fi.real != cur_real) {
+      const double2* src = a.gtab + (int64_t)fi.real * nb;
+      for (int L = tid; L < nb; L += BLOCK) {
+        const double2 v = src[L];
+        tab[2 * L] = (T)v.x;
+        tab[2 * L + 1] = (T)v.y;
+      }
+      cur_real = fi.real;
+    }
+    const Rec* __restrict__ rf = recs + fi.pix0;
+    const int nf = fi.npix;
+
+    for (int g0 = 0; g0 < nf; g0 += kGroup) {
+      const int ng0 = min(kGroup, nf - g0);
+      for (int x = tid; x < ng0; x += BLOCK) {
+        acc1[x] = 0.0;
+        acc2[x] = 0.0;
+      }
+      __syncthreads();
+      for (int ib = 0; ib < ng0; ib += 64) {
+        const int i = g0 + ib + lane;
+        const bool valid = ib + lane < ng0;
+        Rec ri;
+        double Di64 = 0.0;
+        if (valid) {
+          ri = rf[i];
+          if constexpr (sizeof(T) == 4) Di64 = a.dist[fi.pix0 + i];
+        } else {
+          ri.d = (T)1e30;  // far away: never in the grid
+          ri.wd = 0;
+          ri.w = 0;
+          ri.del = 0;
+        }
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = wave; k < item.nb_count; k += NW) {
+          const ForestInfo gi = a.finfo[a.sorted[a.nbr[item.nb_begin + k]]];
+          double s64, c64;
+          pair_sc(fi, gi, s64, c64);
+          const T s = (T)s64, c = (T)c64;
+          const T bsep = sizeof(T) == 4 ? (T)(dc2 * s64) : (T)0;
+          const Rec* __restrict__ rg = recs + gi.pix0;
+          T p1 = 0, p2 = 0;
+          for (int j = 0; j < gi.npix; ++j) {
+            const Rec rj = load_u(rg + j);
+            T rp, rt;
+            separations(ri.d, rj.d, c, s, bsep, rp, rt);
+            const int L = K.bin(rp, rt, [&](double& rp64, double& rt64) {
+              if constexpr (sizeof(T) == 4) {
+                separations64(Di64, load_ud(a.dist + gi.pix0 + j), c64, s64, rp64, rt64);
+              } else {
+                rp64 = rp;
+                rt64 = rt;
+              }
+            });
+            if (L >= 0) {
+              p1 += tab[2 * L] * rj.wd;
+              p2 += tab[2 * L + 1] * rj.w;
+            }
+          }
+          s1 += (double)p1;
+          s2 += (double)p2;
+        }
+        if (valid) {
+          atomicAdd(&acc1[ib + lane], s1);
+          atomicAdd(&acc2[ib + lane], s2);
+        }
+      }
+      __syncthreads();
+      for (int x = tid; x < ng0; x += BLOCK) {
+        const int64_t i = fi.pix0 + g0 + x;
+        const double w = a.weight[i], de = a.delta[i];
+        a.grad_delta[i] = w * acc1[x];
+        a.grad_weight[i] = de * acc1[x] - acc2[x];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// gamma_A = dL/dxi_A / W_A (0 where W_A = 0) and gamma_A xi_A, in the local
+// (LDS) bin order L = kt * NP + kp.
+__global__ void gamma_kernel(const double* grad_xi, const double* xi, const double* wsum,
+                             double2* out, int64_t n, int NP, int NT) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int nb = NP * NT;
+  const int64_t r = idx / nb;
+  const int L = (int)(idx - r * nb);
+  const int kt = L / NP, kp = L - kt * NP;
+  const int64_t A = r * nb + (int64_t)kp * NT + kt;
+  const double w = wsum[A];
+  const double g = w != 0.0 ? grad_xi[A] / w : 0.0;
+  out[idx] = make_double2(g, g * xi[A]);
+}
+
+template <typename T, int BLOCK>
+hipError_t launch_one(const BwdArgs& a, int blocks, hipStream_t st) {
+  const size_t smem = 2 * kGroup * sizeof(double) + (size_t)a.g.n_par * a.g.n_perp * 2 * sizeof(T);
+  auto kern = xi_bwd_kernel<T, BLOCK>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int BLOCK>
+int occupancy(int n_bins) {
+  const size_t smem = 2 * kGroup * sizeof(double) + (size_t)n_bins * 2 * sizeof(T);
+  auto kern = xi_bwd_kernel<T, BLOCK>;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, BLOCK, smem) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+}  // namespace
+
+hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* wsum, double2* out,
+                        int64_t n, int NP, int NT, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, grad_xi, xi, wsum,
+                     out, n, NP, NT);
+  return hipGetLastError();
+}
+
+hipError_t launch_xi_bwd(int precision, const BwdArgs& a, int blocks, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  return precision == LYA_FP64 ? launch_one<double, 512>(a, blocks, st) : launch_one<float, 512>(a, blocks, st);
+}
+
+int xi_bwd_blocks_per_cu(int precision, int n_bins) {
+  return precision == LYA_FP64 ? occupancy<double, 512>(n_bins) : occupancy<float, 512>(n_bins);
+}
+
+}  // namespace lya

@@ -78,6 +78,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
     (&sm.rowG[0][0][0])[x] = 0;
   }
   __syncthreads();
+  unsigned long long n_in = 0, n_fma = 0;  // work counters (statistics only)
 
   for (;;) {
     if (tid == 0) sm.item = (int64_t)atomicAdd(a.counter, 1u);
@@ -112,7 +113,10 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
       const Rec ri = rf[i];
       for (int j = lane; j < ng; j += 64) {
         const int L = pair_bin(ri, rg[j]);
-        if (L >= 0) sm.lidx[L] = 0;
+        if (L >= 0) {
+          sm.lidx[L] = 0;
+          ++n_in;
+        }
       }
     }
     __syncthreads();
@@ -241,6 +245,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             }
             wave_sync();
             const int tot = mA * mB;
+            if (lane == 0) n_fma += 2ull * (unsigned long long)tot;
             const T wneg = -ri.w;
             const float inv = mB ? 1.0f / (float)mB : 0.f;
             for (int idx = lane; idx < tot; idx += 64) {
@@ -267,6 +272,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
         __syncthreads();
 
         // ---- H (x) Q and the Kronecker term, then flush to the global numerator
+        if (tid == 0) n_fma += 4ull * (unsigned long long)(na * nbk);
         for (int idx = tid; idx < na * nbk; idx += BLOCK) {
           const int x = idx / nbk, y = idx - x * nbk;
           T v = sm.H[0][x] * sm.Q[0][y] + sm.H[1][x] * sm.Q[1][y] + sm.H[2][x] * sm.Q[2][y] +
@@ -287,6 +293,17 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
     }
     for (int x = tid; x < Tn; x += BLOCK) sm.lidx[sm.lbins[x]] = 0xFFFF;
     __syncthreads();
+  }
+  if (a.counters) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      n_in += __shfl_xor(n_in, o, 64);
+      n_fma += __shfl_xor(n_fma, o, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&a.counters[0], n_in);
+      atomicAdd(&a.counters[1], n_fma);
+    }
   }
 }
 

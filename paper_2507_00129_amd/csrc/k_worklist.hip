@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void neighbours_kernel(WorklistArgs a) {
   candidate_range(a, p, lo, hi);
   int64_t count = 0;
   int64_t out = kFill ? a.nb_off[p] : 0;
+  unsigned long long pix = 0;
   if (fi.npix > 0) {
     for (int64_t q0 = lo; q0 < hi; q0 += 64) {
       const int64_t q = q0 + lane;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(256) void neighbours_kernel(WorklistArgs a) {
         const int g = a.sorted[q];
         const ForestInfo gi = a.finfo[g];
         ok = gi.npix > 0 && pair_may_bin(fi, gi, a.eperp_max, a.epar_max) && keep_pair(a, f, g);
+        if (!kFill && ok) pix += (unsigned long long)gi.npix;
       }
       const uint64_t m = __ballot(ok);
       if (kFill && ok) {
@@ -96,7 +98,14 @@ __global__ __launch_bounds__(256) void neighbours_kernel(WorklistArgs a) {
       count += c;
     }
   }
-  if (!kFill && lane == 0) a.cnt[p] = count;
+  if (!kFill) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pix += __shfl_xor(pix, o, 64);
+    if (lane == 0) {
+      a.cnt[p] = count;
+      if (a.cand && pix) atomicAdd(a.cand, pix * (unsigned long long)fi.npix);
+    }
+  }
 }
 
 __global__ void count_items_kernel(WorklistArgs a) {

@@ -57,6 +57,31 @@ __device__ __forceinline__ double load_uniform(const double* p) {
   return *(const __attribute__((address_space(4))) double*)p;
 }
 
+// Four FP32 records (64 bytes) or two FP64 records per scalar load.
+typedef float lya_f16 __attribute__((ext_vector_type(16)));
+typedef double lya_d8 __attribute__((ext_vector_type(8)));
+template <typename Rec> struct Batch;
+template <> struct Batch<Rec32> {
+  static constexpr int N = 4;
+  Rec32 r[4];
+  __device__ __forceinline__ void load(const Rec32* p) {
+    const lya_f16 v = *(const __attribute__((address_space(4))) lya_f16*)p;
+    r[0] = Rec32{v[0], v[1], v[2], v[3]};
+    r[1] = Rec32{v[4], v[5], v[6], v[7]};
+    r[2] = Rec32{v[8], v[9], v[10], v[11]};
+    r[3] = Rec32{v[12], v[13], v[14], v[15]};
+  }
+};
+template <> struct Batch<Rec64> {
+  static constexpr int N = 2;
+  Rec64 r[2];
+  __device__ __forceinline__ void load(const Rec64* p) {
+    const lya_d8 v = *(const __attribute__((address_space(4))) lya_d8*)p;
+    r[0] = Rec64{v[0], v[1], v[2], v[3]};
+    r[1] = Rec64{v[4], v[5], v[6], v[7]};
+  }
+};
+
 template <typename T> struct RecOf;
 template <> struct RecOf<float> { using type = Rec32; };
 template <> struct RecOf<double> { using type = Rec64; };
@@ -80,7 +105,7 @@ __device__ void flush_hist(const XiArgs& a, double* hN, double* hW, unsigned* hn
   }
 }
 
-template <typename T, int BLOCK, bool RLE>
+template <typename T, int BLOCK, bool RLE, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   using Rec = typename RecOf<T>::type;
   extern __shared__ double smem[];
@@ -102,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   const Rec* __restrict__ recs;
   if constexpr (sizeof(T) == 4) recs = a.rec32; else recs = a.rec64;
 
-  BinK<T> K;
+  BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
   const double dc2 = 2.0 * a.glob->dc;
 
@@ -206,19 +231,20 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
       T accN = 0, accW = 0;
       unsigned cnt = 0;
 
-#pragma unroll 2
-      for (int i = 0; i < nf; ++i) {
-        const Rec ri = load_uniform(rf + i);
+      auto pair = [&](const Rec& ri, int i) {
         T rp, rt;
         separations(ri.d, dj, cj, sj, bj, rp, rt);
-        const int A = K.bin(rp, rt, [&](double& rp64, double& rt64) {
-          if constexpr (sizeof(T) == 4) {
-            separations64(load_uniform(a.dist + fi.pix0 + i), Dj64, c64, s64, rp64, rt64);
-          } else {
-            rp64 = rp;
-            rt64 = rt;
-          }
-        });
+        int A = -1;
+        if (K.may_be_in(rp, rt)) {
+          A = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
+            if constexpr (sizeof(T) == 4) {
+              separations64(load_uniform(a.dist + fi.pix0 + i), Dj64, c64, s64, rp64, rt64);
+            } else {
+              rp64 = rp;
+              rt64 = rt;
+            }
+          });
+        }
         if constexpr (RLE) {
           // a run ends when the bin changes or after kRunMax pairs, which keeps
           // the FP32 rounding of a run sum below kRunMax units in the last place
@@ -245,7 +271,17 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
             atomicAdd(&hn[A], 1u);
           }
         }
+      };
+
+      constexpr int NB = Batch<Rec>::N;
+      int i = 0;
+      for (; i + NB <= nf; i += NB) {
+        Batch<Rec> b;
+        b.load(rf + i);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) pair(b.r[u], i + u);
       }
+      for (; i < nf; ++i) pair(load_uniform(rf + i), i);
       if constexpr (RLE) {
         if (curA >= 0) {
           atomicAdd(&hN[curA], (double)accN);
@@ -273,31 +309,37 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <typename T, int BLOCK, bool RLE>
+template <typename T, int BLOCK, bool RLE, bool ZLO>
 hipError_t launch_one(const XiArgs& a, int blocks, hipStream_t st) {
   const size_t smem = (size_t)a.g.n_par * a.g.n_perp * (2 * sizeof(double) + sizeof(unsigned));
-  auto kern = xi_kernel<T, BLOCK, RLE>;
+  auto kern = xi_kernel<T, BLOCK, RLE, ZLO>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_t(int v, const XiArgs& a, int blocks, hipStream_t st) {
+template <typename T, bool ZLO>
+hipError_t launch_z(int v, const XiArgs& a, int blocks, hipStream_t st) {
   switch (v) {
-    case 0: return launch_one<T, 256, false>(a, blocks, st);
-    case 1: return launch_one<T, 512, false>(a, blocks, st);
-    case 2: return launch_one<T, 256, true>(a, blocks, st);
-    case 3: return launch_one<T, 512, true>(a, blocks, st);
+    case 0: return launch_one<T, 256, false, ZLO>(a, blocks, st);
+    case 1: return launch_one<T, 512, false, ZLO>(a, blocks, st);
+    case 2: return launch_one<T, 256, true, ZLO>(a, blocks, st);
+    case 3: return launch_one<T, 512, true, ZLO>(a, blocks, st);
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_t(int v, const XiArgs& a, int blocks, hipStream_t st) {
+  const bool zlo = a.g.zero_lo_par && a.g.zero_lo_perp;
+  return zlo ? launch_z<T, true>(v, a, blocks, st) : launch_z<T, false>(v, a, blocks, st);
 }
 
 template <typename T, int BLOCK, bool RLE>
 int occupancy(int n_bins) {
   const size_t smem = (size_t)n_bins * (2 * sizeof(double) + sizeof(unsigned));
-  auto kern = xi_kernel<T, BLOCK, RLE>;
+  auto kern = xi_kernel<T, BLOCK, RLE, true>;
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, BLOCK, smem) != hipSuccess) return 1;

@@ -14,10 +14,13 @@
 
 namespace lya {
 
-template <typename T>
+// ZLO: both first edges are exactly 0 (the usual grid); the lower-edge
+// tests then vanish because separations are never negative.
+template <typename T, bool ZLO = false>
 struct BinK {
   T e0p, e0t, invp, invt;
   T np_hi, nt_hi, lo_p, lo_t;
+  T rp_hi, rt_hi, rp_lo, rt_lo;  // conservative r-space window (rejects most pairs)
   T taup, taut;
   int NP, NT;
   bool zlp, zlt;
@@ -45,8 +48,20 @@ struct BinK {
     zlt = g.zero_lo_perp;
     lo_p = zlp ? (T)-1 : -taup;
     lo_t = zlt ? (T)-1 : -taut;
+    // r-space window: the x-space window widened by one more tau, so that the
+    // FP rounding of the conversion never rejects a pair the x test accepts
+    rp_hi = (T)(g.emax_par + 2.0 * (double)taup / g.inv_par);
+    rt_hi = (T)(g.emax_perp + 2.0 * (double)taut / g.inv_perp);
+    rp_lo = zlp ? (T)-1 : (T)(g.e0_par - 2.0 * (double)taup / g.inv_par);
+    rt_lo = zlt ? (T)-1 : (T)(g.e0_perp - 2.0 * (double)taut / g.inv_perp);
     ep = edges_par;
     et = edges_perp;
+  }
+
+  // Cheap conservative test: false means the pair is certainly outside the grid.
+  __device__ __forceinline__ bool may_be_in(T rp, T rt) const {
+    if constexpr (ZLO) return (rp < rp_hi) & (rt < rt_hi);
+    else return (rp < rp_hi) & (rt < rt_hi) & (rp > rp_lo) & (rt > rt_lo);
   }
 
   // Local (LDS) bin index kt * NP + kp of a pair with separations (rp, rt),
@@ -54,10 +69,23 @@ struct BinK {
   // called only for pairs within tau of an edge.
   template <typename Exact>
   __device__ __forceinline__ int bin(T rp, T rt, Exact&& exact) const {
-    const T xp = (rp - e0p) * invp;
-    const T xt = (rt - e0t) * invt;
+    if (!may_be_in(rp, rt)) return -1;
+    return bin_near(rp, rt, exact);
+  }
+
+  // bin() for a pair that passed may_be_in().
+  template <typename Exact>
+  __device__ __forceinline__ int bin_near(T rp, T rt, Exact&& exact) const {
+    T xp, xt;
+    if constexpr (ZLO) {
+      xp = rp * invp;
+      xt = rt * invt;
+    } else {
+      xp = (rp - e0p) * invp;
+      xt = (rt - e0t) * invt;
+    }
     int A = -1;
-    if ((xp < np_hi) & (xt < nt_hi) & (xp > lo_p) & (xt > lo_t)) {
+    if ((xp < np_hi) & (xt < nt_hi) & (ZLO || ((xp > lo_p) & (xt > lo_t)))) {
       const T rxp = rint(xp), rxt = rint(xt);
       const bool gp = (fabs(xp - rxp) < taup) & !(zlp & (rxp == (T)0));
       const bool gt = (fabs(xt - rxt) < taut) & !(zlt & (rxt == (T)0));
@@ -67,7 +95,7 @@ struct BinK {
         const int kp = bin_exact(rp64, ep, NP, (int)floor((double)xp));
         const int kt = bin_exact(rt64, et, NT, (int)floor((double)xt));
         A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
-      } else if ((xp >= (T)0) & (xt >= (T)0) & (xp < (T)NP) & (xt < (T)NT)) {
+      } else if ((xp < (T)NP) & (xt < (T)NT) & (ZLO || ((xp >= (T)0) & (xt >= (T)0)))) {
         A = (int)xt * NP + (int)xp;
       }
     }

@@ -182,6 +182,7 @@ struct WorklistArgs {
   int64_t* nb_off;        // [n_forests]
   int32_t* nbr;           // neighbour sorted positions
   int32_t* pair_p;        // optional: sorted position of the first forest per entry
+  unsigned long long* cand;  // total candidate pixel pairs (sum n_f n_g), accumulated by the count pass
   int64_t* item_cnt;      // [n_forests]
   int64_t* item_off;
   Item* items;
@@ -236,12 +237,38 @@ struct DmatArgs {
   GridDev g;
   double* dnum;    // [R][nb][nb] numerator of D
   double* wd;      // [R][nb] sum w_i w_j over the kept pairs
+  unsigned long long* counters;  // optional [2]: in-grid pixel pairs, outer-product FMAs
 };
 int dmat_num_variants();
 const char* dmat_variant_name(int v);
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
 int dmat_blocks_per_cu(int variant, int precision);
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st);
+
+struct BwdArgs {
+  const ForestInfo* finfo;
+  const int32_t* sorted;
+  const int32_t* nbr;
+  const Item* items;       // one item per forest, all its neighbours (symmetric list)
+  int64_t n_items;
+  unsigned int* counter;
+  const Rec32* rec32;
+  const Rec64* rec64;
+  const double* dist;
+  const double* weight;
+  const double* delta;
+  const double* edges_par;
+  const double* edges_perp;
+  const Globals* glob;
+  GridDev g;
+  const double2* gtab;     // [R][nb] (gamma, gamma * xi) in local bin order
+  double* grad_delta;
+  double* grad_weight;
+};
+hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* wsum, double2* out,
+                        int64_t n, int NP, int NT, hipStream_t st);
+hipError_t launch_xi_bwd(int precision, const BwdArgs& a, int blocks, hipStream_t st);
+int xi_bwd_blocks_per_cu(int precision, int n_bins);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_finalize_xi(const double* num, const double* wsum, double* xi, int64_t n,

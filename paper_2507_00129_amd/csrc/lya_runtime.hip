@@ -242,6 +242,7 @@ struct Worklist {
   Item* items = nullptr;
   int64_t n_pairs = 0;
   int64_t n_items = 0;
+  int64_t candidates = 0;
 };
 
 lya_status read_i64(lya_context* ctx, const int64_t* dev, int64_t* host, int count, hipStream_t st) {
@@ -297,15 +298,19 @@ lya_status build_worklist(lya_context* ctx, const lya_forests* F, const GridDev&
   a.cub_bytes = worklist_cub_bytes(N);
   LYA_TRY(ws(ctx, "wl_cub", a.cub_bytes, &a.cub_tmp));
 
+  LYA_TRY(wst(ctx, "wl_cand", 1, &a.cand));
+  HIP_TRY(launch_zero(a.cand, sizeof(unsigned long long), st));
   HIP_TRY(launch_sort_forests(a, st));
   HIP_TRY(launch_count_neighbours(a, st));
   HIP_TRY(launch_scan(a.cnt, a.nb_off, N, a.cub_tmp, a.cub_bytes, st));
-  int64_t last[2];
+  int64_t last[3];
   HIP_TRY(hipMemcpyAsync((char*)ctx->pinned, a.cnt + (N - 1), 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 8, a.nb_off + (N - 1), 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 16, a.cand, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  memcpy(last, ctx->pinned, 16);
+  memcpy(last, ctx->pinned, 24);
   const int64_t total = last[0] + last[1];
+  W.candidates = last[2];
   LYA_TRY(wst(ctx, (t + "_nbr").c_str(), (size_t)total, &a.nbr));
   if (want_pairs) LYA_TRY(wst(ctx, (t + "_pair_p").c_str(), (size_t)total, &a.pair_p));
   HIP_TRY(launch_fill_neighbours(a, st));
@@ -454,6 +459,7 @@ lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, con
     tm.at(2);
     ctx->stats.forest_pairs = W.n_pairs;
     ctx->stats.work_items = W.n_items;
+    ctx->stats.candidate_pairs = W.candidates;
     unsigned int* counter;
     LYA_TRY(wst(ctx, "xi_counter", 1, &counter));
     XiArgs a{};
@@ -563,6 +569,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     tm.at(2);
     ctx->stats.forest_pairs = W.n_pairs;
     ctx->stats.work_items = W.n_pairs;
+    ctx->stats.candidate_pairs = W.candidates;
     unsigned int* counter;
     LYA_TRY(wst(ctx, "dm_counter", 1, &counter));
     DmatArgs a{};
@@ -624,10 +631,22 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     const int blocks = dmat_blocks_per_cu(variant, o->precision) * ctx->n_cu;
     ctx->stats.variant = variant;
     ctx->stats.grid_blocks = blocks;
+    unsigned long long* wc = nullptr;
+    if (tm.on) {
+      LYA_TRY(wst(ctx, "dm_work_counters", 2, &wc));
+      HIP_TRY(launch_zero(wc, 2 * sizeof(unsigned long long), st));
+    }
+    a.counters = wc;
     HIP_TRY(launch_zero(counter, 4, st));
     tm.at(3);
     HIP_TRY(launch_dmat(variant, o->precision, a, blocks, st));
     tm.at(4);
+    if (wc) {
+      HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 64, wc, 16, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      ctx->stats.ingrid_pairs = ((int64_t*)((char*)ctx->pinned + 64))[0];
+      ctx->stats.outer_fmas = ((int64_t*)((char*)ctx->pinned + 64))[1];
+    }
   } else {
     tm.at(1);
     tm.at(2);
@@ -643,10 +662,70 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
                            const lya_options* o, void* stream, const double* grad_xi,
                            const double* xi, const double* wsum, double* grad_delta,
                            double* grad_weight) {
-  (void)stream; (void)grad_xi; (void)xi; (void)wsum; (void)grad_delta; (void)grad_weight;
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
-  return fail(ctx, LYA_E_UNSUPPORTED, "lya_xi_backward not built yet");
+  if (!grad_xi || !xi || !wsum) return fail(ctx, LYA_E_INVALID, "NULL grad_xi, xi or wsum");
+  if (!grad_delta || !grad_weight) return fail(ctx, LYA_E_INVALID, "NULL output grad_delta or grad_weight");
+  if (o->project_deltas)
+    return fail(ctx, LYA_E_INVALID, "lya_xi_backward differentiates the deltas as given: project_deltas must be 0");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->err.clear();
+  ctx->stats = lya_stats{};
+  const int nb = gd.n_par * gd.n_perp;
+  const int64_t R = F->n_realisations;
+  Timer tm{ctx, st, o->timing != 0};
+  tm.at(0);
+  HIP_TRY(launch_zero(grad_delta, (size_t)F->n_pix * sizeof(double), st));
+  HIP_TRY(launch_zero(grad_weight, (size_t)F->n_pix * sizeof(double), st));
+  if (F->n_forests > 0 && F->n_pix > 0) {
+    Prepared P;
+    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, false, P));
+    tm.at(1);
+    Worklist W;
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, true, false, 0, 0, false, INT32_MAX, "bw", W));
+    tm.at(2);
+    ctx->stats.forest_pairs = W.n_pairs;
+    ctx->stats.work_items = W.n_items;
+    ctx->stats.candidate_pairs = W.candidates;
+    double2* gtab;
+    LYA_TRY(wst(ctx, "bw_gamma", (size_t)R * nb, &gtab));
+    HIP_TRY(launch_gamma(grad_xi, xi, wsum, gtab, R * nb, gd.n_par, gd.n_perp, st));
+    unsigned int* counter;
+    LYA_TRY(wst(ctx, "bw_counter", 1, &counter));
+    BwdArgs a{};
+    a.finfo = P.finfo;
+    a.sorted = W.sorted;
+    a.nbr = W.nbr;
+    a.items = W.items;
+    a.n_items = W.n_items;
+    a.counter = counter;
+    a.rec32 = P.rec32;
+    a.rec64 = P.rec64;
+    a.dist = F->dist;
+    a.weight = F->weight;
+    a.delta = F->delta;
+    a.edges_par = P.edges_par;
+    a.edges_perp = P.edges_perp;
+    a.glob = P.glob;
+    a.g = gd;
+    a.gtab = gtab;
+    a.grad_delta = grad_delta;
+    a.grad_weight = grad_weight;
+    const int blocks = xi_bwd_blocks_per_cu(o->precision, nb) * ctx->n_cu;
+    ctx->stats.grid_blocks = blocks;
+    HIP_TRY(launch_zero(counter, 4, st));
+    tm.at(3);
+    HIP_TRY(launch_xi_bwd(o->precision, a, blocks, st));
+    tm.at(4);
+  } else {
+    tm.at(1);
+    tm.at(2);
+    tm.at(3);
+    tm.at(4);
+  }
+  tm.at(5);
+  return tm.finish(ctx);
 }
 
 }  // extern "C"

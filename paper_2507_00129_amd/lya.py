@@ -61,6 +61,7 @@ class lya_stats(ctypes.Structure):
         ("candidate_pairs", ctypes.c_int64), ("variant", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("ms_precompute", ctypes.c_float),
         ("ms_worklist", ctypes.c_float), ("ms_main", ctypes.c_float), ("ms_finalize", ctypes.c_float),
+        ("ingrid_pairs", ctypes.c_int64), ("outer_fmas", ctypes.c_int64),
     ]
 
 

@@ -1,0 +1,156 @@
+"""GPU parity of lya_xi_backward (the hand-written gradient of xi) against the
+FP64 oracle gradient, central finite differences and Euler identities.
+e_g = max |dg| / max |g| (normwise): 1e-12 for the FP64 form, 1e-5 for FP32."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import concat_realisations, make_config, make_patch, subset_forests, uniform_grid
+from synth.survey import nearest_to_centre
+
+from test_gpu_xi import _ragged_forests
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+G60 = uniform_grid(15, 60.0)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_00129_amd import Library
+    L = Library(0)
+    yield L
+    L.close()
+
+
+def gpu_grad(lib, F, G, target, prec):
+    from paper_2507_00129_amd import DeviceForests
+    dF = DeviceForests.from_host(F, "cuda:0")
+    out = lib.xi(dF, G, precision=prec)
+    t = torch.as_tensor(target, device="cuda:0").reshape(out["xi"].shape)
+    gxi = 2.0 * (out["xi"] - t)
+    gd, gw = lib.xi_backward(dF, G, gxi, out["xi"], out["wsum"], precision=prec)
+    torch.cuda.synchronize()
+    return gd.cpu().numpy(), gw.cpu().numpy(), out["xi"].cpu().numpy(), out["wsum"].cpu().numpy()
+
+
+_ORACLE_CACHE = {}
+
+
+def oracle_grad(F, G, target, key=None):
+    if key is not None and key in _ORACLE_CACHE:
+        return _ORACLE_CACHE[key]
+    X = O.xi_sums(F, G)
+    gxi = O.loss_grad_xi(X.xi, np.asarray(target).reshape(X.xi.shape))
+    gd, gw = O.xi_grad(F, G, gxi, X.xi, X.wsum)
+    if key is not None:
+        _ORACLE_CACHE[key] = (gd, gw, X)
+    return gd, gw, X
+
+
+def check(gd, gw, rd, rw, prec, what):
+    ed, ew = O.err_norm(gd, rd), O.err_norm(gw, rw)
+    print(f"[{what} {prec}] e_gdelta={ed:.3e} e_gw={ew:.3e}", flush=True)
+    assert ed <= TOL[prec] and ew <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config4_subset_vs_oracle(lib, prec):
+    """The 200 forests nearest the centre of the differentiable workload."""
+    F, G, ex = make_config(4, seed=0, scale=0.05)
+    S = subset_forests(F, nearest_to_centre(F, 200))
+    rd, rw, _ = oracle_grad(S, G, ex["target"], key="config4-200")
+    gd, gw, _, _ = gpu_grad(lib, S, G, ex["target"], prec)
+    check(gd, gw, rd, rw, prec, "config4-200")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_and_realisations(lib, prec):
+    F = _ragged_forests(3)
+    target = np.random.default_rng(1).uniform(-0.01, 0.01, G60.n_bins)
+    rd, rw, _ = oracle_grad(F, G60, target)
+    gd, gw, _, _ = gpu_grad(lib, F, G60, target, prec)
+    check(gd, gw, rd, rw, prec, "ragged")
+    parts = [make_patch(n, 2.0, 80 + r) for r, n in enumerate((25, 40))]
+    R = concat_realisations(parts)
+    tgt = np.random.default_rng(2).uniform(-0.01, 0.01, (2, G60.n_bins))
+    rd, rw, _ = oracle_grad(R, G60, tgt)
+    gd, gw, _, _ = gpu_grad(lib, R, G60, tgt, prec)
+    check(gd, gw, rd, rw, prec, "realisations")
+
+
+def test_finite_differences_on_gpu(lib):
+    """L is quadratic in each delta_i, so central differences of the GPU loss
+    (FP64 form) are exact up to rounding; in w they are O(eps^2)."""
+    from paper_2507_00129_amd import DeviceForests
+    F, G, ex = make_config(4, seed=1, scale=0.02)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    tgt = torch.as_tensor(ex["target"], device="cuda:0")[None, :]
+
+    def loss(d, w):
+        x = lib.xi(dF.with_values(delta=d, weight=w), G, precision="fp64")["xi"]
+        return float(((x - tgt) ** 2).sum())
+
+    out = lib.xi(dF, G, precision="fp64")
+    gd, gw = lib.xi_backward(dF, G, 2.0 * (out["xi"] - tgt), out["xi"], out["wsum"], precision="fp64")
+    gd, gw = gd.cpu().numpy(), gw.cpu().numpy()
+    rng = np.random.default_rng(5)
+    eps = 1e-3
+    for i in rng.choice(F.n_pix, 16, replace=False):
+        d = dF.delta.clone()
+        d[i] += eps
+        lp = loss(d, dF.weight)
+        d[i] -= 2 * eps
+        lm = loss(d, dF.weight)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gd[i]) <= 1e-7 * max(1.0, abs(gd[i])) + 1e-9 * np.abs(gd).max(), (i, fd, gd[i])
+    for i in rng.choice(F.n_pix, 16, replace=False):
+        w = dF.weight.clone()
+        w[i] += eps
+        lp = loss(dF.delta, w)
+        w[i] -= 2 * eps
+        lm = loss(dF.delta, w)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gw[i]) <= 1e-4 * abs(gw[i]) + 1e-6 * np.abs(gw).max(), (i, fd, gw[i])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_euler_identities_full_size(lib, prec):
+    """Full differentiable workload (10k forests, 50x50 bins): xi is homogeneous
+    of degree 2 in delta and 0 in w, so sum delta_i g_delta_i = 4 sum xi (xi - m)
+    and sum w_i g_w_i = 0."""
+    F, G, ex = make_config(4, seed=0)
+    gd, gw, xi, _ = gpu_grad(lib, F, G, ex["target"], prec)
+    lhs = float(np.dot(F.delta, gd))
+    rhs = 4.0 * float(np.sum(xi[0] * (xi[0] - ex["target"])))
+    scale = float(np.dot(np.abs(F.delta), np.abs(gd)))
+    print(f"[euler {prec}] {lhs:.6e} vs {rhs:.6e}; w.gw = {np.dot(F.weight, gw):.3e}", flush=True)
+    assert abs(lhs - rhs) <= TOL[prec] * scale * 10
+    assert abs(np.dot(F.weight, gw)) <= TOL[prec] * float(np.dot(np.abs(F.weight), np.abs(gw))) * 10
+
+
+def test_autograd_function(lib):
+    from paper_2507_00129_amd import DeviceForests, differentiable_xi
+    F, G, ex = make_config(4, seed=2, scale=0.02)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    d = dF.delta.clone().requires_grad_(True)
+    w = dF.weight.clone().requires_grad_(True)
+    xi = differentiable_xi(d, w, lib, dF, G, "fp64")
+    tgt = torch.as_tensor(ex["target"], device="cuda:0")[None, :]
+    L = ((xi - tgt) ** 2).sum()
+    L.backward()
+    gd, gw, _, _ = gpu_grad(lib, F, G, ex["target"], "fp64")
+    assert np.allclose(d.grad.cpu().numpy(), gd, rtol=1e-12, atol=1e-14 * np.abs(gd).max())
+    assert np.allclose(w.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14 * np.abs(gw).max())
+
+
+def test_backward_rejects_projection(lib):
+    from paper_2507_00129_amd import DeviceForests, LyaError, LYA_E_INVALID
+    F, G, _ = make_config(0, seed=0, scale=0.2)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    out = lib.xi(dF, G)
+    with pytest.raises(LyaError) as ei:
+        lib.xi_backward(dF, G, out["xi"], out["xi"], out["wsum"], project_deltas=True)
+    assert ei.value.status == LYA_E_INVALID
