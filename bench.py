@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the full-size FP32-vs-FP64 comparison")
     ap.add_argument("--cpu-xi-forests", type=int, default=150)
     ap.add_argument("--cpu-d-forests", type=int, default=60)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the hot path on one GPU only; --gpus N > 1 is not "
@@ -141,6 +144,15 @@ def main():
     from paper_2507_00129_amd import DeviceForests, Library
     from synth import make_config
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     log(f"[bench] generating config {args.config} (seed {args.seed})")
     F, G, extras = make_config(args.config, seed=args.seed)
     lib = Library(0)

@@ -45,7 +45,7 @@ template <typename T> struct RecOfB;
 template <> struct RecOfB<float> { using type = Rec32; };
 template <> struct RecOfB<double> { using type = Rec64; };
 
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void xi_bwd_kernel(BwdArgs a) {
   using Rec = typename RecOfB<T>::type;
   constexpr int NW = BLOCK / 64;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BLOCK) void xi_bwd_kernel(BwdArgs a) {
   __shared__ int64_t s_item;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  BinK<T> K;
+  BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
   const double dc2 = 2.0 * a.glob->dc;
   const Rec* __restrict__ recs;
@@ -169,7 +169,7 @@ __global__ void gamma_kernel(const double* grad_xi, const double* xi, const doub
 template <typename T, int BLOCK>
 hipError_t launch_one(const BwdArgs& a, int blocks, hipStream_t st) {
   const size_t smem = 2 * kGroup * sizeof(double) + (size_t)a.g.n_par * a.g.n_perp * 2 * sizeof(T);
-  auto kern = xi_bwd_kernel<T, BLOCK>;
+  auto kern = (a.g.zero_lo_par && a.g.zero_lo_perp) ? xi_bwd_kernel<T, BLOCK, true> : xi_bwd_kernel<T, BLOCK, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
@@ -179,7 +179,7 @@ hipError_t launch_one(const BwdArgs& a, int blocks, hipStream_t st) {
 template <typename T, int BLOCK>
 int occupancy(int n_bins) {
   const size_t smem = 2 * kGroup * sizeof(double) + (size_t)n_bins * 2 * sizeof(T);
-  auto kern = xi_bwd_kernel<T, BLOCK>;
+  auto kern = xi_bwd_kernel<T, BLOCK, true>;
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, BLOCK, smem) != hipSuccess) return 1;

@@ -53,7 +53,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T, int BLOCK, int TB>
+template <typename T, int BLOCK, int TB, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   static_assert(TB <= 255, "compact lists use 8-bit indices");
   using Rec = typename DRecOf<T>::type;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   __shared__ DmatSmem<T, BLOCK, TB> sm;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  BinK<T> K;
+  BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
   const int NP = K.NP, NT = K.NT, nb = NP * NT;
   const double dc2 = 2.0 * a.glob->dc;
@@ -318,14 +318,17 @@ template <typename T> constexpr int tb_small() { return sizeof(T) == 4 ? 64 : 48
 
 template <typename T, int BLOCK, int TB>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((dmat_kernel<T, BLOCK, TB>), dim3(blocks), dim3(BLOCK), 0, st, a);
+  if (a.g.zero_lo_par && a.g.zero_lo_perp)
+    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, TB, true>), dim3(blocks), dim3(BLOCK), 0, st, a);
+  else
+    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, TB, false>), dim3(blocks), dim3(BLOCK), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T, int BLOCK, int TB>
 int occupancy() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_kernel<T, BLOCK, TB>, BLOCK, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_kernel<T, BLOCK, TB, true>, BLOCK, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
