@@ -132,6 +132,9 @@ typedef struct {
      on the H (x) Q term (the algorithmic work of the factorised form) */
   int64_t ingrid_pairs;
   int64_t outer_fmas;
+  /* lya_dmat with options.timing != 0: in-grid pixel pairs that fell outside
+     their forest pair's precomputed r_perp window (a consistency check: 0) */
+  int64_t lost_pairs;
 } lya_stats;
 
 typedef struct lya_context lya_context;

@@ -12,12 +12,19 @@
 // G^l_i[B] = sum_{j: A(i,j)=B} q_j^l (C, F alike with f and g swapped) and
 // pair histograms H^kl_A = sum_{A} w_i p_i^k w_j p_j^l, Q^kl_B = sum_B q_i^k q_j^l.
 //
-// One workgroup handles one forest pair at a time (persistent, atomic work
-// counter).  The bins the pair touches are compacted to local indices; the
-// local x local block of D is accumulated in an LDS tile (in column/row
-// blocks of TB if the pair touches more than TB bins) and added to the global
-// FP64 numerator with atomics.  Bins are computed by the shared binner, so a
-// pixel pair falls in the same bin here as in the xi kernel.
+// Work layout.  A forest pair only reaches the r_perp bins between
+// (Dmin_f + Dmin_g) s and (Dmax_f + Dmax_g) s, a "window" of a few k_perp
+// rows, so D is banded in k_perp.  Kept pairs are sorted by (realisation,
+// first k_perp, span); a work item is a chunk of consecutive sorted pairs, and
+// all pairs of a chunk that share a window accumulate into one FP64 LDS tile
+// over that window (in blocks of kTileW x kTileW window bins when the window
+// is wider), which is added to the global FP64 numerator once per chunk.  The
+// waves of a workgroup process different forest pairs of the chunk at the same
+// time; within a wave the lanes sweep the pixels of one forest against one
+// pixel of the other, building the row histograms (and, in the first sweep,
+// H and Q) in wave-private LDS, and each row's outer product is added to the
+// tile.  Bins come from the shared binner, so a pixel pair falls in the same
+// bin here as in the xi kernel.
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -25,27 +32,20 @@ namespace lya {
 
 namespace {
 
+constexpr int kTileW = 100;  // window bins per tile side: 100 x 100 FP64 = 80 KB
+
 template <typename T> struct DRecOf;
 template <> struct DRecOf<float> { using type = DRec32; };
 template <> struct DRecOf<double> { using type = DRec64; };
 
-template <typename T, int BLOCK, int TB>
-struct DmatSmem {
-  static constexpr int NW = BLOCK / 64;
-  uint16_t lidx[kMaxBins];   // local grid bin L -> compact index (0xFFFF: untouched)
-  uint16_t lbins[kMaxBins];  // compact index -> L
-  T tile[TB * TB];
-  T H[4][TB];
-  T Q[4][TB];
-  T rowR[NW][2][TB];
-  T rowG[NW][2][TB];
-  uint8_t flA[NW][TB];
-  uint8_t flB[NW][TB];
-  uint8_t listA[NW][TB];
-  uint8_t listB[NW][TB];
-  int32_t scan[NW + 1];
-  int64_t item;
-  int32_t ntouch;
+template <typename T>
+struct WaveBuf {
+  T H[4][kTileW];
+  T Q[4][kTileW];
+  T R[2][kTileW];
+  T G[2][kTileW];
+  uint8_t fA[kTileW], fB[kTileW], fH[kTileW], fQ[kTileW];
+  uint8_t lA[kTileW], lB[kTileW], lH[kTileW], lQ[kTileW];
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -53,12 +53,46 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T, int BLOCK, int TB, bool ZLO>
+// Compacts the flagged entries of fl[0..n) into list (ascending) and clears
+// the flags.  Returns the count (wave-uniform).
+__device__ __forceinline__ int wave_compact(uint8_t* fl, uint8_t* list, int n, int lane) {
+  int m = 0;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int x0 = 0; x0 < n; x0 += 64) {
+    const int x = x0 + lane;
+    const bool on = x < n && fl[x];
+    const uint64_t b = __ballot(on);
+    if (on) {
+      list[m + __popcll(b & lt)] = (uint8_t)x;
+      fl[x] = 0;
+    }
+    m += __popcll(b);
+  }
+  return m;
+}
+
+// Calls f(x, y) for every x in la[0..ma), y in lb[0..mb), spread over the lanes.
+template <typename F>
+__device__ __forceinline__ void wave_outer(const uint8_t* la, int ma, const uint8_t* lb, int mb, int lane,
+                                           F&& f) {
+  const int tot = ma * mb;
+  const float inv = mb ? 1.0f / (float)mb : 0.f;
+  for (int idx = lane; idx < tot; idx += 64) {
+    int u = (int)((float)idx * inv);
+    if (u * mb > idx) --u;
+    else if ((u + 1) * mb <= idx) ++u;
+    f((int)la[u], (int)lb[idx - u * mb]);
+  }
+}
+
+template <typename T, int BLOCK, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
-  static_assert(TB <= 255, "compact lists use 8-bit indices");
   using Rec = typename DRecOf<T>::type;
-  constexpr int NW = BLOCK / 64;
-  __shared__ DmatSmem<T, BLOCK, TB> sm;
+  constexpr int NW = BLOCK / 64, TW = kTileW;
+  __shared__ double tile[TW * TW];
+  __shared__ double wdacc[TW];
+  __shared__ WaveBuf<T> wbuf[NW];
+  __shared__ int64_t s_item;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   BinK<T, ZLO> K;
@@ -67,281 +101,271 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   const double dc2 = 2.0 * a.glob->dc;
   const Rec* __restrict__ recs;
   if constexpr (sizeof(T) == 4) recs = a.drec32; else recs = a.drec64;
-
-  for (int L = tid; L < nb; L += BLOCK) sm.lidx[L] = 0xFFFF;
-  for (int x = tid; x < NW * TB; x += BLOCK) {
-    (&sm.flA[0][0])[x] = 0;
-    (&sm.flB[0][0])[x] = 0;
+  WaveBuf<T>& W = wbuf[wave];
+  for (int x = lane; x < TW; x += 64) {
+    for (int m = 0; m < 4; ++m) {
+      W.H[m][x] = 0;
+      W.Q[m][x] = 0;
+    }
+    W.R[0][x] = W.R[1][x] = W.G[0][x] = W.G[1][x] = 0;
+    W.fA[x] = W.fB[x] = W.fH[x] = W.fQ[x] = 0;
   }
-  for (int x = tid; x < NW * 2 * TB; x += BLOCK) {
-    (&sm.rowR[0][0][0])[x] = 0;
-    (&sm.rowG[0][0][0])[x] = 0;
-  }
-  __syncthreads();
-  unsigned long long n_in = 0, n_fma = 0;  // work counters (statistics only)
+  unsigned long long n_in = 0, n_fma = 0, n_lost = 0;  // statistics only
 
   for (;;) {
-    if (tid == 0) sm.item = (int64_t)atomicAdd(a.counter, 1u);
+    if (tid == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
-    const int64_t k = sm.item;
-    if (k >= a.n_pairs) break;
-    const ForestInfo fi = a.finfo[a.sorted[a.pair_p[k]]];
-    const ForestInfo gi = a.finfo[a.sorted[a.nbr[k]]];
-    double s64, c64;
-    pair_sc(fi, gi, s64, c64);
-    const T s = (T)s64, c = (T)c64;
-    const T bsep = sizeof(T) == 4 ? (T)(dc2 * s64) : (T)0;
-    const Rec* __restrict__ rf = recs + fi.pix0;
-    const Rec* __restrict__ rg = recs + gi.pix0;
-    const int nf = fi.npix, ng = gi.npix;
-
-    auto pair_bin = [&](const Rec& ri, const Rec& rj) -> int {
-      T rp, rt;
-      separations(ri.d, rj.d, c, s, bsep, rp, rt);
-      return K.bin(rp, rt, [&](double& rp64, double& rt64) {
-        if constexpr (sizeof(T) == 4) {
-          separations64(ri.D, rj.D, c64, s64, rp64, rt64);
-        } else {
-          rp64 = rp;
-          rt64 = rt;
-        }
-      });
-    };
-
-    // ---- touched bins and their compact indices
-    for (int i = wave; i < nf; i += NW) {
-      const Rec ri = rf[i];
-      for (int j = lane; j < ng; j += 64) {
-        const int L = pair_bin(ri, rg[j]);
-        if (L >= 0) {
-          sm.lidx[L] = 0;
-          ++n_in;
-        }
+    const int64_t it = s_item;
+    if (it >= a.n_items) break;
+    const int64_t k0 = it * a.chunk;
+    const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
+    for (int64_t r0 = k0; r0 < k1;) {
+      const uint64_t key = a.wkeys[r0];
+      int64_t lo = r0 + 1, hi = k1;  // end of the run of equal keys
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.wkeys[mid] == key) lo = mid + 1; else hi = mid;
       }
-    }
-    __syncthreads();
-    {
-      const int C = (nb + BLOCK - 1) / BLOCK;
-      const int L0 = tid * C, L1 = min(nb, L0 + C);
-      int cnt = 0;
-      for (int L = L0; L < L1; ++L) cnt += sm.lidx[L] == 0;
-      int incl = cnt;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += v;
+      const int64_t r1 = lo;
+      if (key == ~0ull) {
+        r0 = r1;
+        continue;
       }
-      if (lane == 63) sm.scan[wave + 1] = incl;
-      __syncthreads();
-      if (tid == 0) {
-        sm.scan[0] = 0;
-        for (int w = 1; w <= NW; ++w) sm.scan[w] += sm.scan[w - 1];
-        sm.ntouch = sm.scan[NW];
-      }
-      __syncthreads();
-      int pos = sm.scan[wave] + incl - cnt;
-      for (int L = L0; L < L1; ++L)
-        if (sm.lidx[L] == 0) {
-          sm.lidx[L] = (uint16_t)pos;
-          sm.lbins[pos] = (uint16_t)L;
-          ++pos;
-        }
-    }
-    __syncthreads();
-    const int Tn = sm.ntouch;
-    const int nblk = (Tn + TB - 1) / TB;
-    const int64_t obase = (int64_t)fi.real * nb;
+      const int real = (int)(key >> 40);
+      const int kt0 = (int)((key >> 16) & 0xFFFFFF);
+      const int span = (int)(key & 0xFFFF);
+      const int nwin = span * NP;
+      const int base_L = kt0 * NP;  // window index w = L - kt0 NP
+      const int nblk = (nwin + TW - 1) / TW;
+      const int64_t obase = (int64_t)real * nb;
+      auto win_out = [&](int w) { return out_index(w + base_L, NP, NT); };
 
-    for (int ab = 0; ab < nblk; ++ab) {
-      const int a0 = ab * TB, na = min(TB, Tn - a0);
-      for (int bb = 0; bb < nblk; ++bb) {
-        const int b0 = bb * TB, nbk = min(TB, Tn - b0);
-        for (int x = tid; x < na * nbk; x += BLOCK) sm.tile[x] = 0;
-        for (int x = tid; x < 4 * TB; x += BLOCK) {
-          (&sm.H[0][0])[x] = 0;
-          (&sm.Q[0][0])[x] = 0;
-        }
-        __syncthreads();
+      for (int ab = 0; ab < nblk; ++ab) {
+        const int a0 = ab * TW, na = min(TW, nwin - a0);
+        for (int bb = 0; bb < nblk; ++bb) {
+          const int b0 = bb * TW, nbk = min(TW, nwin - b0);
+          for (int e = tid; e < na * nbk; e += BLOCK) tile[e] = 0.0;
+          for (int x = tid; x < na; x += BLOCK) wdacc[x] = 0.0;
+          __syncthreads();
+          const bool first_pass = ab == 0 && bb == 0;
 
-        // ---- pair histograms H (rows of this block) and Q (columns)
-        for (int i = wave; i < nf; i += NW) {
-          const Rec ri = rf[i];
-          for (int j = lane; j < ng; j += 64) {
-            const Rec rj = rg[j];
-            const int L = pair_bin(ri, rj);
-            if (L < 0) continue;
-            const int la = sm.lidx[L];
-            const int x = la - a0, y = la - b0;
-            if ((unsigned)x < (unsigned)na) {
-              const T ww = ri.w * rj.w;
-              atomicAdd(&sm.H[0][x], ww);
-              atomicAdd(&sm.H[1][x], ww * rj.a);
-              atomicAdd(&sm.H[2][x], ri.a * ww);
-              atomicAdd(&sm.H[3][x], ri.a * ww * rj.a);
+          for (int64_t kk = r0 + wave; kk < r1; kk += NW) {
+            const int q = a.worder[kk];
+            const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
+            const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
+            double s64, c64;
+            pair_sc(fi, gi, s64, c64);
+            const T s = (T)s64, c = (T)c64;
+            const T bsep = sizeof(T) == 4 ? (T)(dc2 * s64) : (T)0;
+            const Rec* __restrict__ rf = recs + fi.pix0;
+            const Rec* __restrict__ rg = recs + gi.pix0;
+            const int nf = fi.npix, ng = gi.npix;
+
+            // window index of pixel pair (ri in f, rj in g), or -1
+            auto wbin = [&](const Rec& ri, const Rec& rj) -> int {
+              T rp, rt;
+              separations(ri.d, rj.d, c, s, bsep, rp, rt);
+              if (!K.may_be_in(rp, rt)) return -1;
+              const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
+                if constexpr (sizeof(T) == 4) {
+                  separations64(ri.D, rj.D, c64, s64, rp64, rt64);
+                } else {
+                  rp64 = rp;
+                  rt64 = rt;
+                }
+              });
+              if (L < 0) return -1;
+              const int w = L - base_L;
+              if ((unsigned)w >= (unsigned)nwin) {
+                ++n_lost;
+                return -1;
+              }
+              return w;
+            };
+
+            // ---- sweep 1: rows i of f; R, G per row and the pair histograms H, Q
+            for (int i = 0; i < nf; ++i) {
+              const Rec ri = rf[i];
+              for (int j = lane; j < ng; j += 64) {
+                const Rec rj = rg[j];
+                const int w = wbin(ri, rj);
+                if (w < 0) continue;
+                if (first_pass) ++n_in;
+                const int x = w - a0, y = w - b0;
+                if ((unsigned)x < (unsigned)na) {
+                  const T ww = ri.w * rj.w;
+                  atomicAdd(&W.R[0][x], rj.w);
+                  atomicAdd(&W.R[1][x], rj.w * rj.a);
+                  atomicAdd(&W.H[0][x], ww);
+                  atomicAdd(&W.H[1][x], ww * rj.a);
+                  atomicAdd(&W.H[2][x], ri.a * ww);
+                  atomicAdd(&W.H[3][x], ri.a * ww * rj.a);
+                  W.fA[x] = 1;
+                  W.fH[x] = 1;
+                }
+                if ((unsigned)y < (unsigned)nbk) {
+                  atomicAdd(&W.G[0][y], rj.u);
+                  atomicAdd(&W.G[1][y], rj.b);
+                  atomicAdd(&W.Q[0][y], ri.u * rj.u);
+                  atomicAdd(&W.Q[1][y], ri.u * rj.b);
+                  atomicAdd(&W.Q[2][y], ri.b * rj.u);
+                  atomicAdd(&W.Q[3][y], ri.b * rj.b);
+                  W.fB[y] = 1;
+                  W.fQ[y] = 1;
+                }
+              }
+              wave_sync();
+              const int mA = wave_compact(W.fA, W.lA, na, lane);
+              const int mB = wave_compact(W.fB, W.lB, nbk, lane);
+              wave_sync();
+              const T wneg = -ri.w;
+              wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
+                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[0][x] * W.G[0][y] + W.R[1][x] * W.G[1][y])));
+              });
+              if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
+              wave_sync();
+              for (int u = lane; u < mA; u += 64) W.R[0][W.lA[u]] = W.R[1][W.lA[u]] = 0;
+              for (int v = lane; v < mB; v += 64) W.G[0][W.lB[v]] = W.G[1][W.lB[v]] = 0;
+              wave_sync();
             }
-            if ((unsigned)y < (unsigned)nbk) {
-              atomicAdd(&sm.Q[0][y], ri.u * rj.u);
-              atomicAdd(&sm.Q[1][y], ri.u * rj.b);
-              atomicAdd(&sm.Q[2][y], ri.b * rj.u);
-              atomicAdd(&sm.Q[3][y], ri.b * rj.b);
+
+            // ---- H (x) Q and the Kronecker term of this pair
+            {
+              const int mH = wave_compact(W.fH, W.lH, na, lane);
+              const int mQ = wave_compact(W.fQ, W.lQ, nbk, lane);
+              wave_sync();
+              wave_outer(W.lH, mH, W.lQ, mQ, lane, [&](int x, int y) {
+                double v = (double)(W.H[0][x] * W.Q[0][y] + W.H[1][x] * W.Q[1][y] +
+                                    W.H[2][x] * W.Q[2][y] + W.H[3][x] * W.Q[3][y]);
+                if (a0 + x == b0 + y) v += (double)W.H[0][x];
+                atomicAdd(&tile[x * nbk + y], v);
+              });
+              if (bb == 0)
+                for (int u = lane; u < mH; u += 64) atomicAdd(&wdacc[W.lH[u]], (double)W.H[0][W.lH[u]]);
+              if (lane == 0) n_fma += 4ull * (unsigned long long)(mH * mQ);
+              wave_sync();
+              for (int u = lane; u < mH; u += 64) {
+                const int x = W.lH[u];
+                W.H[0][x] = W.H[1][x] = W.H[2][x] = W.H[3][x] = 0;
+              }
+              for (int v = lane; v < mQ; v += 64) {
+                const int y = W.lQ[v];
+                W.Q[0][y] = W.Q[1][y] = W.Q[2][y] = W.Q[3][y] = 0;
+              }
+              wave_sync();
+            }
+
+            // ---- sweep 2: rows j of g; C, F per row (roles of f and g swapped)
+            for (int j = 0; j < ng; ++j) {
+              const Rec rj = rg[j];
+              for (int i = lane; i < nf; i += 64) {
+                const Rec ri = rf[i];
+                const int w = wbin(ri, rj);
+                if (w < 0) continue;
+                const int x = w - a0, y = w - b0;
+                if ((unsigned)x < (unsigned)na) {
+                  atomicAdd(&W.R[0][x], ri.w);
+                  atomicAdd(&W.R[1][x], ri.w * ri.a);
+                  W.fA[x] = 1;
+                }
+                if ((unsigned)y < (unsigned)nbk) {
+                  atomicAdd(&W.G[0][y], ri.u);
+                  atomicAdd(&W.G[1][y], ri.b);
+                  W.fB[y] = 1;
+                }
+              }
+              wave_sync();
+              const int mA = wave_compact(W.fA, W.lA, na, lane);
+              const int mB = wave_compact(W.fB, W.lB, nbk, lane);
+              wave_sync();
+              const T wneg = -rj.w;
+              wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
+                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[0][x] * W.G[0][y] + W.R[1][x] * W.G[1][y])));
+              });
+              if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
+              wave_sync();
+              for (int u = lane; u < mA; u += 64) W.R[0][W.lA[u]] = W.R[1][W.lA[u]] = 0;
+              for (int v = lane; v < mB; v += 64) W.G[0][W.lB[v]] = W.G[1][W.lB[v]] = 0;
+              wave_sync();
             }
           }
-        }
+          __syncthreads();
 
-        // ---- row outer products: rows of f (side 0) then rows of g (side 1)
-        T* R0 = sm.rowR[wave][0];
-        T* R1 = sm.rowR[wave][1];
-        T* G0 = sm.rowG[wave][0];
-        T* G1 = sm.rowG[wave][1];
-        uint8_t* fA = sm.flA[wave];
-        uint8_t* fB = sm.flB[wave];
-        uint8_t* lA = sm.listA[wave];
-        uint8_t* lB = sm.listB[wave];
-        const uint64_t lt_mask = (1ull << lane) - 1ull;
-        for (int side = 0; side < 2; ++side) {
-          const Rec* __restrict__ rrow = side ? rg : rf;
-          const Rec* __restrict__ rcol = side ? rf : rg;
-          const int nrow = side ? ng : nf, ncol = side ? nf : ng;
-          for (int i = wave; i < nrow; i += NW) {
-            const Rec ri = rrow[i];
-            for (int j = lane; j < ncol; j += 64) {
-              const Rec rj = rcol[j];
-              const int L = pair_bin(ri, rj);
-              if (L < 0) continue;
-              const int la = sm.lidx[L];
-              const int x = la - a0, y = la - b0;
-              if ((unsigned)x < (unsigned)na) {
-                atomicAdd(&R0[x], rj.w);
-                atomicAdd(&R1[x], rj.w * rj.a);
-                fA[x] = 1;
-              }
-              if ((unsigned)y < (unsigned)nbk) {
-                atomicAdd(&G0[y], rj.u);
-                atomicAdd(&G1[y], rj.b);
-                fB[y] = 1;
-              }
+          // ---- add the tile block to the global numerator (and w_A)
+          for (int e = tid; e < na * nbk; e += BLOCK) {
+            const double v = tile[e];
+            if (v != 0.0) {
+              const int x = e / nbk, y = e - x * nbk;
+              atomicAdd(&a.dnum[(obase + win_out(a0 + x)) * nb + win_out(b0 + y)], v);
             }
-            wave_sync();
-            int mA = 0, mB = 0;
-            for (int x0 = 0; x0 < na; x0 += 64) {
-              const int x = x0 + lane;
-              const bool on = x < na && fA[x];
-              const uint64_t m = __ballot(on);
-              if (on) {
-                lA[mA + __popcll(m & lt_mask)] = (uint8_t)x;
-                fA[x] = 0;
-              }
-              mA += __popcll(m);
-            }
-            for (int y0 = 0; y0 < nbk; y0 += 64) {
-              const int y = y0 + lane;
-              const bool on = y < nbk && fB[y];
-              const uint64_t m = __ballot(on);
-              if (on) {
-                lB[mB + __popcll(m & lt_mask)] = (uint8_t)y;
-                fB[y] = 0;
-              }
-              mB += __popcll(m);
-            }
-            wave_sync();
-            const int tot = mA * mB;
-            if (lane == 0) n_fma += 2ull * (unsigned long long)tot;
-            const T wneg = -ri.w;
-            const float inv = mB ? 1.0f / (float)mB : 0.f;
-            for (int idx = lane; idx < tot; idx += 64) {
-              int u = (int)((float)idx * inv);
-              if (u * mB > idx) --u;
-              else if ((u + 1) * mB <= idx) ++u;
-              const int x = lA[u], y = lB[idx - u * mB];
-              atomicAdd(&sm.tile[x * nbk + y], wneg * (R0[x] * G0[y] + R1[x] * G1[y]));
-            }
-            wave_sync();
-            for (int u = lane; u < mA; u += 64) {
-              const int x = lA[u];
-              R0[x] = 0;
-              R1[x] = 0;
-            }
-            for (int v = lane; v < mB; v += 64) {
-              const int y = lB[v];
-              G0[y] = 0;
-              G1[y] = 0;
-            }
-            wave_sync();
           }
+          if (bb == 0)
+            for (int x = tid; x < na; x += BLOCK)
+              if (wdacc[x] != 0.0) atomicAdd(&a.wd[obase + win_out(a0 + x)], wdacc[x]);
+          __syncthreads();
         }
-        __syncthreads();
-
-        // ---- H (x) Q and the Kronecker term, then flush to the global numerator
-        if (tid == 0) n_fma += 4ull * (unsigned long long)(na * nbk);
-        for (int idx = tid; idx < na * nbk; idx += BLOCK) {
-          const int x = idx / nbk, y = idx - x * nbk;
-          T v = sm.H[0][x] * sm.Q[0][y] + sm.H[1][x] * sm.Q[1][y] + sm.H[2][x] * sm.Q[2][y] +
-                sm.H[3][x] * sm.Q[3][y];
-          if (a0 + x == b0 + y) v += sm.H[0][x];
-          v += sm.tile[idx];
-          if (v != (T)0) {
-            const int A = out_index(sm.lbins[a0 + x], NP, NT);
-            const int B = out_index(sm.lbins[b0 + y], NP, NT);
-            atomicAdd(&a.dnum[(obase + A) * nb + B], (double)v);
-          }
-        }
-        if (bb == 0)
-          for (int x = tid; x < na; x += BLOCK)
-            atomicAdd(&a.wd[obase + out_index(sm.lbins[a0 + x], NP, NT)], (double)sm.H[0][x]);
-        __syncthreads();
       }
+      r0 = r1;
     }
-    for (int x = tid; x < Tn; x += BLOCK) sm.lidx[sm.lbins[x]] = 0xFFFF;
-    __syncthreads();
   }
   if (a.counters) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       n_in += __shfl_xor(n_in, o, 64);
       n_fma += __shfl_xor(n_fma, o, 64);
+      n_lost += __shfl_xor(n_lost, o, 64);
     }
     if (lane == 0) {
       atomicAdd(&a.counters[0], n_in);
       atomicAdd(&a.counters[1], n_fma);
+      atomicAdd(&a.counters[2], n_lost);
     }
   }
 }
 
-struct Variant {
-  const char* name;
-};
-constexpr Variant kVariants[] = {{"b512-t128/88"}, {"b256-t64/48"}};
+// Window key of each kept pair from its exact r_perp range.  Every pixel pair
+// has r_perp in [(Dmin_f + Dmin_g) s, (Dmax_f + Dmax_g) s] (monotone rounding),
+// and every bin decision (FP64, or FP32 away from edges) agrees with the FP64
+// edge comparison, so the k_perp of every in-grid pixel pair is inside.
+__global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.n_pairs) return;
+  const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
+  const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
+  double s, c;
+  pair_sc(fi, gi, s, c);
+  const double rmin = __dmul_rn(__dadd_rn(fi.dmin, gi.dmin), s);
+  const double rmax = __dmul_rn(__dadd_rn(fi.dmax, gi.dmax), s);
+  const int NT = a.g.n_perp;
+  const double* et = a.edges_perp;
+  uint64_t key = ~0ull;
+  if (rmin < et[NT] && rmax >= et[0]) {
+    const int lo = rmin < et[0] ? 0 : bin_exact(rmin, et, NT, (int)((rmin - a.g.e0_perp) * a.g.inv_perp));
+    const int hi = rmax >= et[NT] ? NT - 1 : bin_exact(rmax, et, NT, (int)((rmax - a.g.e0_perp) * a.g.inv_perp));
+    if (lo >= 0 && hi >= lo)
+      key = ((uint64_t)fi.real << 40) | ((uint64_t)lo << 16) | (uint64_t)(hi - lo + 1);
+  }
+  keys[q] = key;
+  idx[q] = (int32_t)q;
+}
+
 constexpr int kNumVariants = 2;
+const char* const kNames[kNumVariants] = {"fp32:b512/fp64:b256", "b256"};
 
-template <typename T> constexpr int tb_big() { return sizeof(T) == 4 ? 128 : 88; }
-template <typename T> constexpr int tb_small() { return sizeof(T) == 4 ? 64 : 48; }
-
-template <typename T, int BLOCK, int TB>
+template <typename T, int BLOCK>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.g.zero_lo_par && a.g.zero_lo_perp)
-    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, TB, true>), dim3(blocks), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, true>), dim3(blocks), dim3(BLOCK), 0, st, a);
   else
-    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, TB, false>), dim3(blocks), dim3(BLOCK), 0, st, a);
+    hipLaunchKernelGGL((dmat_kernel<T, BLOCK, false>), dim3(blocks), dim3(BLOCK), 0, st, a);
   return hipGetLastError();
 }
 
-template <typename T, int BLOCK, int TB>
+template <typename T, int BLOCK>
 int occupancy() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_kernel<T, BLOCK, TB, true>, BLOCK, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_kernel<T, BLOCK, true>, BLOCK, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
-}
-
-template <typename T>
-hipError_t launch_t(int v, const DmatArgs& a, int blocks, hipStream_t st) {
-  if (v == 0) return launch_one<T, 512, tb_big<T>()>(a, blocks, st);
-  return launch_one<T, 256, tb_small<T>()>(a, blocks, st);
-}
-
-template <typename T>
-int occ_t(int v) {
-  if (v == 0) return occupancy<T, 512, tb_big<T>()>();
-  return occupancy<T, 256, tb_small<T>()>();
 }
 
 __global__ void finalize_dmat_kernel(double* d, const double* wd, int64_t n_rows, int nb) {
@@ -355,16 +379,23 @@ __global__ void finalize_dmat_kernel(double* d, const double* wd, int64_t n_rows
 }  // namespace
 
 int dmat_num_variants() { return kNumVariants; }
-const char* dmat_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : "?"; }
+const char* dmat_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kNames[v] : "?"; }
+
+hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st) {
+  if (a.n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(dmat_keys_kernel, dim3((unsigned)((a.n_pairs + 255) / 256)), dim3(256), 0, st, a, keys, idx);
+  return hipGetLastError();
+}
 
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
-  if (a.n_pairs == 0) return hipSuccess;
-  return precision == LYA_FP64 ? launch_t<double>(variant, a, blocks, st)
-                               : launch_t<float>(variant, a, blocks, st);
+  if (a.n_items == 0) return hipSuccess;
+  if (precision == LYA_FP64) return launch_one<double, 256>(a, blocks, st);
+  return variant == 0 ? launch_one<float, 512>(a, blocks, st) : launch_one<float, 256>(a, blocks, st);
 }
 
 int dmat_blocks_per_cu(int variant, int precision) {
-  return precision == LYA_FP64 ? occ_t<double>(variant) : occ_t<float>(variant);
+  if (precision == LYA_FP64) return occupancy<double, 256>();
+  return variant == 0 ? occupancy<float, 512>() : occupancy<float, 256>();
 }
 
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st) {

@@ -176,6 +176,19 @@ hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, void* tmp, si
   return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, st);
 }
 
+size_t sort_keys_bytes(int64_t n) {
+  size_t b = 0;
+  hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                     (int32_t*)nullptr, (int32_t*)nullptr, (int)n);
+  return b + 256;
+}
+
+hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in, int32_t* v_out,
+                            int64_t n, void* tmp, size_t bytes, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, keys_in, keys_out, v_in, v_out, (int)n, 0, 64, st);
+}
+
 hipError_t launch_count_items(const WorklistArgs& a, hipStream_t st) {
   if (a.n_forests == 0) return hipSuccess;
   hipLaunchKernelGGL(count_items_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);

@@ -228,6 +228,11 @@ struct DmatArgs {
   const int32_t* nbr;      // second forest (sorted position) of each kept pair
   const int32_t* pair_p;   // first forest (sorted position) of each kept pair
   int64_t n_pairs;
+  // pairs ordered by their r_perp window (realisation, first k_perp, span)
+  const uint64_t* wkeys;   // sorted window keys
+  const int32_t* worder;   // pair index of each sorted key
+  int64_t n_items;         // chunks of `chunk` consecutive sorted pairs
+  int32_t chunk;
   unsigned int* counter;
   const DRec32* drec32;
   const DRec64* drec64;
@@ -237,8 +242,14 @@ struct DmatArgs {
   GridDev g;
   double* dnum;    // [R][nb][nb] numerator of D
   double* wd;      // [R][nb] sum w_i w_j over the kept pairs
-  unsigned long long* counters;  // optional [2]: in-grid pixel pairs, outer-product FMAs
+  unsigned long long* counters;  // optional [3]: in-grid pixel pairs, outer-product FMAs, out-of-window pairs
 };
+// window key of every kept pair: (realisation << 40) | (first k_perp << 16) | span;
+// pairs with no possible in-grid pixel pair get ~0
+hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st);
+hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in, int32_t* v_out,
+                            int64_t n, void* tmp, size_t bytes, hipStream_t st);
+size_t sort_keys_bytes(int64_t n);
 int dmat_num_variants();
 const char* dmat_variant_name(int v);
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);

@@ -33,6 +33,7 @@ struct lya_context {
 namespace {
 
 constexpr double kPi = 3.141592653589793;
+constexpr int kDmatChunk = 1024;  // kept forest pairs per distortion work item
 
 lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) {
@@ -579,6 +580,26 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     a.pair_p = W.pair_p;
     a.n_pairs = W.n_pairs;
     a.counter = counter;
+    a.edges_perp = P.edges_perp;
+    a.g = gd;
+    // order the pairs by r_perp window so that pairs sharing a window share a tile
+    {
+      uint64_t *k_in, *k_out;
+      int32_t *v_in, *v_out;
+      LYA_TRY(wst(ctx, "dm_keys_in", (size_t)W.n_pairs, &k_in));
+      LYA_TRY(wst(ctx, "dm_keys", (size_t)W.n_pairs, &k_out));
+      LYA_TRY(wst(ctx, "dm_idx_in", (size_t)W.n_pairs, &v_in));
+      LYA_TRY(wst(ctx, "dm_order", (size_t)W.n_pairs, &v_out));
+      const size_t bytes = sort_keys_bytes(W.n_pairs);
+      void* tmp;
+      LYA_TRY(ws(ctx, "dm_sort_tmp", bytes, &tmp));
+      HIP_TRY(launch_dmat_keys(a, k_in, v_in, st));
+      HIP_TRY(launch_sort_keys(k_in, k_out, v_in, v_out, W.n_pairs, tmp, bytes, st));
+      a.wkeys = k_out;
+      a.worder = v_out;
+      a.chunk = kDmatChunk;
+      a.n_items = (W.n_pairs + kDmatChunk - 1) / kDmatChunk;
+    }
     a.drec32 = P.drec32;
     a.drec64 = P.drec64;
     a.edges_par = P.edges_par;
@@ -607,7 +628,8 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
         DmatArgs t = a;
         t.dnum = sd;
         t.wd = sw;
-        t.n_pairs = W.n_pairs < 16 * ctx->n_cu ? W.n_pairs : (W.n_pairs / 16 > 16 * ctx->n_cu ? W.n_pairs / 16 : 16 * ctx->n_cu);
+        // a spread-out sample: every 8th chunk would need a gather; take a prefix of items
+        t.n_items = a.n_items < 2 * ctx->n_cu ? a.n_items : (a.n_items / 8 > 2 * ctx->n_cu ? a.n_items / 8 : 2 * ctx->n_cu);
         float best = 1e30f;
         for (int v = 0; v < dmat_num_variants(); ++v) {
           const int blocks = dmat_blocks_per_cu(v, o->precision) * ctx->n_cu;
@@ -633,8 +655,8 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     ctx->stats.grid_blocks = blocks;
     unsigned long long* wc = nullptr;
     if (tm.on) {
-      LYA_TRY(wst(ctx, "dm_work_counters", 2, &wc));
-      HIP_TRY(launch_zero(wc, 2 * sizeof(unsigned long long), st));
+      LYA_TRY(wst(ctx, "dm_work_counters", 3, &wc));
+      HIP_TRY(launch_zero(wc, 3 * sizeof(unsigned long long), st));
     }
     a.counters = wc;
     HIP_TRY(launch_zero(counter, 4, st));
@@ -642,10 +664,11 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     HIP_TRY(launch_dmat(variant, o->precision, a, blocks, st));
     tm.at(4);
     if (wc) {
-      HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 64, wc, 16, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 64, wc, 24, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       ctx->stats.ingrid_pairs = ((int64_t*)((char*)ctx->pinned + 64))[0];
       ctx->stats.outer_fmas = ((int64_t*)((char*)ctx->pinned + 64))[1];
+      ctx->stats.lost_pairs = ((int64_t*)((char*)ctx->pinned + 64))[2];
     }
   } else {
     tm.at(1);

@@ -62,6 +62,7 @@ class lya_stats(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32), ("ms_precompute", ctypes.c_float),
         ("ms_worklist", ctypes.c_float), ("ms_main", ctypes.c_float), ("ms_finalize", ctypes.c_float),
         ("ingrid_pairs", ctypes.c_int64), ("outer_fmas", ctypes.c_int64),
+        ("lost_pairs", ctypes.c_int64),
     ]
 
 
