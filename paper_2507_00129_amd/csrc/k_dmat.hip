@@ -38,13 +38,16 @@ template <typename T> struct DRecOf;
 template <> struct DRecOf<float> { using type = DRec32; };
 template <> struct DRecOf<double> { using type = DRec64; };
 
+// Per-wave scratch.  R and G hold the two components (l = 0, 1) of a row
+// histogram interleaved, so one 2-element load fetches both.  Flags are whole
+// dwords: lanes flagging neighbouring bins must not share a dword.
 template <typename T>
 struct WaveBuf {
   T H[4][kTileW];
   T Q[4][kTileW];
-  T R[2][kTileW];
-  T G[2][kTileW];
-  uint8_t fA[kTileW], fB[kTileW], fH[kTileW], fQ[kTileW];
+  __attribute__((aligned(16))) T R[kTileW][2];
+  __attribute__((aligned(16))) T G[kTileW][2];
+  uint32_t fA[kTileW], fB[kTileW], fH[kTileW], fQ[kTileW];
   uint8_t lA[kTileW], lB[kTileW], lH[kTileW], lQ[kTileW];
 };
 
@@ -55,7 +58,7 @@ __device__ __forceinline__ void wave_sync() {
 
 // Compacts the flagged entries of fl[0..n) into list (ascending) and clears
 // the flags.  Returns the count (wave-uniform).
-__device__ __forceinline__ int wave_compact(uint8_t* fl, uint8_t* list, int n, int lane) {
+__device__ __forceinline__ int wave_compact(uint32_t* fl, uint8_t* list, int n, int lane) {
   int m = 0;
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int x0 = 0; x0 < n; x0 += 64) {
@@ -71,17 +74,23 @@ __device__ __forceinline__ int wave_compact(uint8_t* fl, uint8_t* list, int n, i
   return m;
 }
 
-// Calls f(x, y) for every x in la[0..ma), y in lb[0..mb), spread over the lanes.
+// Calls f(x, y) for every x in la[0..ma), y in lb[0..mb), spread over the
+// lanes: lane k starts at flat index k = u mb + v and advances by 64 with an
+// incremental (u, v) update instead of a division.
 template <typename F>
 __device__ __forceinline__ void wave_outer(const uint8_t* la, int ma, const uint8_t* lb, int mb, int lane,
                                            F&& f) {
-  const int tot = ma * mb;
-  const float inv = mb ? 1.0f / (float)mb : 0.f;
-  for (int idx = lane; idx < tot; idx += 64) {
-    int u = (int)((float)idx * inv);
-    if (u * mb > idx) --u;
-    else if ((u + 1) * mb <= idx) ++u;
-    f((int)la[u], (int)lb[idx - u * mb]);
+  if (ma == 0 || mb == 0) return;
+  const int du = 64 / mb, dv = 64 - du * mb;
+  int u = lane / mb, v = lane - (lane / mb) * mb;
+  for (; u < ma;) {
+    f((int)la[u], (int)lb[v]);
+    u += du;
+    v += dv;
+    if (v >= mb) {
+      v -= mb;
+      ++u;
+    }
   }
 }
 
@@ -107,7 +116,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
       W.H[m][x] = 0;
       W.Q[m][x] = 0;
     }
-    W.R[0][x] = W.R[1][x] = W.G[0][x] = W.G[1][x] = 0;
+    W.R[x][0] = W.R[x][1] = W.G[x][0] = W.G[x][1] = 0;
     W.fA[x] = W.fB[x] = W.fH[x] = W.fQ[x] = 0;
   }
   unsigned long long n_in = 0, n_fma = 0, n_lost = 0;  // statistics only
@@ -194,8 +203,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 const int x = w - a0, y = w - b0;
                 if ((unsigned)x < (unsigned)na) {
                   const T ww = ri.w * rj.w;
-                  atomicAdd(&W.R[0][x], rj.w);
-                  atomicAdd(&W.R[1][x], rj.w * rj.a);
+                  atomicAdd(&W.R[x][0], rj.w);
+                  atomicAdd(&W.R[x][1], rj.w * rj.a);
                   atomicAdd(&W.H[0][x], ww);
                   atomicAdd(&W.H[1][x], ww * rj.a);
                   atomicAdd(&W.H[2][x], ri.a * ww);
@@ -204,8 +213,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   W.fH[x] = 1;
                 }
                 if ((unsigned)y < (unsigned)nbk) {
-                  atomicAdd(&W.G[0][y], rj.u);
-                  atomicAdd(&W.G[1][y], rj.b);
+                  atomicAdd(&W.G[y][0], rj.u);
+                  atomicAdd(&W.G[y][1], rj.b);
                   atomicAdd(&W.Q[0][y], ri.u * rj.u);
                   atomicAdd(&W.Q[1][y], ri.u * rj.b);
                   atomicAdd(&W.Q[2][y], ri.b * rj.u);
@@ -220,12 +229,12 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
               wave_sync();
               const T wneg = -ri.w;
               wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
-                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[0][x] * W.G[0][y] + W.R[1][x] * W.G[1][y])));
+                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[x][0] * W.G[y][0] + W.R[x][1] * W.G[y][1])));
               });
               if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
               wave_sync();
-              for (int u = lane; u < mA; u += 64) W.R[0][W.lA[u]] = W.R[1][W.lA[u]] = 0;
-              for (int v = lane; v < mB; v += 64) W.G[0][W.lB[v]] = W.G[1][W.lB[v]] = 0;
+              for (int u = lane; u < mA; u += 64) W.R[W.lA[u]][0] = W.R[W.lA[u]][1] = 0;
+              for (int v = lane; v < mB; v += 64) W.G[W.lB[v]][0] = W.G[W.lB[v]][1] = 0;
               wave_sync();
             }
 
@@ -264,13 +273,13 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 if (w < 0) continue;
                 const int x = w - a0, y = w - b0;
                 if ((unsigned)x < (unsigned)na) {
-                  atomicAdd(&W.R[0][x], ri.w);
-                  atomicAdd(&W.R[1][x], ri.w * ri.a);
+                  atomicAdd(&W.R[x][0], ri.w);
+                  atomicAdd(&W.R[x][1], ri.w * ri.a);
                   W.fA[x] = 1;
                 }
                 if ((unsigned)y < (unsigned)nbk) {
-                  atomicAdd(&W.G[0][y], ri.u);
-                  atomicAdd(&W.G[1][y], ri.b);
+                  atomicAdd(&W.G[y][0], ri.u);
+                  atomicAdd(&W.G[y][1], ri.b);
                   W.fB[y] = 1;
                 }
               }
@@ -280,12 +289,12 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
               wave_sync();
               const T wneg = -rj.w;
               wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
-                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[0][x] * W.G[0][y] + W.R[1][x] * W.G[1][y])));
+                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[x][0] * W.G[y][0] + W.R[x][1] * W.G[y][1])));
               });
               if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
               wave_sync();
-              for (int u = lane; u < mA; u += 64) W.R[0][W.lA[u]] = W.R[1][W.lA[u]] = 0;
-              for (int v = lane; v < mB; v += 64) W.G[0][W.lB[v]] = W.G[1][W.lB[v]] = 0;
+              for (int u = lane; u < mA; u += 64) W.R[W.lA[u]][0] = W.R[W.lA[u]][1] = 0;
+              for (int v = lane; v < mB; v += 64) W.G[W.lB[v]][0] = W.G[W.lB[v]][1] = 0;
               wave_sync();
             }
           }
