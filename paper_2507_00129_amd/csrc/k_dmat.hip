@@ -16,15 +16,27 @@
 // (Dmin_f + Dmin_g) s and (Dmax_f + Dmax_g) s, a "window" of a few k_perp
 // rows, so D is banded in k_perp.  Kept pairs are sorted by (realisation,
 // first k_perp, span); a work item is a chunk of consecutive sorted pairs, and
-// all pairs of a chunk that share a window accumulate into one FP64 LDS tile
-// over that window (in blocks of kTileW x kTileW window bins when the window
-// is wider), which is added to the global FP64 numerator once per chunk.  The
-// waves of a workgroup process different forest pairs of the chunk at the same
-// time; within a wave the lanes sweep the pixels of one forest against one
-// pixel of the other, building the row histograms (and, in the first sweep,
-// H and Q) in wave-private LDS, and each row's outer product is added to the
-// tile.  Bins come from the shared binner, so a pixel pair falls in the same
-// bin here as in the xi kernel.
+// all pairs of a chunk that share a window accumulate into one tile of D over
+// that window (in blocks of kTileW x kTileW window bins when the window is
+// wider), added to the global FP64 numerator once per chunk.
+//
+// The row terms are a contraction over rows: for a group of rows r with
+// weights -w_r, tile[x][y] += sum_r sum_l (-w_r R^l_r[x]) G^l_r[y], a
+// [W x 2n] by [2n x W] product.  It runs on the matrix cores: one FP64
+// 16x16x4 MFMA step takes two rows for one 16 x 16 block of the tile.  A row
+// only touches a few runs of bins, so each row records which 16-bin blocks its
+// R and G reach, and a step is issued only for the blocks that one of its two
+// rows reaches on both sides; the work issued stays close to the sparse row
+// outer products.  The workgroup takes the pairs of a run one at a time: both
+// forests' pixels are staged in LDS, each wave sweeps RPW rows (lanes over the
+// other forest's pixels) and builds their histograms in LDS with atomics (in
+// the working precision); after a barrier every wave issues the steps of its
+// own tile blocks.  The pair histograms H, Q follow from the sweep-1 rows and
+// their rank-4 product is one more step.  The accumulators are FP64 in both
+// forms (the MFMA products of FP32 operands are exact in FP64), so the tile
+// needs no compensation; it is added to the global numerator once per run.
+// Bins come from the shared binner, so a pixel pair falls in the same bin here
+// as in the xi kernel.
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -32,99 +44,91 @@ namespace lya {
 
 namespace {
 
-constexpr int kTileW = 100;  // window bins per tile side: 100 x 100 FP64 = 80 KB
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
 
-template <typename T> struct DRecOf;
-template <> struct DRecOf<float> { using type = DRec32; };
-template <> struct DRecOf<double> { using type = DRec64; };
+// Lane layout of the FP64 16x16x4 MFMA: operand A[i][k] and B[k][j] come from
+// lane 16 k + i (resp. 16 k + j); accumulator register r of lane 16 g + j holds
+// row i = g + 4 r, column j.
+__device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 
-// Per-wave scratch.  R and G hold the two components (l = 0, 1) of a row
-// histogram interleaved, so one 2-element load fetches both.  Flags are whole
-// dwords: lanes flagging neighbouring bins must not share a dword.
-template <typename T>
-struct WaveBuf {
-  T H[4][kTileW];
-  T Q[4][kTileW];
-  __attribute__((aligned(16))) T R[kTileW][2];
-  __attribute__((aligned(16))) T G[kTileW][2];
-  uint32_t fA[kTileW], fB[kTileW], fH[kTileW], fQ[kTileW];
-  uint8_t lA[kTileW], lB[kTileW], lH[kTileW], lQ[kTileW];
+constexpr int kTileW = 160;           // window bins per tile side
+constexpr int kBlk = 16;              // MFMA block side
+constexpr int kNBlk = kTileW / kBlk;  // blocks per tile side (<= 32: one mask word)
+
+template <int N> struct IC { static constexpr int value = N; };
+
+template <typename T> struct DCfg;
+template <> struct DCfg<float> {
+  using Rec = DRec32;
+  static constexpr int RPW = 2;        // rows per wave per group
+  static constexpr int kStage = 1024;  // pixels per forest staged in LDS
+};
+template <> struct DCfg<double> {
+  using Rec = DRec64;
+  static constexpr int RPW = 1;
+  static constexpr int kStage = 512;
 };
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+template <typename T, int NW>
+struct DSmem {
+  static constexpr int NR = NW * DCfg<T>::RPW;  // rows per group
+  static constexpr int S = DCfg<T>::kStage;
+  T sd[2][S], sw[2][S], sa[2][S], su[2][S], sb[2][S];  // staged pixels (0: f, 1: g)
+  T rowR[NR][2][kTileW];    // R^0, R^1 of each row of the group
+  T rowG[NR][2][kTileW];    // G^0, G^1
+  T rw[NR];                 // -w of each row (0: no row)
+  T rowc[NR][4];            // w, w a, u, b of each sweep-1 row
+  uint32_t mx[NR], my[NR];  // 16-bin blocks reached by R (x) and G (y)
+  T H[4][kTileW];           // pair histograms, written after sweep 1
+  T Q[4][kTileW];
+  double wdacc[kTileW];
+  int32_t ox[kTileW], oy[kTileW];  // output bin index of each tile row / column
+  int64_t item;
+};
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= (uint32_t)__shfl_xor((int)v, o, 64);
+  return v;
 }
 
-// Compacts the flagged entries of fl[0..n) into list (ascending) and clears
-// the flags.  Returns the count (wave-uniform).
-__device__ __forceinline__ int wave_compact(uint32_t* fl, uint8_t* list, int n, int lane) {
-  int m = 0;
-  const uint64_t lt = (1ull << lane) - 1ull;
-  for (int x0 = 0; x0 < n; x0 += 64) {
-    const int x = x0 + lane;
-    const bool on = x < n && fl[x];
-    const uint64_t b = __ballot(on);
-    if (on) {
-      list[m + __popcll(b & lt)] = (uint8_t)x;
-      fl[x] = 0;
-    }
-    m += __popcll(b);
-  }
-  return m;
-}
-
-// Calls f(x, y) for every x in la[0..ma), y in lb[0..mb), spread over the
-// lanes: lane k starts at flat index k = u mb + v and advances by 64 with an
-// incremental (u, v) update instead of a division.
-template <typename F>
-__device__ __forceinline__ void wave_outer(const uint8_t* la, int ma, const uint8_t* lb, int mb, int lane,
-                                           F&& f) {
-  if (ma == 0 || mb == 0) return;
-  const int du = 64 / mb, dv = 64 - du * mb;
-  int u = lane / mb, v = lane - (lane / mb) * mb;
-  for (; u < ma;) {
-    f((int)la[u], (int)lb[v]);
-    u += du;
-    v += dv;
-    if (v >= mb) {
-      v -= mb;
-      ++u;
-    }
-  }
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 template <typename T, int BLOCK, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
-  using Rec = typename DRecOf<T>::type;
-  constexpr int NW = BLOCK / 64, TW = kTileW;
-  __shared__ double tile[TW * TW];
-  __shared__ double wdacc[TW];
-  __shared__ WaveBuf<T> wbuf[NW];
-  __shared__ int64_t s_item;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  using Cfg = DCfg<T>;
+  using Rec = typename Cfg::Rec;
+  constexpr int NW = BLOCK / 64, RPW = Cfg::RPW, NR = NW * RPW, S = Cfg::kStage, TW = kTileW;
+  constexpr int MB = (kNBlk * kNBlk + NW - 1) / NW;  // tile blocks per wave
+  constexpr bool kF32 = sizeof(T) == 4;
+  static_assert(NR % 2 == 0, "two rows per MFMA step");
+  __shared__ DSmem<T, NW> sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lk = lane >> 4, lm = lane & 15;  // MFMA operand coordinates: k, and row/column in the block
 
   BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
   const int NP = K.NP, NT = K.NT, nb = NP * NT;
-  const double dc2 = 2.0 * a.glob->dc;
   const Rec* __restrict__ recs;
-  if constexpr (sizeof(T) == 4) recs = a.drec32; else recs = a.drec64;
-  WaveBuf<T>& W = wbuf[wave];
-  for (int x = lane; x < TW; x += 64) {
-    for (int m = 0; m < 4; ++m) {
-      W.H[m][x] = 0;
-      W.Q[m][x] = 0;
-    }
-    W.R[x][0] = W.R[x][1] = W.G[x][0] = W.G[x][1] = 0;
-    W.fA[x] = W.fB[x] = W.fH[x] = W.fQ[x] = 0;
+  if constexpr (kF32) recs = a.drec32; else recs = a.drec64;
+
+  for (int e = tid; e < NR * 2 * TW; e += BLOCK) {
+    (&sm.rowR[0][0][0])[e] = 0;
+    (&sm.rowG[0][0][0])[e] = 0;
   }
-  unsigned long long n_in = 0, n_fma = 0, n_lost = 0;  // statistics only
+  unsigned long long n_in = 0, n_alg = 0, n_lost = 0;  // statistics only
+  mf_d4 cacc[MB];  // FP64 MFMA accumulators of the wave's blocks (block b = wave + NW m)
 
   for (;;) {
-    if (tid == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
+    __syncthreads();  // every thread has read the previous item
+    if (tid == 0) sm.item = (int64_t)atomicAdd(a.counter, 1u);
     __syncthreads();
-    const int64_t it = s_item;
+    const int64_t it = sm.item;
     if (it >= a.n_items) break;
     const int64_t k0 = it * a.chunk;
     const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
@@ -145,173 +149,277 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
       const int span = (int)(key & 0xFFFF);
       const int nwin = span * NP;
       const int base_L = kt0 * NP;  // window index w = L - kt0 NP
-      const int nblk = (nwin + TW - 1) / TW;
+      const int npass = (nwin + TW - 1) / TW;
       const int64_t obase = (int64_t)real * nb;
-      auto win_out = [&](int w) { return out_index(w + base_L, NP, NT); };
 
-      for (int ab = 0; ab < nblk; ++ab) {
+      for (int ab = 0; ab < npass; ++ab) {
         const int a0 = ab * TW, na = min(TW, nwin - a0);
-        for (int bb = 0; bb < nblk; ++bb) {
+        for (int bb = 0; bb < npass; ++bb) {
           const int b0 = bb * TW, nbk = min(TW, nwin - b0);
-          for (int e = tid; e < na * nbk; e += BLOCK) tile[e] = 0.0;
-          for (int x = tid; x < na; x += BLOCK) wdacc[x] = 0.0;
-          __syncthreads();
           const bool first_pass = ab == 0 && bb == 0;
+          const int nbx = (na + kBlk - 1) / kBlk, nby = (nbk + kBlk - 1) / kBlk;
+#pragma unroll
+          for (int m = 0; m < MB; ++m) cacc[m] = mf_d4{0.0, 0.0, 0.0, 0.0};
+          __syncthreads();  // the previous pass's flush has read the index tables
+          for (int x = tid; x < TW; x += BLOCK) {
+            sm.wdacc[x] = 0.0;
+            sm.ox[x] = x < na ? out_index(a0 + x + base_L, NP, NT) : -1;
+            sm.oy[x] = x < nbk ? out_index(b0 + x + base_L, NP, NT) : -1;
+          }
 
-          for (int64_t kk = r0 + wave; kk < r1; kk += NW) {
+          for (int64_t kk = r0; kk < r1; ++kk) {
             const int q = a.worder[kk];
-            const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
-            const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
+            int64_t pf, pg;
+            int nf, ng;
             double s64, c64;
-            pair_sc(fi, gi, s64, c64);
+            {
+              const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
+              const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
+              pair_sc(fi, gi, s64, c64);
+              pf = fi.pix0;
+              pg = gi.pix0;
+              nf = fi.npix;
+              ng = gi.npix;
+            }
             const T s = (T)s64, c = (T)c64;
-            const T bsep = sizeof(T) == 4 ? (T)(dc2 * s64) : (T)0;
-            const Rec* __restrict__ rf = recs + fi.pix0;
-            const Rec* __restrict__ rg = recs + gi.pix0;
-            const int nf = fi.npix, ng = gi.npix;
+            const T bsep = kF32 ? (T)(2.0 * a.glob->dc * s64) : (T)0;
 
-            // window index of pixel pair (ri in f, rj in g), or -1
-            auto wbin = [&](const Rec& ri, const Rec& rj) -> int {
-              T rp, rt;
-              separations(ri.d, rj.d, c, s, bsep, rp, rt);
-              if (!K.may_be_in(rp, rt)) return -1;
-              const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
-                if constexpr (sizeof(T) == 4) {
-                  separations64(ri.D, rj.D, c64, s64, rp64, rt64);
-                } else {
-                  rp64 = rp;
-                  rt64 = rt;
-                }
-              });
-              if (L < 0) return -1;
-              const int w = L - base_L;
-              if ((unsigned)w >= (unsigned)nwin) {
-                ++n_lost;
-                return -1;
+            // stage both forests' pixels (the first S of each)
+            __syncthreads();
+            {
+              const int sf = min(nf, S), sg = min(ng, S);
+              for (int e = tid; e < sf + sg; e += BLOCK) {
+                const bool gside = e >= sf;
+                const int k = gside ? e - sf : e;
+                const Rec r = recs[(gside ? pg : pf) + k];
+                const int sd = gside ? 1 : 0;
+                sm.sd[sd][k] = r.d;
+                sm.sw[sd][k] = r.w;
+                sm.sa[sd][k] = r.a;
+                sm.su[sd][k] = r.u;
+                sm.sb[sd][k] = r.b;
               }
-              return w;
+            }
+            __syncthreads();
+
+            // sweep-1 rows give H^{hm}[hx], Q^{hm}[hx] for entries e = tid + BLOCK v
+            constexpr int NHE = (4 * TW + BLOCK - 1) / BLOCK;
+            T hreg[NHE], qreg[NHE];
+#pragma unroll
+            for (int v = 0; v < NHE; ++v) hreg[v] = qreg[v] = 0;
+
+            // one sweep: rows of side RS, lanes over the pixels of the other side
+            auto sweep = [&](auto rs_tag) {
+              constexpr int RS = decltype(rs_tag)::value, OS = 1 - RS;
+              const int nr = RS ? ng : nf, no = RS ? nf : ng;
+              const int64_t prow0 = RS ? pg : pf, poth0 = RS ? pf : pg;
+              for (int g0 = 0; g0 < nr; g0 += NR) {
+#pragma unroll
+                for (int qq = 0; qq < RPW; ++qq) {
+                  const int slot = wave * RPW + qq, row = g0 + slot;
+                  uint32_t bx = 0, by = 0;
+                  if (row < nr) {
+                    T rd, rwt, raa, ruu, rbb;
+                    if (row < S) {
+                      rd = sm.sd[RS][row];
+                      rwt = sm.sw[RS][row];
+                      raa = sm.sa[RS][row];
+                      ruu = sm.su[RS][row];
+                      rbb = sm.sb[RS][row];
+                    } else {
+                      const Rec r = recs[prow0 + row];
+                      rd = r.d; rwt = r.w; raa = r.a; ruu = r.u; rbb = r.b;
+                    }
+                    for (int j = lane; j < no; j += 64) {
+                      T od, ow, oa, ou, ob;
+                      if (j < S) {
+                        od = sm.sd[OS][j];
+                        ow = sm.sw[OS][j];
+                        oa = sm.sa[OS][j];
+                        ou = sm.su[OS][j];
+                        ob = sm.sb[OS][j];
+                      } else {
+                        const Rec r = recs[poth0 + j];
+                        od = r.d; ow = r.w; oa = r.a; ou = r.u; ob = r.b;
+                      }
+                      T rp, rt;
+                      separations(rd, od, c, s, bsep, rp, rt);
+                      if (!K.may_be_in(rp, rt)) continue;
+                      const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
+                        if constexpr (kF32) {
+                          separations64(recs[prow0 + row].D, recs[poth0 + j].D, c64, s64, rp64, rt64);
+                        } else {
+                          rp64 = rp;
+                          rt64 = rt;
+                        }
+                      });
+                      if (L < 0) continue;
+                      const int w = L - base_L;
+                      if ((unsigned)w >= (unsigned)nwin) {
+                        ++n_lost;
+                        continue;
+                      }
+                      if (RS == 0 && first_pass) ++n_in;
+                      const int x = w - a0, y = w - b0;
+                      if ((unsigned)x < (unsigned)na) {
+                        atomicAdd(&sm.rowR[slot][0][x], ow);
+                        atomicAdd(&sm.rowR[slot][1][x], ow * oa);
+                        bx |= 1u << (x >> 4);
+                      }
+                      if ((unsigned)y < (unsigned)nbk) {
+                        atomicAdd(&sm.rowG[slot][0][y], ou);
+                        atomicAdd(&sm.rowG[slot][1][y], ob);
+                        by |= 1u << (y >> 4);
+                      }
+                    }
+                    if (lane == 0) {
+                      sm.rw[slot] = -rwt;
+                      sm.rowc[slot][0] = rwt;
+                      sm.rowc[slot][1] = rwt * raa;
+                      sm.rowc[slot][2] = ruu;
+                      sm.rowc[slot][3] = rbb;
+                    }
+                  } else if (lane == 0) {
+                    sm.rw[slot] = 0;
+                    sm.rowc[slot][0] = sm.rowc[slot][1] = sm.rowc[slot][2] = sm.rowc[slot][3] = 0;
+                  }
+                  bx = wave_or(bx);
+                  by = wave_or(by);
+                  if (lane == 0) {
+                    sm.mx[slot] = bx;
+                    sm.my[slot] = by;
+                  }
+                }
+                __syncthreads();
+
+                // MFMA steps on the wave's blocks, rows (2 st, 2 st + 1) per step
+#pragma unroll 1
+                for (int st = 0; st < NR / 2; ++st) {
+                  const uint32_t mx0 = sm.mx[2 * st], mx1 = sm.mx[2 * st + 1];
+                  const uint32_t my0 = sm.my[2 * st], my1 = sm.my[2 * st + 1];
+                  if ((mx0 == 0u || my0 == 0u) && (mx1 == 0u || my1 == 0u)) continue;
+                  const int slot = 2 * st + (lk >> 1), comp = lk & 1;
+                  const double wr = (double)sm.rw[slot];
+                  // block coordinates are recomputed every step (an opaque copy
+                  // of the wave index keeps them from being hoisted into registers)
+                  int wv = wave;
+                  asm volatile("" : "+s"(wv));
+#pragma unroll
+                  for (int m = 0; m < MB; ++m) {
+                    const int b = wv + NW * m;
+                    const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
+                    if (ibx < nbx && iby < nby &&
+                        ((((mx0 >> ibx) & (my0 >> iby)) | ((mx1 >> ibx) & (my1 >> iby))) & 1u)) {
+                      const double av = wr * (double)sm.rowR[slot][comp][ibx * kBlk + lm];
+                      const double bv = (double)sm.rowG[slot][comp][iby * kBlk + lm];
+                      cacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cacc[m], 0, 0, 0);
+                    }
+                  }
+                }
+                if (RS == 0) {
+#pragma unroll
+                  for (int v = 0; v < NHE; ++v) {
+                    const int e = tid + BLOCK * v;
+                    if (e < 4 * TW) {
+                      const int hm = e / TW, hx = e - hm * TW, l = hm & 1, k = hm >> 1;
+#pragma unroll 1
+                      for (int r = 0; r < NR; ++r) {
+                        hreg[v] = fma(sm.rowc[r][k], sm.rowR[r][l][hx], hreg[v]);
+                        qreg[v] = fma(sm.rowc[r][2 + k], sm.rowG[r][l][hx], qreg[v]);
+                      }
+                    }
+                  }
+                }
+                __syncthreads();
+                // clear the wave's rows; count the sparse outer-product work (statistics)
+#pragma unroll
+                for (int qq = 0; qq < RPW; ++qq) {
+                  const int slot = wave * RPW + qq;
+                  int cx = 0, cy = 0;
+                  for (int x = lane; x < TW; x += 64) {
+                    if (a.counters) {
+                      cx += (sm.rowR[slot][0][x] != (T)0) | (sm.rowR[slot][1][x] != (T)0);
+                      cy += (sm.rowG[slot][0][x] != (T)0) | (sm.rowG[slot][1][x] != (T)0);
+                    }
+                    sm.rowR[slot][0][x] = sm.rowR[slot][1][x] = 0;
+                    sm.rowG[slot][0][x] = sm.rowG[slot][1][x] = 0;
+                  }
+                  if (a.counters) {
+                    cx = wave_isum(cx);
+                    cy = wave_isum(cy);
+                    if (lane == 0) n_alg += 2ull * (unsigned long long)cx * (unsigned long long)cy;
+                  }
+                }
+              }
             };
 
-            // ---- sweep 1: rows i of f; R, G per row and the pair histograms H, Q
-            for (int i = 0; i < nf; ++i) {
-              const Rec ri = rf[i];
-              for (int j = lane; j < ng; j += 64) {
-                const Rec rj = rg[j];
-                const int w = wbin(ri, rj);
-                if (w < 0) continue;
-                if (first_pass) ++n_in;
-                const int x = w - a0, y = w - b0;
-                if ((unsigned)x < (unsigned)na) {
-                  const T ww = ri.w * rj.w;
-                  atomicAdd(&W.R[x][0], rj.w);
-                  atomicAdd(&W.R[x][1], rj.w * rj.a);
-                  atomicAdd(&W.H[0][x], ww);
-                  atomicAdd(&W.H[1][x], ww * rj.a);
-                  atomicAdd(&W.H[2][x], ri.a * ww);
-                  atomicAdd(&W.H[3][x], ri.a * ww * rj.a);
-                  W.fA[x] = 1;
-                  W.fH[x] = 1;
-                }
-                if ((unsigned)y < (unsigned)nbk) {
-                  atomicAdd(&W.G[y][0], rj.u);
-                  atomicAdd(&W.G[y][1], rj.b);
-                  atomicAdd(&W.Q[0][y], ri.u * rj.u);
-                  atomicAdd(&W.Q[1][y], ri.u * rj.b);
-                  atomicAdd(&W.Q[2][y], ri.b * rj.u);
-                  atomicAdd(&W.Q[3][y], ri.b * rj.b);
-                  W.fB[y] = 1;
-                  W.fQ[y] = 1;
+            // ---- sweep 1: rows i of f
+            sweep(IC<0>{});
+#pragma unroll
+            for (int v = 0; v < NHE; ++v) {
+              const int e = tid + BLOCK * v;
+              if (e < 4 * TW) {
+                (&sm.H[0][0])[e] = hreg[v];
+                (&sm.Q[0][0])[e] = qreg[v];
+              }
+            }
+            __syncthreads();
+            // ---- H (x) Q: one more step; the Kronecker term on the diagonal; w_A
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+              const int b = wave + NW * m;
+              const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
+              if (ibx < nbx && iby < nby) {
+                const double av = (double)sm.H[lk][ibx * kBlk + lm];
+                const double bv = (double)sm.Q[lk][iby * kBlk + lm];
+                cacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cacc[m], 0, 0, 0);
+                if (a0 == b0 && ibx == iby) {
+#pragma unroll
+                  for (int r = 0; r < 4; ++r)
+                    if (mfma_row(lk, r) == lm) cacc[m][r] += (double)sm.H[0][ibx * kBlk + lm];
                 }
               }
-              wave_sync();
-              const int mA = wave_compact(W.fA, W.lA, na, lane);
-              const int mB = wave_compact(W.fB, W.lB, nbk, lane);
-              wave_sync();
-              const T wneg = -ri.w;
-              wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
-                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[x][0] * W.G[y][0] + W.R[x][1] * W.G[y][1])));
-              });
-              if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
-              wave_sync();
-              for (int u = lane; u < mA; u += 64) W.R[W.lA[u]][0] = W.R[W.lA[u]][1] = 0;
-              for (int v = lane; v < mB; v += 64) W.G[W.lB[v]][0] = W.G[W.lB[v]][1] = 0;
-              wave_sync();
             }
+            if (a.counters && wave == 0) {
+              int hx = 0, qy = 0;
+              for (int x = lane; x < TW; x += 64) {
+                hx += x < na && sm.H[0][x] != (T)0;
+                qy += x < nbk && ((sm.Q[0][x] != (T)0) | (sm.Q[3][x] != (T)0));
+              }
+              hx = wave_isum(hx);
+              qy = wave_isum(qy);
+              if (lane == 0) n_alg += 4ull * (unsigned long long)hx * (unsigned long long)qy;
+            }
+            if (bb == 0)
+              for (int x = tid; x < na; x += BLOCK) sm.wdacc[x] += (double)sm.H[0][x];
 
-            // ---- H (x) Q and the Kronecker term of this pair
-            {
-              const int mH = wave_compact(W.fH, W.lH, na, lane);
-              const int mQ = wave_compact(W.fQ, W.lQ, nbk, lane);
-              wave_sync();
-              wave_outer(W.lH, mH, W.lQ, mQ, lane, [&](int x, int y) {
-                double v = (double)(W.H[0][x] * W.Q[0][y] + W.H[1][x] * W.Q[1][y] +
-                                    W.H[2][x] * W.Q[2][y] + W.H[3][x] * W.Q[3][y]);
-                if (a0 + x == b0 + y) v += (double)W.H[0][x];
-                atomicAdd(&tile[x * nbk + y], v);
-              });
-              if (bb == 0)
-                for (int u = lane; u < mH; u += 64) atomicAdd(&wdacc[W.lH[u]], (double)W.H[0][W.lH[u]]);
-              if (lane == 0) n_fma += 4ull * (unsigned long long)(mH * mQ);
-              wave_sync();
-              for (int u = lane; u < mH; u += 64) {
-                const int x = W.lH[u];
-                W.H[0][x] = W.H[1][x] = W.H[2][x] = W.H[3][x] = 0;
-              }
-              for (int v = lane; v < mQ; v += 64) {
-                const int y = W.lQ[v];
-                W.Q[0][y] = W.Q[1][y] = W.Q[2][y] = W.Q[3][y] = 0;
-              }
-              wave_sync();
-            }
-
-            // ---- sweep 2: rows j of g; C, F per row (roles of f and g swapped)
-            for (int j = 0; j < ng; ++j) {
-              const Rec rj = rg[j];
-              for (int i = lane; i < nf; i += 64) {
-                const Rec ri = rf[i];
-                const int w = wbin(ri, rj);
-                if (w < 0) continue;
-                const int x = w - a0, y = w - b0;
-                if ((unsigned)x < (unsigned)na) {
-                  atomicAdd(&W.R[x][0], ri.w);
-                  atomicAdd(&W.R[x][1], ri.w * ri.a);
-                  W.fA[x] = 1;
-                }
-                if ((unsigned)y < (unsigned)nbk) {
-                  atomicAdd(&W.G[y][0], ri.u);
-                  atomicAdd(&W.G[y][1], ri.b);
-                  W.fB[y] = 1;
-                }
-              }
-              wave_sync();
-              const int mA = wave_compact(W.fA, W.lA, na, lane);
-              const int mB = wave_compact(W.fB, W.lB, nbk, lane);
-              wave_sync();
-              const T wneg = -rj.w;
-              wave_outer(W.lA, mA, W.lB, mB, lane, [&](int x, int y) {
-                atomicAdd(&tile[x * nbk + y], (double)(wneg * (W.R[x][0] * W.G[y][0] + W.R[x][1] * W.G[y][1])));
-              });
-              if (lane == 0) n_fma += 2ull * (unsigned long long)(mA * mB);
-              wave_sync();
-              for (int u = lane; u < mA; u += 64) W.R[W.lA[u]][0] = W.R[W.lA[u]][1] = 0;
-              for (int v = lane; v < mB; v += 64) W.G[W.lB[v]][0] = W.G[W.lB[v]][1] = 0;
-              wave_sync();
-            }
+            // ---- sweep 2: rows j of g
+            sweep(IC<1>{});
           }
           __syncthreads();
 
-          // ---- add the tile block to the global numerator (and w_A)
-          for (int e = tid; e < na * nbk; e += BLOCK) {
-            const double v = tile[e];
-            if (v != 0.0) {
-              const int x = e / nbk, y = e - x * nbk;
-              atomicAdd(&a.dnum[(obase + win_out(a0 + x)) * nb + win_out(b0 + y)], v);
+          // ---- add the wave's blocks to the global numerator (and w_A)
+          {
+            int wv = wave;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) {
+              asm volatile("" : "+s"(wv));
+              const int b = wv + NW * m;
+              const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
+              if (ibx < nbx && iby < nby) {
+                const int oy = sm.oy[iby * kBlk + lm];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const int ox = sm.ox[ibx * kBlk + mfma_row(lk, r)];
+                  const double v = cacc[m][r];
+                  if (ox >= 0 && oy >= 0 && v != 0.0) atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
+                }
+              }
             }
           }
           if (bb == 0)
             for (int x = tid; x < na; x += BLOCK)
-              if (wdacc[x] != 0.0) atomicAdd(&a.wd[obase + win_out(a0 + x)], wdacc[x]);
-          __syncthreads();
+              if (sm.wdacc[x] != 0.0) atomicAdd(&a.wd[obase + sm.ox[x]], sm.wdacc[x]);
         }
       }
       r0 = r1;
@@ -321,12 +429,11 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       n_in += __shfl_xor(n_in, o, 64);
-      n_fma += __shfl_xor(n_fma, o, 64);
       n_lost += __shfl_xor(n_lost, o, 64);
     }
     if (lane == 0) {
       atomicAdd(&a.counters[0], n_in);
-      atomicAdd(&a.counters[1], n_fma);
+      atomicAdd(&a.counters[1], n_alg);
       atomicAdd(&a.counters[2], n_lost);
     }
   }
@@ -358,8 +465,8 @@ __global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
   idx[q] = (int32_t)q;
 }
 
-constexpr int kNumVariants = 2;
-const char* const kNames[kNumVariants] = {"fp32:b512/fp64:b256", "b256"};
+constexpr int kNumVariants = 1;
+const char* const kNames[kNumVariants] = {"b512-mfma64"};
 
 template <typename T, int BLOCK>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
@@ -398,13 +505,14 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  if (precision == LYA_FP64) return launch_one<double, 256>(a, blocks, st);
-  return variant == 0 ? launch_one<float, 512>(a, blocks, st) : launch_one<float, 256>(a, blocks, st);
+  (void)variant;
+  if (precision == LYA_FP64) return launch_one<double, 512>(a, blocks, st);
+  return launch_one<float, 512>(a, blocks, st);
 }
 
 int dmat_blocks_per_cu(int variant, int precision) {
-  if (precision == LYA_FP64) return occupancy<double, 256>();
-  return variant == 0 ? occupancy<float, 512>() : occupancy<float, 256>();
+  (void)variant;
+  return precision == LYA_FP64 ? occupancy<double, 512>() : occupancy<float, 512>();
 }
 
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st) {

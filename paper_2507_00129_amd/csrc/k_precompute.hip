@@ -122,11 +122,18 @@ __global__ __launch_bounds__(256) void forest_stats_kernel(PrecomputeArgs a, lya
 }
 
 // Re-centring distance and FP32 edge-guard widths (single thread).
-// Error bound of the FP32 separations, with u = 2^-24 and M = max |D - dc|:
-//   |r_par32 - r_par|   <= u (2 M + 3 r_par)       (+ 2 u r for the bin scaling)
-//   |r_perp32 - r_perp| <= u (8 M s_max + 2 r_perp) (+ 2 u r for the bin scaling)
-// s_max = e_perp_max / (2 Dmin) bounds s for any pair near or inside the grid.
-// The guard half-widths are twice these bounds, in bin units.
+// u = 2^-24, M = max |D - dc|, N = number of bins on the axis, and
+// s_max = e_perp_max / (2 Dmin), which bounds s for any pair near or inside
+// the grid.  Two FP32 forms are in use:
+//  r-space form, r_par = |d_i - d_j| c and r_perp = (d_i + d_j) s + fl(2 dc s),
+//  then x = (r - e0) / dr:
+//   |x_par32 - x_par|   <= u (2 M + 5 e_par_max + |e0|) / dr
+//   |x_perp32 - x_perp| <= u (8 M s_max + 4 e_perp_max + |e0|) / dr
+//  x-space form, x_par = |d_i - d_j| fl(c / dr) - fl(e0 / dr) and
+//  x_perp = d_i fl(s / dr) + fl(((D_j + dc) s - e0) / dr) (one FMA each):
+//   |x_par32 - x_par|   <= u ((2 M + 3 |e0|) / dr + 3 (N + 2))
+//   |x_perp32 - x_perp| <= u (((3 M + 2 |dc|) s_max + |e0|) / dr + N + 2)
+// The guard half-widths are twice the larger bound, in bin units.
 __global__ void globals_kernel(PrecomputeArgs a) {
   Globals* g = a.glob;
   const double dmin = __longlong_as_double((long long)g->dmin_bits);
@@ -137,12 +144,16 @@ __global__ void globals_kernel(PrecomputeArgs a) {
   const double m = fmax(fabs(dmax - dc), fabs(dc - dmin));
   g->dc = dc;
   g->m = isfinite(m) ? m : 0.0;
+  const double M = g->m;
   const double u = 5.9604644775390625e-08;  // 2^-24
   const double smax = (dmin > 0.0 && isfinite(dmin)) ? fmin(1.0, a.eperp_max / (2.0 * dmin)) : 1.0;
-  const double tp = 2.0 * u * (2.0 * g->m + 5.0 * a.epar_max + fabs(a.e0_par)) * a.inv_par;
-  const double tt = 2.0 * u * (8.0 * g->m * smax + 4.0 * a.eperp_max + fabs(a.e0_perp)) * a.inv_perp;
-  g->tau_par = (float)tp;
-  g->tau_perp = (float)tt;
+  const double np = (a.epar_max - a.e0_par) * a.inv_par, nt = (a.eperp_max - a.e0_perp) * a.inv_perp;
+  const double tp_r = u * (2.0 * M + 5.0 * a.epar_max + fabs(a.e0_par)) * a.inv_par;
+  const double tt_r = u * (8.0 * M * smax + 4.0 * a.eperp_max + fabs(a.e0_perp)) * a.inv_perp;
+  const double tp_x = u * ((2.0 * M + 3.0 * fabs(a.e0_par)) * a.inv_par + 3.0 * (np + 2.0));
+  const double tt_x = u * (((3.0 * M + 2.0 * fabs(dc)) * smax + fabs(a.e0_perp)) * a.inv_perp + nt + 2.0);
+  g->tau_par = (float)(2.0 * fmax(tp_r, tp_x));
+  g->tau_perp = (float)(2.0 * fmax(tt_r, tt_x));
 }
 
 // One wave per forest: pack pixel records.

@@ -35,7 +35,6 @@ constexpr unsigned kRunMax = 32;
 struct NbTable {
   int64_t pix0[kChunkMax];
   int32_t pref[kChunkMax + 1];
-  float s32[kChunkMax], c32[kChunkMax], b32[kChunkMax];
   double s64[kChunkMax], c64[kChunkMax];
 };
 
@@ -129,7 +128,10 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
 
   BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
-  const double dc2 = 2.0 * a.glob->dc;
+  // x-space constants: x_par = |d_i - d_j| cp + mep, x_perp = d_i st + bt_j
+  const double dcx = sizeof(T) == 4 ? a.glob->dc : 0.0;  // FP32 distances are re-centred
+  const double invp = a.g.inv_par, invt = a.g.inv_perp, e0t = a.g.e0_perp;
+  const T mep = (T)(-a.g.e0_par * a.g.inv_par);
 
   int cur_real = -1;
   double pending = 0.0;  // upper bound on pairs added to any bin since the last flush
@@ -156,9 +158,6 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         tb.pix0[lane] = gi.pix0;
         tb.s64[lane] = s;
         tb.c64[lane] = c;
-        tb.s32[lane] = (float)s;
-        tb.c32[lane] = (float)c;
-        tb.b32[lane] = (float)(dc2 * s);
         n = gi.npix;
       }
       int incl = n;
@@ -197,7 +196,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         }
         k = lo;
       }
-      T dj, wdj, wj, sj, cj, bj;
+      T dj, wdj, wj, cp, st, bt;
       double Dj64 = 0.0, s64 = 0.0, c64 = 1.0;
       if (q < total) {
         const int64_t j = tb.pix0[k] + (q - tb.pref[k]);
@@ -205,26 +204,20 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         dj = rj.d;
         wdj = rj.wd;
         wj = rj.w;
-        if constexpr (sizeof(T) == 4) {
-          sj = tb.s32[k];
-          cj = tb.c32[k];
-          bj = tb.b32[k];
-          Dj64 = a.dist[j];
-          s64 = tb.s64[k];
-          c64 = tb.c64[k];
-        } else {
-          sj = tb.s64[k];
-          cj = tb.c64[k];
-          bj = 0;
-        }
+        s64 = tb.s64[k];
+        c64 = tb.c64[k];
+        if constexpr (sizeof(T) == 4) Dj64 = a.dist[j]; else Dj64 = rj.d;
+        cp = (T)(c64 * invp);
+        st = (T)(s64 * invt);
+        bt = (T)(((Dj64 + dcx) * s64 - e0t) * invt);
       } else {
         // out-of-range lane: a far-away pixel, never in the grid
         dj = (T)1e30;
         wdj = 0;
         wj = 0;
-        sj = 0;
-        cj = 1;
-        bj = 0;
+        cp = 1;
+        st = 0;
+        bt = (T)1e30;
       }
 
       int curA = -1;
@@ -232,22 +225,19 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
       unsigned cnt = 0;
 
       auto pair = [&](const Rec& ri, int i) {
-        T rp, rt;
-        separations(ri.d, dj, cj, sj, bj, rp, rt);
-        int A = -1;
-        if (K.may_be_in(rp, rt)) {
-          A = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
-            if constexpr (sizeof(T) == 4) {
-              separations64(load_uniform(a.dist + fi.pix0 + i), Dj64, c64, s64, rp64, rt64);
-            } else {
-              rp64 = rp;
-              rt64 = rt;
-            }
-          });
-        }
+        const T ad = fabs(ri.d - dj);
+        T xp;
+        if constexpr (ZLO) xp = ad * cp; else xp = fma(ad, cp, mep);
+        const T xt = fma(ri.d, st, bt);
+        const int A = K.bin_x(xp, xt, [&](double& rp64, double& rt64) {
+          double Di64;
+          if constexpr (sizeof(T) == 4) Di64 = load_uniform(a.dist + fi.pix0 + i); else Di64 = ri.d;
+          separations64(Di64, Dj64, c64, s64, rp64, rt64);
+        });
         if constexpr (RLE) {
           // a run ends when the bin changes or after kRunMax pairs, which keeps
-          // the FP32 rounding of a run sum below kRunMax units in the last place
+          // the FP32 rounding of a run sum below kRunMax units in the last place;
+          // out-of-grid pairs form runs with A = -1 that are never added
           if (A != curA || cnt == kRunMax) {
             if (curA >= 0) {
               atomicAdd(&hN[curA], (double)accN);
@@ -259,11 +249,9 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
             accW = 0;
             cnt = 0;
           }
-          if (A >= 0) {
-            accN += ri.wd * wdj;
-            accW += ri.w * wj;
-            ++cnt;
-          }
+          accN = fma(ri.wd, wdj, accN);
+          accW = fma(ri.w, wj, accW);
+          ++cnt;
         } else {
           if (A >= 0) {
             atomicAdd(&hN[A], (double)(ri.wd * wdj));

@@ -76,26 +76,36 @@ struct BinK {
   // bin() for a pair that passed may_be_in().
   template <typename Exact>
   __device__ __forceinline__ int bin_near(T rp, T rt, Exact&& exact) const {
-    T xp, xt;
-    if constexpr (ZLO) {
-      xp = rp * invp;
-      xt = rt * invt;
-    } else {
-      xp = (rp - e0p) * invp;
-      xt = (rt - e0t) * invt;
-    }
+    if constexpr (ZLO) return bin_x(rp * invp, rt * invt, exact);
+    else return bin_x((rp - e0p) * invp, (rt - e0t) * invt, exact);
+  }
+
+  // Bin of a pair from its coordinates in bin units, x = (r - e0) / dr, each
+  // within tau of the exact FP64 value.  A pair within tau of an edge is binned
+  // from exact()'s FP64 separations against the edge arrays; a zero lower edge
+  // needs no guard (separations are never negative).  Away from the edges,
+  // x < N + tau already implies x < N - tau, so no second range test is needed.
+  template <typename Exact>
+  __device__ __forceinline__ int bin_x(T xp, T xt, Exact&& exact) const {
     int A = -1;
     if ((xp < np_hi) & (xt < nt_hi) & (ZLO || ((xp > lo_p) & (xt > lo_t)))) {
       const T rxp = rint(xp), rxt = rint(xt);
-      const bool gp = (fabs(xp - rxp) < taup) & !(zlp & (rxp == (T)0));
-      const bool gt = (fabs(xt - rxt) < taut) & !(zlt & (rxt == (T)0));
+      bool gp = fabs(xp - rxp) < taup;
+      bool gt = fabs(xt - rxt) < taut;
+      if constexpr (ZLO) {
+        gp &= rxp != (T)0;
+        gt &= rxt != (T)0;
+      } else {
+        gp &= !(zlp & (rxp == (T)0));
+        gt &= !(zlt & (rxt == (T)0));
+      }
       if (gp | gt) {
         double rp64, rt64;
         exact(rp64, rt64);
         const int kp = bin_exact(rp64, ep, NP, (int)floor((double)xp));
         const int kt = bin_exact(rt64, et, NT, (int)floor((double)xt));
         A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
-      } else if ((xp < (T)NP) & (xt < (T)NT) & (ZLO || ((xp >= (T)0) & (xt >= (T)0)))) {
+      } else {
         A = (int)xt * NP + (int)xp;
       }
     }

@@ -619,7 +619,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
       auto found = ctx->tuned.find(key);
       if (found != ctx->tuned.end()) {
         variant = found->second;
-      } else if (o->autotune && W.n_pairs > 0) {
+      } else if (o->autotune && W.n_pairs > 0 && dmat_num_variants() > 1) {
         // time each variant on a prefix of the pair list into scratch outputs
         double* sd;
         double* sw;
