@@ -24,19 +24,24 @@
 // weights -w_r, tile[x][y] += sum_r sum_l (-w_r R^l_r[x]) G^l_r[y], a
 // [W x 2n] by [2n x W] product.  It runs on the matrix cores: one FP64
 // 16x16x4 MFMA step takes two rows for one 16 x 16 block of the tile.  A row
-// only touches a few runs of bins, so each row records which 16-bin blocks its
-// R and G reach, and a step is issued only for the blocks that one of its two
-// rows reaches on both sides; the work issued stays close to the sparse row
-// outer products.  The workgroup takes the pairs of a run one at a time: both
-// forests' pixels are staged in LDS, each wave sweeps RPW rows (lanes over the
-// other forest's pixels) and builds their histograms in LDS with atomics (in
+// only touches a few runs of bins, so each row records which blocks its R and G
+// reach (one ballot gives every wave's block bits), and a step is issued only
+// for the blocks that one of its two rows reaches on both sides; the work issued
+// stays close to the sparse row outer products.  The tile is 10 x 10 blocks;
+// wave w = (wx, wy) = (w & 1, w >> 1) owns block rows wx + 2i (i < 5) and
+// block columns wy + 4k (k < 3), so its operand addresses are one per-wave base
+// plus compile-time offsets.
+//
+// The workgroup takes the pairs of a run one at a time.  In each sweep the
+// pixels the lanes run over are staged in LDS (in chunks for long forests),
+// each wave sweeps RPW rows and builds their histograms in LDS with atomics (in
 // the working precision); after a barrier every wave issues the steps of its
-// own tile blocks.  The pair histograms H, Q follow from the sweep-1 rows and
-// their rank-4 product is one more step.  The accumulators are FP64 in both
-// forms (the MFMA products of FP32 operands are exact in FP64), so the tile
-// needs no compensation; it is added to the global numerator once per run.
-// Bins come from the shared binner, so a pixel pair falls in the same bin here
-// as in the xi kernel.
+// own blocks.
+// The pair histograms H, Q follow from the sweep-1 rows and their rank-4 product
+// is one more step.  The accumulators are FP64 in both forms (the products of
+// FP32 operands are exact in FP64), so the tile needs no compensation; it is
+// added to the global numerator once per run.  Bins come from the shared binner,
+// so a pixel pair falls in the same bin here as in the xi kernel.
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -53,15 +58,18 @@ __device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 
 constexpr int kTileW = 160;           // window bins per tile side
 constexpr int kBlk = 16;              // MFMA block side
-constexpr int kNBlk = kTileW / kBlk;  // blocks per tile side (<= 32: one mask word)
+constexpr int kNBlk = kTileW / kBlk;  // 10 blocks per tile side
+constexpr int kBI = 5, kBK = 3;       // block rows / block columns per wave
+constexpr int kMB = kBI * kBK;        // blocks per wave (slot j = kBK i + k)
 
 template <int N> struct IC { static constexpr int value = N; };
+
 
 template <typename T> struct DCfg;
 template <> struct DCfg<float> {
   using Rec = DRec32;
   static constexpr int RPW = 2;        // rows per wave per group
-  static constexpr int kStage = 1024;  // pixels per forest staged in LDS
+  static constexpr int kStage = 1024;  // pixels of the swept forest staged in LDS at a time
 };
 template <> struct DCfg<double> {
   using Rec = DRec64;
@@ -73,12 +81,14 @@ template <typename T, int NW>
 struct DSmem {
   static constexpr int NR = NW * DCfg<T>::RPW;  // rows per group
   static constexpr int S = DCfg<T>::kStage;
-  T sd[2][S], sw[2][S], sa[2][S], su[2][S], sb[2][S];  // staged pixels (0: f, 1: g)
-  T rowR[NR][2][kTileW];    // R^0, R^1 of each row of the group
-  T rowG[NR][2][kTileW];    // G^0, G^1
+  T sd[S], sw[S], sa[S], su[S], sb[S];  // staged pixels of the forest the lanes sweep
+  // R^0, R^1 and G^0, G^1 of each row of the group.  FP64 in both forms: LDS
+  // FP64 atomic adds run at about twice the rate of FP32 ones here.
+  double rowR[NR][2][kTileW];
+  double rowG[NR][2][kTileW];
   T rw[NR];                 // -w of each row (0: no row)
   T rowc[NR][4];            // w, w a, u, b of each sweep-1 row
-  uint32_t mx[NR], my[NR];  // 16-bin blocks reached by R (x) and G (y)
+  uint64_t act[NR][2];      // block bits of each row: bit 16 (W & 3) + j of word W >> 2
   T H[4][kTileW];           // pair histograms, written after sweep 1
   T Q[4][kTileW];
   double wdacc[kTileW];
@@ -92,6 +102,16 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
   return v;
 }
 
+__device__ __forceinline__ float lane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ int wave_isum(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -103,13 +123,15 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   using Cfg = DCfg<T>;
   using Rec = typename Cfg::Rec;
   constexpr int NW = BLOCK / 64, RPW = Cfg::RPW, NR = NW * RPW, S = Cfg::kStage, TW = kTileW;
-  constexpr int MB = (kNBlk * kNBlk + NW - 1) / NW;  // tile blocks per wave
   constexpr bool kF32 = sizeof(T) == 4;
+  static_assert(NW == 8, "block ownership assumes 8 waves");
   static_assert(NR % 2 == 0, "two rows per MFMA step");
   __shared__ DSmem<T, NW> sm;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lk = lane >> 4, lm = lane & 15;  // MFMA operand coordinates: k, and row/column in the block
+  const int wx = wave & 1, wy = wave >> 1;    // the wave's blocks: (wx + 2 i, wy + 4 k)
+  const bool col2 = wy + 4 * (kBK - 1) < kNBlk;  // the wave's third block column exists
 
   BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
@@ -117,12 +139,23 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   const Rec* __restrict__ recs;
   if constexpr (kF32) recs = a.drec32; else recs = a.drec64;
 
+  // this lane's (wave, slot) in the row activity ballots: word h covers waves 4h..4h+3
+  int bal_x[2], bal_y[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int W = 4 * h + (lane >> 4), j = lane & 15;
+    const int bx = (W & 1) + 2 * (j / kBK), by = (W >> 1) + 4 * (j % kBK);
+    const bool ok = j < kMB && by < kNBlk;
+    bal_x[h] = ok ? bx : 31;
+    bal_y[h] = ok ? by : 31;
+  }
+
   for (int e = tid; e < NR * 2 * TW; e += BLOCK) {
     (&sm.rowR[0][0][0])[e] = 0;
     (&sm.rowG[0][0][0])[e] = 0;
   }
   unsigned long long n_in = 0, n_alg = 0, n_lost = 0;  // statistics only
-  mf_d4 cacc[MB];  // FP64 MFMA accumulators of the wave's blocks (block b = wave + NW m)
+  mf_d4 cacc[kMB];  // FP64 MFMA accumulators of the wave's blocks
 
   for (;;) {
     __syncthreads();  // every thread has read the previous item
@@ -159,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           const bool first_pass = ab == 0 && bb == 0;
           const int nbx = (na + kBlk - 1) / kBlk, nby = (nbk + kBlk - 1) / kBlk;
 #pragma unroll
-          for (int m = 0; m < MB; ++m) cacc[m] = mf_d4{0.0, 0.0, 0.0, 0.0};
+          for (int j = 0; j < kMB; ++j) cacc[j] = mf_d4{0.0, 0.0, 0.0, 0.0};
           __syncthreads();  // the previous pass's flush has read the index tables
           for (int x = tid; x < TW; x += BLOCK) {
             sm.wdacc[x] = 0.0;
@@ -183,71 +216,84 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             }
             const T s = (T)s64, c = (T)c64;
             const T bsep = kF32 ? (T)(2.0 * a.glob->dc * s64) : (T)0;
-
-            // stage both forests' pixels (the first S of each)
-            __syncthreads();
-            {
-              const int sf = min(nf, S), sg = min(ng, S);
-              for (int e = tid; e < sf + sg; e += BLOCK) {
-                const bool gside = e >= sf;
-                const int k = gside ? e - sf : e;
-                const Rec r = recs[(gside ? pg : pf) + k];
-                const int sd = gside ? 1 : 0;
-                sm.sd[sd][k] = r.d;
-                sm.sw[sd][k] = r.w;
-                sm.sa[sd][k] = r.a;
-                sm.su[sd][k] = r.u;
-                sm.sb[sd][k] = r.b;
-              }
-            }
-            __syncthreads();
-
             // sweep-1 rows give H^{hm}[hx], Q^{hm}[hx] for entries e = tid + BLOCK v
             constexpr int NHE = (4 * TW + BLOCK - 1) / BLOCK;
             T hreg[NHE], qreg[NHE];
 #pragma unroll
             for (int v = 0; v < NHE; ++v) hreg[v] = qreg[v] = 0;
 
-            // one sweep: rows of side RS, lanes over the pixels of the other side
+            // one sweep: rows of side RS, lanes over the pixels of the other side,
+            // which are staged in LDS S at a time
             auto sweep = [&](auto rs_tag) {
-              constexpr int RS = decltype(rs_tag)::value, OS = 1 - RS;
+              constexpr int RS = decltype(rs_tag)::value;
               const int nr = RS ? ng : nf, no = RS ? nf : ng;
               const int64_t prow0 = RS ? pg : pf, poth0 = RS ? pf : pg;
+              const int nchunk = (no + S - 1) / S;
+              auto stage = [&](int c0) {
+                __syncthreads();
+                for (int e = tid; e < min(S, no - c0); e += BLOCK) {
+                  const Rec r = recs[poth0 + c0 + e];
+                  sm.sd[e] = r.d;
+                  sm.sw[e] = r.w;
+                  sm.sa[e] = r.a;
+                  sm.su[e] = r.u;
+                  sm.sb[e] = r.b;
+                }
+                __syncthreads();
+              };
+              if (nchunk == 1) stage(0);
+              // lane qq < RPW of each wave holds the record of the wave's row qq of
+              // the next group (loaded one group ahead)
+              T pd = 0, pw = 0, pa = 0, pu = 0, pb = 0;
+              double pD = 0.0;
+              auto fetch = [&](int gn) {
+                const int row = gn + wave * RPW + lane;
+                if (lane < RPW && row < nr) {
+                  const Rec r = recs[prow0 + row];
+                  pd = r.d; pw = r.w; pa = r.a; pu = r.u; pb = r.b;
+                  if constexpr (kF32) pD = r.D;
+                }
+              };
+              fetch(0);
               for (int g0 = 0; g0 < nr; g0 += NR) {
+                T gd[RPW], gw[RPW], ga[RPW], gu[RPW], gb[RPW];
+                double gD[RPW];
 #pragma unroll
                 for (int qq = 0; qq < RPW; ++qq) {
-                  const int slot = wave * RPW + qq, row = g0 + slot;
-                  uint32_t bx = 0, by = 0;
-                  if (row < nr) {
-                    T rd, rwt, raa, ruu, rbb;
-                    if (row < S) {
-                      rd = sm.sd[RS][row];
-                      rwt = sm.sw[RS][row];
-                      raa = sm.sa[RS][row];
-                      ruu = sm.su[RS][row];
-                      rbb = sm.sb[RS][row];
-                    } else {
-                      const Rec r = recs[prow0 + row];
-                      rd = r.d; rwt = r.w; raa = r.a; ruu = r.u; rbb = r.b;
-                    }
-                    for (int j = lane; j < no; j += 64) {
-                      T od, ow, oa, ou, ob;
-                      if (j < S) {
-                        od = sm.sd[OS][j];
-                        ow = sm.sw[OS][j];
-                        oa = sm.sa[OS][j];
-                        ou = sm.su[OS][j];
-                        ob = sm.sb[OS][j];
-                      } else {
-                        const Rec r = recs[poth0 + j];
-                        od = r.d; ow = r.w; oa = r.a; ou = r.u; ob = r.b;
-                      }
+                  gd[qq] = lane_val(pd, qq);
+                  gw[qq] = lane_val(pw, qq);
+                  ga[qq] = lane_val(pa, qq);
+                  gu[qq] = lane_val(pu, qq);
+                  gb[qq] = lane_val(pb, qq);
+                  gD[qq] = kF32 ? lane_val(pD, qq) : 0.0;
+                }
+                if (g0 + NR < nr) fetch(g0 + NR);
+                uint32_t bx[RPW], by[RPW];
+#pragma unroll
+                for (int qq = 0; qq < RPW; ++qq) bx[qq] = by[qq] = 0;
+                for (int ch = 0; ch < nchunk; ++ch) {
+                  const int c0 = ch * S, cn = min(S, no - c0);
+                  if (nchunk > 1) stage(c0);
+#pragma unroll
+                  for (int qq = 0; qq < RPW; ++qq) {
+                    const int slot = wave * RPW + qq, row = g0 + slot;
+                    if (row >= nr) continue;
+                    const T rd = gd[qq];
+                    const double rD = gD[qq];
+                    // a lane takes every niter-th pixel, so the 64 pixels of one pass are
+                    // spread over the forest and mostly fall in different bins (fewer
+                    // same-address LDS atomics)
+                    const int niter = (cn + 63) >> 6;
+                    for (int it = 0; it < niter; ++it) {
+                      const int j = it + niter * lane;
+                      if (j >= cn) continue;
+                      const T od = sm.sd[j], ow = sm.sw[j], oa = sm.sa[j], ou = sm.su[j], ob = sm.sb[j];
                       T rp, rt;
                       separations(rd, od, c, s, bsep, rp, rt);
                       if (!K.may_be_in(rp, rt)) continue;
                       const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
                         if constexpr (kF32) {
-                          separations64(recs[prow0 + row].D, recs[poth0 + j].D, c64, s64, rp64, rt64);
+                          separations64(rD, recs[poth0 + c0 + j].D, c64, s64, rp64, rt64);
                         } else {
                           rp64 = rp;
                           rt64 = rt;
@@ -262,58 +308,66 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                       if (RS == 0 && first_pass) ++n_in;
                       const int x = w - a0, y = w - b0;
                       if ((unsigned)x < (unsigned)na) {
-                        atomicAdd(&sm.rowR[slot][0][x], ow);
-                        atomicAdd(&sm.rowR[slot][1][x], ow * oa);
-                        bx |= 1u << (x >> 4);
+                        atomicAdd(&sm.rowR[slot][0][x], (double)ow);
+                        atomicAdd(&sm.rowR[slot][1][x], (double)(ow * oa));
+                        bx[qq] |= 1u << (x >> 4);
                       }
                       if ((unsigned)y < (unsigned)nbk) {
-                        atomicAdd(&sm.rowG[slot][0][y], ou);
-                        atomicAdd(&sm.rowG[slot][1][y], ob);
-                        by |= 1u << (y >> 4);
+                        atomicAdd(&sm.rowG[slot][0][y], (double)ou);
+                        atomicAdd(&sm.rowG[slot][1][y], (double)ob);
+                        by[qq] |= 1u << (y >> 4);
                       }
                     }
-                    if (lane == 0) {
-                      sm.rw[slot] = -rwt;
-                      sm.rowc[slot][0] = rwt;
-                      sm.rowc[slot][1] = rwt * raa;
-                      sm.rowc[slot][2] = ruu;
-                      sm.rowc[slot][3] = rbb;
-                    }
-                  } else if (lane == 0) {
-                    sm.rw[slot] = 0;
-                    sm.rowc[slot][0] = sm.rowc[slot][1] = sm.rowc[slot][2] = sm.rowc[slot][3] = 0;
                   }
-                  bx = wave_or(bx);
-                  by = wave_or(by);
+                }
+#pragma unroll
+                for (int qq = 0; qq < RPW; ++qq) {
+                  const int slot = wave * RPW + qq, row = g0 + slot;
                   if (lane == 0) {
-                    sm.mx[slot] = bx;
-                    sm.my[slot] = by;
+                    if (row < nr) {
+                      sm.rw[slot] = -gw[qq];
+                      sm.rowc[slot][0] = gw[qq];
+                      sm.rowc[slot][1] = gw[qq] * ga[qq];
+                      sm.rowc[slot][2] = gu[qq];
+                      sm.rowc[slot][3] = gb[qq];
+                    } else {
+                      sm.rw[slot] = 0;
+                      sm.rowc[slot][0] = sm.rowc[slot][1] = sm.rowc[slot][2] = sm.rowc[slot][3] = 0;
+                    }
+                  }
+                  const uint32_t bxq = wave_or(bx[qq]), byq = wave_or(by[qq]);
+                  // block bits of every wave for this row
+                  const uint64_t w0 = __ballot(((bxq >> bal_x[0]) & (byq >> bal_y[0]) & 1u) != 0u);
+                  const uint64_t w1 = __ballot(((bxq >> bal_x[1]) & (byq >> bal_y[1]) & 1u) != 0u);
+                  if (lane == 0) {
+                    sm.act[slot][0] = w0;
+                    sm.act[slot][1] = w1;
                   }
                 }
                 __syncthreads();
 
                 // MFMA steps on the wave's blocks, rows (2 st, 2 st + 1) per step
+                {
+                  const int slot_l = lk >> 1, comp = lk & 1;
+                  const double* pa = &sm.rowR[slot_l][comp][wx * kBlk + lm];
+                  const double* pb = &sm.rowG[slot_l][comp][wy * kBlk + lm];
 #pragma unroll 1
-                for (int st = 0; st < NR / 2; ++st) {
-                  const uint32_t mx0 = sm.mx[2 * st], mx1 = sm.mx[2 * st + 1];
-                  const uint32_t my0 = sm.my[2 * st], my1 = sm.my[2 * st + 1];
-                  if ((mx0 == 0u || my0 == 0u) && (mx1 == 0u || my1 == 0u)) continue;
-                  const int slot = 2 * st + (lk >> 1), comp = lk & 1;
-                  const double wr = (double)sm.rw[slot];
-                  // block coordinates are recomputed every step (an opaque copy
-                  // of the wave index keeps them from being hoisted into registers)
-                  int wv = wave;
-                  asm volatile("" : "+s"(wv));
+                  for (int st = 0; st < NR / 2; ++st) {
+                    const uint32_t bits = __builtin_amdgcn_readfirstlane(
+                        (uint32_t)((sm.act[2 * st][wave >> 2] | sm.act[2 * st + 1][wave >> 2]) >> (16 * (wave & 3))) &
+                        ((1u << kMB) - 1u));
+                    if (bits == 0u) continue;
+                    const int so = 2 * st * 2 * TW;  // two rows further per step
+                    const double wr = (double)sm.rw[2 * st + slot_l];
+                    double av[kBI], bv[kBK];
 #pragma unroll
-                  for (int m = 0; m < MB; ++m) {
-                    const int b = wv + NW * m;
-                    const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
-                    if (ibx < nbx && iby < nby &&
-                        ((((mx0 >> ibx) & (my0 >> iby)) | ((mx1 >> ibx) & (my1 >> iby))) & 1u)) {
-                      const double av = wr * (double)sm.rowR[slot][comp][ibx * kBlk + lm];
-                      const double bv = (double)sm.rowG[slot][comp][iby * kBlk + lm];
-                      cacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cacc[m], 0, 0, 0);
-                    }
+                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + 2 * kBlk * i];
+#pragma unroll
+                    for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || col2) ? (double)pb[so + 4 * kBlk * k] : 0.0;
+#pragma unroll
+                    for (int j = 0; j < kMB; ++j)
+                      if ((bits >> j) & 1u)
+                        cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
                   }
                 }
                 if (RS == 0) {
@@ -322,11 +376,14 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                     const int e = tid + BLOCK * v;
                     if (e < 4 * TW) {
                       const int hm = e / TW, hx = e - hm * TW, l = hm & 1, k = hm >> 1;
-#pragma unroll 1
+                      T h = hreg[v], qv = qreg[v];
+#pragma unroll
                       for (int r = 0; r < NR; ++r) {
-                        hreg[v] = fma(sm.rowc[r][k], sm.rowR[r][l][hx], hreg[v]);
-                        qreg[v] = fma(sm.rowc[r][2 + k], sm.rowG[r][l][hx], qreg[v]);
+                        h = fma(sm.rowc[r][k], (T)sm.rowR[r][l][hx], h);
+                        qv = fma(sm.rowc[r][2 + k], (T)sm.rowG[r][l][hx], qv);
                       }
+                      hreg[v] = h;
+                      qreg[v] = qv;
                     }
                   }
                 }
@@ -338,8 +395,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   int cx = 0, cy = 0;
                   for (int x = lane; x < TW; x += 64) {
                     if (a.counters) {
-                      cx += (sm.rowR[slot][0][x] != (T)0) | (sm.rowR[slot][1][x] != (T)0);
-                      cy += (sm.rowG[slot][0][x] != (T)0) | (sm.rowG[slot][1][x] != (T)0);
+                      cx += (sm.rowR[slot][0][x] != 0.0) | (sm.rowR[slot][1][x] != 0.0);
+                      cy += (sm.rowG[slot][0][x] != 0.0) | (sm.rowG[slot][1][x] != 0.0);
                     }
                     sm.rowR[slot][0][x] = sm.rowR[slot][1][x] = 0;
                     sm.rowG[slot][0][x] = sm.rowG[slot][1][x] = 0;
@@ -365,18 +422,22 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             }
             __syncthreads();
             // ---- H (x) Q: one more step; the Kronecker term on the diagonal; w_A
+            {
+              double av[kBI], bv[kBK];
 #pragma unroll
-            for (int m = 0; m < MB; ++m) {
-              const int b = wave + NW * m;
-              const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
-              if (ibx < nbx && iby < nby) {
-                const double av = (double)sm.H[lk][ibx * kBlk + lm];
-                const double bv = (double)sm.Q[lk][iby * kBlk + lm];
-                cacc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cacc[m], 0, 0, 0);
-                if (a0 == b0 && ibx == iby) {
+              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + 2 * i) * kBlk + lm];
 #pragma unroll
-                  for (int r = 0; r < 4; ++r)
-                    if (mfma_row(lk, r) == lm) cacc[m][r] += (double)sm.H[0][ibx * kBlk + lm];
+              for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || col2) ? (double)sm.Q[lk][(wy + 4 * k) * kBlk + lm] : 0.0;
+#pragma unroll
+              for (int j = 0; j < kMB; ++j) {
+                const int bx = wx + 2 * (j / kBK), by = wy + 4 * (j % kBK);
+                if (bx < nbx && by < nby) {
+                  cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
+                  if (a0 == b0 && bx == by) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                      if (mfma_row(lk, r) == lm) cacc[j][r] += (double)sm.H[0][bx * kBlk + lm];
+                  }
                 }
               }
             }
@@ -399,21 +460,16 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           __syncthreads();
 
           // ---- add the wave's blocks to the global numerator (and w_A)
-          {
-            int wv = wave;
 #pragma unroll
-            for (int m = 0; m < MB; ++m) {
-              asm volatile("" : "+s"(wv));
-              const int b = wv + NW * m;
-              const int ibx = b / kNBlk, iby = b - ibx * kNBlk;
-              if (ibx < nbx && iby < nby) {
-                const int oy = sm.oy[iby * kBlk + lm];
+          for (int j = 0; j < kMB; ++j) {
+            const int bx = wx + 2 * (j / kBK), by = wy + 4 * (j % kBK);
+            if (bx < nbx && by < nby) {
+              const int oy = sm.oy[by * kBlk + lm];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                  const int ox = sm.ox[ibx * kBlk + mfma_row(lk, r)];
-                  const double v = cacc[m][r];
-                  if (ox >= 0 && oy >= 0 && v != 0.0) atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
-                }
+              for (int r = 0; r < 4; ++r) {
+                const int ox = sm.ox[bx * kBlk + mfma_row(lk, r)];
+                const double v = cacc[j][r];
+                if (ox >= 0 && oy >= 0 && v != 0.0) atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
               }
             }
           }

@@ -597,8 +597,11 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
       HIP_TRY(launch_sort_keys(k_in, k_out, v_in, v_out, W.n_pairs, tmp, bytes, st));
       a.wkeys = k_out;
       a.worder = v_out;
-      a.chunk = kDmatChunk;
-      a.n_items = (W.n_pairs + kDmatChunk - 1) / kDmatChunk;
+      // at least ~8 items per workgroup slot, at most kDmatChunk pairs per item
+      // (each item adds its tile to the global numerator once per run)
+      const int64_t per = W.n_pairs / (8 * (int64_t)ctx->n_cu);
+      a.chunk = (int32_t)(per < 64 ? 64 : (per > kDmatChunk ? kDmatChunk : per));
+      a.n_items = (W.n_pairs + a.chunk - 1) / a.chunk;
     }
     a.drec32 = P.drec32;
     a.drec64 = P.drec64;
