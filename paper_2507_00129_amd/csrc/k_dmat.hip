@@ -28,9 +28,17 @@
 // reach (one ballot gives every wave's block bits), and a step is issued only
 // for the blocks that one of its two rows reaches on both sides; the work issued
 // stays close to the sparse row outer products.  The tile is 10 x 10 blocks;
-// wave w = (wx, wy) = (w & 1, w >> 1) owns block rows wx + 2i (i < 5) and
-// block columns wy + 4k (k < 3), so its operand addresses are one per-wave base
-// plus compile-time offsets.
+// the waves form a WX x WY grid and wave (wx, wy) owns block rows wx + WX i and
+// block columns wy + WY k, so its operand addresses are one per-wave base plus
+// compile-time offsets.  With 8 waves (2 per SIMD) a wave holds up to 15 FP64
+// blocks; with 4 waves (1 per SIMD, twice the registers) it holds 25 and sweeps
+// four rows per group, which gives the sweep more independent work.
+//
+// Within one forest, q = (u, b) = (w / W, w a / S) is p weighted per pixel and
+// scaled per forest, so the G histograms of a row are its R histograms times
+// (1 / W, 1 / S) of the other forest: only R^0 = sum w and R^1 = sum w a are
+// built (over a second range too when the tile's two axes cover different
+// window blocks).
 //
 // The workgroup takes the pairs of a run one at a time.  In each sweep the
 // pixels the lanes run over are staged in LDS (in chunks for long forests),
@@ -59,8 +67,15 @@ __device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 constexpr int kTileW = 160;           // window bins per tile side
 constexpr int kBlk = 16;              // MFMA block side
 constexpr int kNBlk = kTileW / kBlk;  // 10 blocks per tile side
-constexpr int kBI = 5, kBK = 3;       // block rows / block columns per wave
-constexpr int kMB = kBI * kBK;        // blocks per wave (slot j = kBK i + k)
+// Wave grid of a workgroup of NW waves: WX x WY waves, BI block rows and BK
+// block columns per wave (slot j = BK i + k), RPW rows swept per wave per group.
+template <int NW> struct WaveGrid;
+template <> struct WaveGrid<8> {
+  static constexpr int WX = 2, WY = 4, BI = 5, BK = 3, RPW = 2;
+};
+template <> struct WaveGrid<4> {
+  static constexpr int WX = 2, WY = 2, BI = 5, BK = 5, RPW = 4;
+};
 
 template <int N> struct IC { static constexpr int value = N; };
 
@@ -68,27 +83,26 @@ template <int N> struct IC { static constexpr int value = N; };
 template <typename T> struct DCfg;
 template <> struct DCfg<float> {
   using Rec = DRec32;
-  static constexpr int RPW = 2;        // rows per wave per group
   static constexpr int kStage = 1024;  // pixels of the swept forest staged in LDS at a time
 };
 template <> struct DCfg<double> {
   using Rec = DRec64;
-  static constexpr int RPW = 1;
   static constexpr int kStage = 512;
 };
 
 template <typename T, int NW>
 struct DSmem {
-  static constexpr int NR = NW * DCfg<T>::RPW;  // rows per group
+  static constexpr int NR = NW * WaveGrid<NW>::RPW;  // rows per group
   static constexpr int S = DCfg<T>::kStage;
-  T sd[S], sw[S], sa[S], su[S], sb[S];  // staged pixels of the forest the lanes sweep
-  // R^0, R^1 and G^0, G^1 of each row of the group.  FP64 in both forms: LDS
-  // FP64 atomic adds run at about twice the rate of FP32 ones here.
+  T sd[S], sw[S], sa[S];  // staged pixels of the forest the lanes sweep
+  // R^0, R^1 of each row of the group over the tile's x range, and over its y
+  // range when that differs.  FP64 in both forms: LDS FP64 atomic adds run at
+  // about twice the rate of FP32 ones here.
   double rowR[NR][2][kTileW];
   double rowG[NR][2][kTileW];
   T rw[NR];                 // -w of each row (0: no row)
   T rowc[NR][4];            // w, w a, u, b of each sweep-1 row
-  uint64_t act[NR][2];      // block bits of each row: bit 16 (W & 3) + j of word W >> 2
+  uint64_t act[NR][2];      // block bits of each row: 128 / NW bits per wave
   T H[4][kTileW];           // pair histograms, written after sweep 1
   T Q[4][kTileW];
   double wdacc[kTileW];
@@ -96,10 +110,12 @@ struct DSmem {
   int64_t item;
 };
 
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+// OR of a kNBlk-bit mask over the wave, one ballot per bit (no LDS round trips).
+__device__ __forceinline__ uint32_t wave_or_blocks(uint32_t v) {
+  uint32_t r = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= (uint32_t)__shfl_xor((int)v, o, 64);
-  return v;
+  for (int b = 0; b < kNBlk; ++b) r |= (__ballot((v >> b) & 1u) != 0ull) ? (1u << b) : 0u;
+  return r;
 }
 
 __device__ __forceinline__ float lane_val(float v, int l) {
@@ -112,26 +128,24 @@ __device__ __forceinline__ double lane_val(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 template <typename T, int BLOCK, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   using Cfg = DCfg<T>;
   using Rec = typename Cfg::Rec;
-  constexpr int NW = BLOCK / 64, RPW = Cfg::RPW, NR = NW * RPW, S = Cfg::kStage, TW = kTileW;
+  constexpr int NW = BLOCK / 64, S = Cfg::kStage, TW = kTileW;
+  using WG = WaveGrid<NW>;
+  constexpr int RPW = WG::RPW, NR = NW * RPW, WX = WG::WX, WY = WG::WY;
+  constexpr int kBI = WG::BI, kBK = WG::BK, kMB = kBI * kBK;
+  constexpr int BPW = 128 / NW, WPW = 64 / BPW;  // ballot bits per wave, waves per 64-bit word
   constexpr bool kF32 = sizeof(T) == 4;
-  static_assert(NW == 8, "block ownership assumes 8 waves");
+  static_assert(WX * WY == NW && kMB <= BPW && kMB < 32, "wave grid");
   static_assert(NR % 2 == 0, "two rows per MFMA step");
   __shared__ DSmem<T, NW> sm;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lk = lane >> 4, lm = lane & 15;  // MFMA operand coordinates: k, and row/column in the block
-  const int wx = wave & 1, wy = wave >> 1;    // the wave's blocks: (wx + 2 i, wy + 4 k)
-  const bool col2 = wy + 4 * (kBK - 1) < kNBlk;  // the wave's third block column exists
+  const int wx = wave % WX, wy = wave / WX;  // the wave's blocks: (wx + WX i, wy + WY k)
+  const bool lastcol = wy + WY * (kBK - 1) < kNBlk;  // the wave's last block column exists
 
   BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
@@ -143,9 +157,9 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   int bal_x[2], bal_y[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int W = 4 * h + (lane >> 4), j = lane & 15;
-    const int bx = (W & 1) + 2 * (j / kBK), by = (W >> 1) + 4 * (j % kBK);
-    const bool ok = j < kMB && by < kNBlk;
+    const int W = WPW * h + lane / BPW, j = lane % BPW;
+    const int bx = W % WX + WX * (j / kBK), by = W / WX + WY * (j % kBK);
+    const bool ok = j < kMB && bx < kNBlk && by < kNBlk;
     bal_x[h] = ok ? bx : 31;
     bal_y[h] = ok ? by : 31;
   }
@@ -191,6 +205,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           const int b0 = bb * TW, nbk = min(TW, nwin - b0);
           const bool first_pass = ab == 0 && bb == 0;
           const int nbx = (na + kBlk - 1) / kBlk, nby = (nbk + kBlk - 1) / kBlk;
+          const bool diag = a0 == b0;  // both axes cover the same window bins
 #pragma unroll
           for (int j = 0; j < kMB; ++j) cacc[j] = mf_d4{0.0, 0.0, 0.0, 0.0};
           __syncthreads();  // the previous pass's flush has read the index tables
@@ -214,13 +229,29 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
               nf = fi.npix;
               ng = gi.npix;
             }
+            // G = R (1 / W, 1 / S) of the forest the lanes sweep (0 where the term is off)
+            double gsc[2][2];
+            {
+              const EtaInfo ef = a.einfo[a.sorted[a.pair_p[q]]];
+              const EtaInfo eg = a.einfo[a.sorted[a.nbr[q]]];
+              gsc[0][0] = ef.active ? 1.0 / ef.W : 0.0;
+              gsc[0][1] = ef.slope ? 1.0 / ef.S : 0.0;
+              gsc[1][0] = eg.active ? 1.0 / eg.W : 0.0;
+              gsc[1][1] = eg.slope ? 1.0 / eg.S : 0.0;
+            }
             const T s = (T)s64, c = (T)c64;
             const T bsep = kF32 ? (T)(2.0 * a.glob->dc * s64) : (T)0;
-            // sweep-1 rows give H^{hm}[hx], Q^{hm}[hx] for entries e = tid + BLOCK v
-            constexpr int NHE = (4 * TW + BLOCK - 1) / BLOCK;
-            T hreg[NHE], qreg[NHE];
-#pragma unroll
-            for (int v = 0; v < NHE; ++v) hreg[v] = qreg[v] = 0;
+            // sweep-1 rows give the pair histograms H^{kl}[x], Q^{kl}[x] (kl = 2k + l),
+            // kept in registers: with 8 waves, thread tid - (BLOCK - 2 TW) (the last
+            // waves, which own fewer tile blocks) keeps H (< TW) or Q of one x; with
+            // 4 waves, thread tid < TW keeps both for x = tid
+            constexpr bool kHQsplit = BLOCK >= 2 * TW;
+            const int hq_t = kHQsplit ? tid - (BLOCK - 2 * TW) : tid;
+            const bool hq_on = hq_t >= 0 && hq_t < (kHQsplit ? 2 * TW : TW);
+            const bool hq_q = kHQsplit && hq_t >= TW;
+            const int hq_x = hq_q ? hq_t - TW : hq_t;
+            T hq0 = 0, hq1 = 0, hq2 = 0, hq3 = 0;
+            T qq0 = 0, qq1 = 0, qq2 = 0, qq3 = 0;  // Q when not split
 
             // one sweep: rows of side RS, lanes over the pixels of the other side,
             // which are staged in LDS S at a time
@@ -236,8 +267,6 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   sm.sd[e] = r.d;
                   sm.sw[e] = r.w;
                   sm.sa[e] = r.a;
-                  sm.su[e] = r.u;
-                  sm.sb[e] = r.b;
                 }
                 __syncthreads();
               };
@@ -274,26 +303,26 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 for (int ch = 0; ch < nchunk; ++ch) {
                   const int c0 = ch * S, cn = min(S, no - c0);
                   if (nchunk > 1) stage(c0);
+                  // a lane takes every niter-th pixel, so the 64 pixels of one pass are
+                  // spread over the forest and mostly fall in different bins; each pixel
+                  // is paired with all RPW rows of the wave
+                  const int niter = (cn + 63) >> 6;
+                  for (int it = 0; it < niter; ++it) {
+                    const int j = it + niter * lane;
+                    if (j >= cn) continue;
+                    const T od = sm.sd[j], ow = sm.sw[j], oa = sm.sa[j];
+                    const T owa = ow * oa;
 #pragma unroll
-                  for (int qq = 0; qq < RPW; ++qq) {
-                    const int slot = wave * RPW + qq, row = g0 + slot;
-                    if (row >= nr) continue;
-                    const T rd = gd[qq];
-                    const double rD = gD[qq];
-                    // a lane takes every niter-th pixel, so the 64 pixels of one pass are
-                    // spread over the forest and mostly fall in different bins (fewer
-                    // same-address LDS atomics)
-                    const int niter = (cn + 63) >> 6;
-                    for (int it = 0; it < niter; ++it) {
-                      const int j = it + niter * lane;
-                      if (j >= cn) continue;
-                      const T od = sm.sd[j], ow = sm.sw[j], oa = sm.sa[j], ou = sm.su[j], ob = sm.sb[j];
+                    for (int qq = 0; qq < RPW; ++qq) {
+                      const int slot = wave * RPW + qq;
+                      if (g0 + slot >= nr) continue;
+                      const T rd = gd[qq];
                       T rp, rt;
                       separations(rd, od, c, s, bsep, rp, rt);
                       if (!K.may_be_in(rp, rt)) continue;
                       const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
                         if constexpr (kF32) {
-                          separations64(rD, recs[poth0 + c0 + j].D, c64, s64, rp64, rt64);
+                          separations64(gD[qq], recs[poth0 + c0 + j].D, c64, s64, rp64, rt64);
                         } else {
                           rp64 = rp;
                           rt64 = rt;
@@ -309,12 +338,12 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                       const int x = w - a0, y = w - b0;
                       if ((unsigned)x < (unsigned)na) {
                         atomicAdd(&sm.rowR[slot][0][x], (double)ow);
-                        atomicAdd(&sm.rowR[slot][1][x], (double)(ow * oa));
+                        atomicAdd(&sm.rowR[slot][1][x], (double)owa);
                         bx[qq] |= 1u << (x >> 4);
                       }
-                      if ((unsigned)y < (unsigned)nbk) {
-                        atomicAdd(&sm.rowG[slot][0][y], (double)ou);
-                        atomicAdd(&sm.rowG[slot][1][y], (double)ob);
+                      if (!diag && (unsigned)y < (unsigned)nbk) {
+                        atomicAdd(&sm.rowG[slot][0][y], (double)ow);
+                        atomicAdd(&sm.rowG[slot][1][y], (double)owa);
                         by[qq] |= 1u << (y >> 4);
                       }
                     }
@@ -335,7 +364,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                       sm.rowc[slot][0] = sm.rowc[slot][1] = sm.rowc[slot][2] = sm.rowc[slot][3] = 0;
                     }
                   }
-                  const uint32_t bxq = wave_or(bx[qq]), byq = wave_or(by[qq]);
+                  const uint32_t bxq = wave_or_blocks(bx[qq]);
+                  const uint32_t byq = diag ? bxq : wave_or_blocks(by[qq]);
                   // block bits of every wave for this row
                   const uint64_t w0 = __ballot(((bxq >> bal_x[0]) & (byq >> bal_y[0]) & 1u) != 0u);
                   const uint64_t w1 = __ballot(((bxq >> bal_x[1]) & (byq >> bal_y[1]) & 1u) != 0u);
@@ -350,40 +380,47 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 {
                   const int slot_l = lk >> 1, comp = lk & 1;
                   const double* pa = &sm.rowR[slot_l][comp][wx * kBlk + lm];
-                  const double* pb = &sm.rowG[slot_l][comp][wy * kBlk + lm];
+                  const double* pb = diag ? &sm.rowR[slot_l][comp][wy * kBlk + lm] : &sm.rowG[slot_l][comp][wy * kBlk + lm];
+                  const double gs = gsc[1 - RS][comp];
 #pragma unroll 1
                   for (int st = 0; st < NR / 2; ++st) {
                     const uint32_t bits = __builtin_amdgcn_readfirstlane(
-                        (uint32_t)((sm.act[2 * st][wave >> 2] | sm.act[2 * st + 1][wave >> 2]) >> (16 * (wave & 3))) &
+                        (uint32_t)((sm.act[2 * st][wave / WPW] | sm.act[2 * st + 1][wave / WPW]) >>
+                                   (BPW * (wave % WPW))) &
                         ((1u << kMB) - 1u));
                     if (bits == 0u) continue;
                     const int so = 2 * st * 2 * TW;  // two rows further per step
                     const double wr = (double)sm.rw[2 * st + slot_l];
                     double av[kBI], bv[kBK];
 #pragma unroll
-                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + 2 * kBlk * i];
+                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + WX * kBlk * i];
 #pragma unroll
-                    for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || col2) ? (double)pb[so + 4 * kBlk * k] : 0.0;
+                    for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || lastcol) ? gs * pb[so + WY * kBlk * k] : 0.0;
 #pragma unroll
                     for (int j = 0; j < kMB; ++j)
                       if ((bits >> j) & 1u)
                         cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
                   }
                 }
-                if (RS == 0) {
+                if (RS == 0 && hq_on) {
+                  const double* hv = (hq_q && !diag) ? &sm.rowG[0][0][hq_x] : &sm.rowR[0][0][hq_x];
+                  const int ck = hq_q ? 2 : 0;
 #pragma unroll
-                  for (int v = 0; v < NHE; ++v) {
-                    const int e = tid + BLOCK * v;
-                    if (e < 4 * TW) {
-                      const int hm = e / TW, hx = e - hm * TW, l = hm & 1, k = hm >> 1;
-                      T h = hreg[v], qv = qreg[v];
-#pragma unroll
-                      for (int r = 0; r < NR; ++r) {
-                        h = fma(sm.rowc[r][k], (T)sm.rowR[r][l][hx], h);
-                        qv = fma(sm.rowc[r][2 + k], (T)sm.rowG[r][l][hx], qv);
-                      }
-                      hreg[v] = h;
-                      qreg[v] = qv;
+                  for (int r = 0; r < NR; ++r) {
+                    const T v0 = (T)hv[r * 2 * TW], v1 = (T)hv[r * 2 * TW + TW];
+                    const T c0 = sm.rowc[r][ck], c1 = sm.rowc[r][ck + 1];
+                    hq0 = fma(c0, v0, hq0);
+                    hq1 = fma(c0, v1, hq1);
+                    hq2 = fma(c1, v0, hq2);
+                    hq3 = fma(c1, v1, hq3);
+                    if constexpr (!kHQsplit) {
+                      const double* gv = diag ? &sm.rowR[r][0][hq_x] : &sm.rowG[r][0][hq_x];
+                      const T g0 = (T)gv[0], g1 = (T)gv[TW];
+                      const T d0 = sm.rowc[r][2], d1 = sm.rowc[r][3];
+                      qq0 = fma(d0, g0, qq0);
+                      qq1 = fma(d0, g1, qq1);
+                      qq2 = fma(d1, g0, qq2);
+                      qq3 = fma(d1, g1, qq3);
                     }
                   }
                 }
@@ -395,29 +432,39 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   int cx = 0, cy = 0;
                   for (int x = lane; x < TW; x += 64) {
                     if (a.counters) {
-                      cx += (sm.rowR[slot][0][x] != 0.0) | (sm.rowR[slot][1][x] != 0.0);
-                      cy += (sm.rowG[slot][0][x] != 0.0) | (sm.rowG[slot][1][x] != 0.0);
+                      cx += __popcll(__ballot((sm.rowR[slot][0][x] != 0.0) | (sm.rowR[slot][1][x] != 0.0)));
+                      if (!diag) cy += __popcll(__ballot((sm.rowG[slot][0][x] != 0.0) | (sm.rowG[slot][1][x] != 0.0)));
                     }
                     sm.rowR[slot][0][x] = sm.rowR[slot][1][x] = 0;
                     sm.rowG[slot][0][x] = sm.rowG[slot][1][x] = 0;
                   }
-                  if (a.counters) {
-                    cx = wave_isum(cx);
-                    cy = wave_isum(cy);
-                    if (lane == 0) n_alg += 2ull * (unsigned long long)cx * (unsigned long long)cy;
-                  }
+                  if (diag) cy = cx;
+                  if (a.counters && lane == 0) n_alg += 2ull * (unsigned long long)cx * (unsigned long long)cy;
                 }
               }
             };
 
             // ---- sweep 1: rows i of f
             sweep(IC<0>{});
-#pragma unroll
-            for (int v = 0; v < NHE; ++v) {
-              const int e = tid + BLOCK * v;
-              if (e < 4 * TW) {
-                (&sm.H[0][0])[e] = hreg[v];
-                (&sm.Q[0][0])[e] = qreg[v];
+            if (hq_on) {
+              // Q^{kl} = (1 / W_g, 1 / S_g)_l sum_r (u_r, b_r)_k R^l_r
+              const T s0 = (T)gsc[1][0], s1 = (T)gsc[1][1];
+              if (hq_q) {
+                sm.Q[0][hq_x] = hq0 * s0;
+                sm.Q[1][hq_x] = hq1 * s1;
+                sm.Q[2][hq_x] = hq2 * s0;
+                sm.Q[3][hq_x] = hq3 * s1;
+              } else {
+                sm.H[0][hq_x] = hq0;
+                sm.H[1][hq_x] = hq1;
+                sm.H[2][hq_x] = hq2;
+                sm.H[3][hq_x] = hq3;
+              }
+              if constexpr (!kHQsplit) {
+                sm.Q[0][hq_x] = qq0 * s0;
+                sm.Q[1][hq_x] = qq1 * s1;
+                sm.Q[2][hq_x] = qq2 * s0;
+                sm.Q[3][hq_x] = qq3 * s1;
               }
             }
             __syncthreads();
@@ -425,12 +472,13 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             {
               double av[kBI], bv[kBK];
 #pragma unroll
-              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + 2 * i) * kBlk + lm];
+              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + WX * i) * kBlk + lm];
 #pragma unroll
-              for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || col2) ? (double)sm.Q[lk][(wy + 4 * k) * kBlk + lm] : 0.0;
+              for (int k = 0; k < kBK; ++k)
+                bv[k] = (k < kBK - 1 || lastcol) ? (double)sm.Q[lk][(wy + WY * k) * kBlk + lm] : 0.0;
 #pragma unroll
               for (int j = 0; j < kMB; ++j) {
-                const int bx = wx + 2 * (j / kBK), by = wy + 4 * (j % kBK);
+                const int bx = wx + WX * (j / kBK), by = wy + WY * (j % kBK);
                 if (bx < nbx && by < nby) {
                   cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
                   if (a0 == b0 && bx == by) {
@@ -444,11 +492,9 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             if (a.counters && wave == 0) {
               int hx = 0, qy = 0;
               for (int x = lane; x < TW; x += 64) {
-                hx += x < na && sm.H[0][x] != (T)0;
-                qy += x < nbk && ((sm.Q[0][x] != (T)0) | (sm.Q[3][x] != (T)0));
+                hx += __popcll(__ballot(x < na && sm.H[0][x] != (T)0));
+                qy += __popcll(__ballot(x < nbk && ((sm.Q[0][x] != (T)0) | (sm.Q[3][x] != (T)0))));
               }
-              hx = wave_isum(hx);
-              qy = wave_isum(qy);
               if (lane == 0) n_alg += 4ull * (unsigned long long)hx * (unsigned long long)qy;
             }
             if (bb == 0)
@@ -462,7 +508,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           // ---- add the wave's blocks to the global numerator (and w_A)
 #pragma unroll
           for (int j = 0; j < kMB; ++j) {
-            const int bx = wx + 2 * (j / kBK), by = wy + 4 * (j % kBK);
+            const int bx = wx + WX * (j / kBK), by = wy + WY * (j % kBK);
             if (bx < nbx && by < nby) {
               const int oy = sm.oy[by * kBlk + lm];
 #pragma unroll
@@ -521,8 +567,8 @@ __global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
   idx[q] = (int32_t)q;
 }
 
-constexpr int kNumVariants = 1;
-const char* const kNames[kNumVariants] = {"b512-mfma64"};
+constexpr int kNumVariants = 2;
+const char* const kNames[kNumVariants] = {"b512-mfma64", "b256-mfma64"};
 
 template <typename T, int BLOCK>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
@@ -561,14 +607,14 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  (void)variant;
-  if (precision == LYA_FP64) return launch_one<double, 512>(a, blocks, st);
-  return launch_one<float, 512>(a, blocks, st);
+  if (precision == LYA_FP64)
+    return variant == 0 ? launch_one<double, 512>(a, blocks, st) : launch_one<double, 256>(a, blocks, st);
+  return variant == 0 ? launch_one<float, 512>(a, blocks, st) : launch_one<float, 256>(a, blocks, st);
 }
 
 int dmat_blocks_per_cu(int variant, int precision) {
-  (void)variant;
-  return precision == LYA_FP64 ? occupancy<double, 512>() : occupancy<float, 512>();
+  if (precision == LYA_FP64) return variant == 0 ? occupancy<double, 512>() : occupancy<double, 256>();
+  return variant == 0 ? occupancy<float, 512>() : occupancy<float, 256>();
 }
 
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st) {

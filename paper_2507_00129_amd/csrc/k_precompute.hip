@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void forest_stats_kernel(PrecomputeArgs a, lya
     e.lbar = lbar;
     e.S = S;
     e.slope = slope;
-    e.pad = active;
+    e.active = active;
     a.einfo[f] = e;
     if (n > 0) {
       // positive doubles order like their bit patterns
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PrecomputeArgs a, lya_forests
     if (a.want_xi32) a.rec32[i] = Rec32{(float)(D - dc), (float)wd, (float)w, (float)de};
     if (a.want_xi64) a.rec64[i] = Rec64{D, wd, w, de};
     if (a.want_d32 || a.want_d64) {
-      const bool act = e.pad != 0;
+      const bool act = e.active != 0;
       const double am = act ? F.loglam[i] - e.lbar : 0.0;
       const double uu = act ? w / e.W : 0.0;
       const double bb = e.slope ? w * am / e.S : 0.0;

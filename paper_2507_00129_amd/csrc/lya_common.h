@@ -28,8 +28,8 @@ struct EtaInfo {
   double W;      // sum w
   double lbar;   // sum w L / W
   double S;      // sum w (L - lbar)^2
-  int32_t slope; // slope term kept
-  int32_t pad;
+  int32_t slope;   // slope term kept
+  int32_t active;  // W > 0 and the projection applies (eta mode not identity)
 };
 
 // Device-side scalars produced by the precompute stage.
@@ -224,6 +224,7 @@ int xi_blocks_per_cu(int variant, int precision, int n_bins);
 
 struct DmatArgs {
   const ForestInfo* finfo;
+  const EtaInfo* einfo;    // per-forest eta sums (scales of the q vectors)
   const int32_t* sorted;
   const int32_t* nbr;      // second forest (sorted position) of each kept pair
   const int32_t* pair_p;   // first forest (sorted position) of each kept pair

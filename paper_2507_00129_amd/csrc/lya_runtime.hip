@@ -168,6 +168,7 @@ struct Prepared {
   DRec64* drec64 = nullptr;
   double* edges_par = nullptr;
   double* edges_perp = nullptr;
+  EtaInfo* einfo = nullptr;
   Globals host{};
 };
 
@@ -229,6 +230,7 @@ lya_status prepare(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
   HIP_TRY(hipMemcpyAsync(ctx->pinned, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   memcpy(&P.host, ctx->pinned, sizeof(Globals));
+  P.einfo = einfo;
   P.rec32 = a.rec32;
   P.rec64 = a.rec64;
   P.drec32 = a.drec32;
@@ -575,6 +577,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     LYA_TRY(wst(ctx, "dm_counter", 1, &counter));
     DmatArgs a{};
     a.finfo = P.finfo;
+    a.einfo = P.einfo;
     a.sorted = W.sorted;
     a.nbr = W.nbr;
     a.pair_p = W.pair_p;
