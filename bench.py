@@ -25,7 +25,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_ALU_OPS = 256 * 64 * 2.4e9          # one VALU op per lane per clock, non-packed
+PEAK_MFMA_F64 = 78.6e12                   # dense FP64 matrix peak (flop/s)
 PEAK_HBM = 8.0e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 WORKLOADS = {
     1: "eBOSS-like patch: 30k forests over 400 deg^2, log-lambda pixels (50-150 per forest), "
        "GRF + unit-noise deltas; xi and D on 50x50 bins to 200 Mpc/h",
@@ -36,19 +38,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_step(lib, dF, G, prec, keep, seed, stream):
-    xo = lib.xi(dF, G, precision=prec, timing=True, stream=stream)
+def run_step(lib, dF, G, prec, keep, seed, stream, xv, dv):
+    xo = lib.xi(dF, G, precision=prec, timing=True, stream=stream, variant=xv, autotune=False)
     sx = lib.last_stats()
-    do = lib.dmat(dF, G, precision=prec, timing=True, keep_fraction=keep, seed=seed, stream=stream)
+    do = lib.dmat(dF, G, precision=prec, timing=True, keep_fraction=keep, seed=seed, stream=stream,
+                  variant=dv, autotune=False)
     sd = lib.last_stats()
     return xo, do, sx, sd
 
 
-def time_form(lib, dF, G, prec, keep, seed, steps, warmup):
+def time_form(lib, dF, G, prec, keep, seed, steps, warmup, xv, dv):
     import torch
     stream = torch.cuda.current_stream()
     for w in range(warmup):
-        run_step(lib, dF, G, prec, keep, seed, stream)
+        run_step(lib, dF, G, prec, keep, seed, stream, xv, dv)
         torch.cuda.synchronize()
         log(f"[bench] {prec} warmup {w + 1}/{warmup} done")
     sx_all, sd_all = [], []
@@ -57,7 +60,7 @@ def time_form(lib, dF, G, prec, keep, seed, steps, warmup):
     t0 = time.perf_counter()
     ev0.record(stream)
     for k in range(steps):
-        xo, do, sx, sd = run_step(lib, dF, G, prec, keep, seed, stream)
+        xo, do, sx, sd = run_step(lib, dF, G, prec, keep, seed, stream, xv, dv)
         sx_all.append(sx)
         sd_all.append(sd)
     ev1.record(stream)
@@ -72,9 +75,53 @@ def mean(xs):
     return sum(xs) / max(1, len(xs))
 
 
-def cpu_baseline_and_sample_errors(lib, F, G, keep, seed, n_xi, n_d):
+def source_digest(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2507_00129_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from the hardware counters recorded in
+    profiles/traffic.json, or None when absent or taken on another version of
+    the kernel's source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_digest(source):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def xi_roofline(r):
+    ops = 6.0 * r["cand"] + 7.0 * r["xi_pairs"]
+    achieved = ops / (r["ms_xi_kernel"] / 1e3) / 1e12
+    return dict(kernel="xi_kernel<float>", bound="alu", achieved=achieved, peak=PEAK_ALU_OPS / 1e12,
+                unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12),
+                traffic=measured_traffic("xi_kernel", "k_xi.hip"),
+                work=f"6 ops x {r['cand']} candidate pairs + 7 ops x {r['xi_pairs']} in-grid pairs",
+                ms=r["ms_xi_kernel"])
+
+
+def d_roofline(r):
+    flops = 2.0 * r["d_fmas"]
+    achieved = flops / (r["ms_d_kernel"] / 1e3) / 1e12
+    return dict(kernel="dmat_kernel<float>", bound="mfma", achieved=achieved, peak=PEAK_MFMA_F64 / 1e12,
+                unit="TFLOP/s", frac=achieved / (PEAK_MFMA_F64 / 1e12),
+                traffic=measured_traffic("dmat_kernel", "k_dmat.hip"),
+                work=f"2 x {r['d_fmas']} FMAs of the sparse row outer products and the rank-4 pair term "
+                     f"(FP64 MFMA accumulation)",
+                ms=r["ms_d_kernel"])
+
+
+def cpu_baseline_and_sample_errors(lib, F, G, keep, seed, n_xi, n_d, xv, dv):
     """The FP64 oracle on a compact sub-patch (timed on one host thread), and the
-    GPU forms' errors against it on the same sample."""
+    GPU forms' errors against it on the same sample (run with the other kernel
+    variants, so the timed kernels' profiler averages cover full-size launches
+    only; every variant is parity-tested)."""
     import numpy as np
     import oracle
     from paper_2507_00129_amd import DeviceForests
@@ -100,10 +147,10 @@ def cpu_baseline_and_sample_errors(lib, F, G, keep, seed, n_xi, n_d):
     errs = {}
     dSx, dSd = DeviceForests.from_host(Sx), DeviceForests.from_host(Sd)
     for prec in ("fp32", "fp64"):
-        o = lib.xi(dSx, G, precision=prec)
+        o = lib.xi(dSx, G, precision=prec, variant=xv, autotune=False)
         xi = o["xi"].cpu().numpy()
         same = bool(np.array_equal(o["npairs"].cpu().numpy(), X.npairs))
-        d = lib.dmat(dSd, G, precision=prec, keep_fraction=keep, seed=seed)
+        d = lib.dmat(dSd, G, precision=prec, keep_fraction=keep, seed=seed, variant=dv, autotune=False)
         errs[prec] = dict(e_xi=oracle.err_xi(xi, X.xi, X.wsum, X.absnum),
                           e_W=oracle.err_rel(o["wsum"].cpu().numpy(), X.wsum),
                           e_D=oracle.err_rows(d["dmat"].cpu().numpy(), Dr.D),
@@ -119,7 +166,7 @@ def cpu_baseline_and_sample_errors(lib, F, G, keep, seed, n_xi, n_d):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--keep", type=float, default=1.0, help="distortion-matrix forest-pair keep fraction")
@@ -127,8 +174,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the full-size FP32-vs-FP64 comparison")
-    ap.add_argument("--cpu-xi-forests", type=int, default=150)
-    ap.add_argument("--cpu-d-forests", type=int, default=60)
+    ap.add_argument("--cpu-xi-forests", type=int, default=400)
+    ap.add_argument("--cpu-d-forests", type=int, default=120)
+    ap.add_argument("--xi-variant", type=int, default=3,
+                    help="xi kernel variant (3 = 512 threads with run-length sums, the autotuner's "
+                         "choice for this workload on MI355X)")
+    ap.add_argument("--d-variant", type=int, default=0,
+                    help="distortion kernel variant (0 = 8 waves, the autotuner's choice)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference for hardware traffic counters)")
@@ -163,7 +215,8 @@ def main():
     res = {}
     forms = ["fp32"] if args.no_fp64 else ["fp32", "fp64"]
     for prec in forms:
-        xo, do, sx, sd, wall = time_form(lib, dF, G, prec, args.keep, args.seed, args.steps, args.warmup)
+        xo, do, sx, sd, wall = time_form(lib, dF, G, prec, args.keep, args.seed, args.steps, args.warmup,
+                                         args.xi_variant, args.d_variant)
         xi_pairs = int(xo["npairs"].sum().item())
         d_pairs = int(mean([s["ingrid_pairs"] for s in sd]))
         res[prec] = dict(out_xi={k: v.cpu().numpy() for k, v in xo.items()},
@@ -184,21 +237,9 @@ def main():
             f"({d_pairs / max(r['ms_d_kernel'], 1e-9) * 1e3:.3e} pairs/s)")
 
     r32 = res["fp32"]
-    # dominant kernel and its roofline (algorithmic work / measured kernel time)
-    if r32["ms_xi_kernel"] >= r32["ms_d_kernel"]:
-        ops = 6.0 * r32["cand"] + 7.0 * r32["xi_pairs"]
-        achieved = ops / (r32["ms_xi_kernel"] / 1e3) / 1e12
-        roof = dict(kernel="xi_kernel<float>", bound="alu", achieved=achieved, peak=PEAK_ALU_OPS / 1e12,
-                    unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12), traffic=None,
-                    work=f"6 ops x {r32['cand']} candidate pairs + 7 ops x {r32['xi_pairs']} in-grid pairs",
-                    ms=r32["ms_xi_kernel"])
-    else:
-        ops = 2.0 * r32["d_fmas"] + 16.0 * r32["d_pairs"]
-        achieved = ops / (r32["ms_d_kernel"] / 1e3) / 1e12
-        roof = dict(kernel="dmat_kernel<float>", bound="alu", achieved=achieved, peak=PEAK_ALU_OPS / 1e12,
-                    unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12), traffic=None,
-                    work=f"2 x {r32['d_fmas']} outer-product FMAs + 16 ops x {r32['d_pairs']} in-grid pairs",
-                    ms=r32["ms_d_kernel"])
+    # dominant kernel and its roofline (algorithmic work / kernel time from HIP
+    # events recorded around the launch on its stream)
+    roof = xi_roofline(r32) if r32["ms_xi_kernel"] >= r32["ms_d_kernel"] else d_roofline(r32)
 
     line = dict(metric="pixel pairs/sec for xi + distortion matrix, FP32 vs FP64 at stated rel. error",
                 value=r32["value"], unit="pixel pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -209,6 +250,7 @@ def main():
                             xi_pairs=r32["xi_pairs"], d_pairs=r32["d_pairs"],
                             d_forest_pairs=r32["d_forest_pairs"], candidate_pairs=r32["cand"]),
                 roofline=roof)
+    line["roofline_xi"] = xi_roofline(r32)
     line["xi_pairs_per_s_kernel"] = r32["xi_pairs"] / (r32["ms_xi_kernel"] / 1e3)
     line["d_pairs_per_s_kernel"] = r32["d_pairs"] / max(r32["ms_d_kernel"] / 1e3, 1e-12)
     if "fp64" in res:
@@ -232,7 +274,9 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a compact sub-patch")
         base, errs = cpu_baseline_and_sample_errors(lib, F, G, args.keep, args.seed,
-                                                    args.cpu_xi_forests, args.cpu_d_forests)
+                                                    args.cpu_xi_forests, args.cpu_d_forests,
+                                                    0 if args.xi_variant != 0 else 1,
+                                                    1 if args.d_variant != 1 else 0)
         line["cpu_baseline"] = base
         line["vs_oracle_sample"] = errs
     print(json.dumps(line), flush=True)
