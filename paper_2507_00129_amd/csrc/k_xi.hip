@@ -21,8 +21,9 @@
 // binned by comparison with the FP64 edges, so the FP32 and FP64 forms bin
 // every pair identically.  Products are FP32 and are accumulated in FP64 in
 // LDS (ds_add_f64 is native on gfx950 and moves the same bytes as a hi/lo
-// pair of FP32 accumulators); with run-length accumulation, up to 32
-// consecutive products of the same bin are first summed in FP32 registers.
+// pair of FP32 accumulators); with run-length accumulation, consecutive
+// products of the same bin are first summed in FP32 registers (runs end at
+// every 32nd pixel of f, so a run holds at most 32 products).
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -85,8 +86,10 @@ template <typename T> struct RecOf;
 template <> struct RecOf<float> { using type = Rec32; };
 template <> struct RecOf<double> { using type = Rec64; };
 
+// LDS histograms: hNW[2 L] = sum w_i d_i w_j d_j, hNW[2 L + 1] = sum w_i w_j
+// (interleaved, so one address serves both), hn[L] = pair count.
 template <int BLOCK>
-__device__ void flush_hist(const XiArgs& a, double* hN, double* hW, unsigned* hn, int real) {
+__device__ void flush_hist(const XiArgs& a, double* hNW, unsigned* hn, int real) {
   const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
   const int64_t base = (int64_t)real * nb;
   for (int L = threadIdx.x; L < nb; L += BLOCK) {
@@ -94,12 +97,12 @@ __device__ void flush_hist(const XiArgs& a, double* hN, double* hW, unsigned* hn
     if (c) {
       const int kp = L % NP, kt = L / NP;
       const int64_t A = base + (int64_t)kp * NT + kt;
-      atomicAdd(&a.num[A], hN[L]);
-      atomicAdd(&a.wsum[A], hW[L]);
+      atomicAdd(&a.num[A], hNW[2 * L]);
+      atomicAdd(&a.wsum[A], hNW[2 * L + 1]);
       atomicAdd(&a.npairs[A], (unsigned long long)c);
     }
-    hN[L] = 0.0;
-    hW[L] = 0.0;
+    hNW[2 * L] = 0.0;
+    hNW[2 * L + 1] = 0.0;
     hn[L] = 0u;
   }
 }
@@ -112,14 +115,13 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   __shared__ int64_t s_item;
 
   const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
-  double* hN = smem;
-  double* hW = smem + nb;
+  double* hNW = smem;
   unsigned* hn = (unsigned*)(smem + 2 * nb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   for (int L = threadIdx.x; L < nb; L += BLOCK) {
-    hN[L] = 0.0;
-    hW[L] = 0.0;
+    hNW[2 * L] = 0.0;
+    hNW[2 * L + 1] = 0.0;
     hn[L] = 0u;
   }
 
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
 
     if (fi.real != cur_real || pending + (double)total * fi.npix > 4.0e9) {
       if (cur_real >= 0) {
-        flush_hist<BLOCK>(a, hN, hW, hn, cur_real);
+        flush_hist<BLOCK>(a, hNW, hn, cur_real);
         __syncthreads();
       }
       cur_real = fi.real;
@@ -220,68 +222,81 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         bt = (T)1e30;
       }
 
-      int curA = -1;
-      T accN = 0, accW = 0;
-      unsigned cnt = 0;
-
-      auto pair = [&](const Rec& ri, int i) {
+      // bin of the pair (pixel i of f, this lane's pixel), or -1
+      auto bin_of = [&](const Rec& ri, int i) -> int {
         const T ad = fabs(ri.d - dj);
         T xp;
         if constexpr (ZLO) xp = ad * cp; else xp = fma(ad, cp, mep);
         const T xt = fma(ri.d, st, bt);
-        const int A = K.bin_x(xp, xt, [&](double& rp64, double& rt64) {
+        return K.bin_x(xp, xt, [&](double& rp64, double& rt64) {
           double Di64;
           if constexpr (sizeof(T) == 4) Di64 = load_uniform(a.dist + fi.pix0 + i); else Di64 = ri.d;
           separations64(Di64, Dj64, c64, s64, rp64, rt64);
         });
-        if constexpr (RLE) {
-          // a run ends when the bin changes or after kRunMax pairs, which keeps
-          // the FP32 rounding of a run sum below kRunMax units in the last place;
-          // out-of-grid pairs form runs with A = -1 that are never added
-          if (A != curA || cnt == kRunMax) {
-            if (curA >= 0) {
-              atomicAdd(&hN[curA], (double)accN);
-              atomicAdd(&hW[curA], (double)accW);
-              atomicAdd(&hn[curA], cnt);
+      };
+      constexpr int NB = Batch<Rec>::N;
+
+      if constexpr (RLE) {
+        // runs of equal bins along f, ended at every kRunMax-th pixel of f (a run
+        // sum holds at most kRunMax FP32 products); out-of-grid pairs form runs
+        // with A = -1 that are never added
+        for (int c0 = 0; c0 < nf; c0 += (int)kRunMax) {
+          const int c1 = min(nf, c0 + (int)kRunMax);
+          int curA = -1, ist = c0;
+          T accN = 0, accW = 0;
+          auto pair = [&](const Rec& ri, int i) {
+            const int A = bin_of(ri, i);
+            if (A != curA) {
+              if (curA >= 0) {
+                atomicAdd(&hNW[2 * curA], (double)accN);
+                atomicAdd(&hNW[2 * curA + 1], (double)accW);
+                atomicAdd(&hn[curA], (unsigned)(i - ist));
+              }
+              curA = A;
+              accN = 0;
+              accW = 0;
+              ist = i;
             }
-            curA = A;
-            accN = 0;
-            accW = 0;
-            cnt = 0;
+            accN = fma(ri.wd, wdj, accN);
+            accW = fma(ri.w, wj, accW);
+          };
+          int i = c0;
+          for (; i + NB <= c1; i += NB) {
+            Batch<Rec> b;
+            b.load(rf + i);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) pair(b.r[u], i + u);
           }
-          accN = fma(ri.wd, wdj, accN);
-          accW = fma(ri.w, wj, accW);
-          ++cnt;
-        } else {
+          for (; i < c1; ++i) pair(load_uniform(rf + i), i);
+          if (curA >= 0) {
+            atomicAdd(&hNW[2 * curA], (double)accN);
+            atomicAdd(&hNW[2 * curA + 1], (double)accW);
+            atomicAdd(&hn[curA], (unsigned)(c1 - ist));
+          }
+        }
+      } else {
+        auto pair = [&](const Rec& ri, int i) {
+          const int A = bin_of(ri, i);
           if (A >= 0) {
-            atomicAdd(&hN[A], (double)(ri.wd * wdj));
-            atomicAdd(&hW[A], (double)(ri.w * wj));
+            atomicAdd(&hNW[2 * A], (double)(ri.wd * wdj));
+            atomicAdd(&hNW[2 * A + 1], (double)(ri.w * wj));
             atomicAdd(&hn[A], 1u);
           }
-        }
-      };
-
-      constexpr int NB = Batch<Rec>::N;
-      int i = 0;
-      for (; i + NB <= nf; i += NB) {
-        Batch<Rec> b;
-        b.load(rf + i);
+        };
+        int i = 0;
+        for (; i + NB <= nf; i += NB) {
+          Batch<Rec> b;
+          b.load(rf + i);
 #pragma unroll
-        for (int u = 0; u < NB; ++u) pair(b.r[u], i + u);
-      }
-      for (; i < nf; ++i) pair(load_uniform(rf + i), i);
-      if constexpr (RLE) {
-        if (curA >= 0) {
-          atomicAdd(&hN[curA], (double)accN);
-          atomicAdd(&hW[curA], (double)accW);
-          atomicAdd(&hn[curA], cnt);
+          for (int u = 0; u < NB; ++u) pair(b.r[u], i + u);
         }
+        for (; i < nf; ++i) pair(load_uniform(rf + i), i);
       }
     }
     __syncthreads();
   }
   __syncthreads();
-  if (cur_real >= 0) flush_hist<BLOCK>(a, hN, hW, hn, cur_real);
+  if (cur_real >= 0) flush_hist<BLOCK>(a, hNW, hn, cur_real);
 }
 
 struct Variant {

@@ -93,8 +93,9 @@ struct BinK {
       bool gp = fabs(xp - rxp) < taup;
       bool gt = fabs(xt - rxt) < taut;
       if constexpr (ZLO) {
+        // r_par = 0 is common (aligned pixel grids); r_perp ~ 0 needs coincident
+        // sky positions and is left to the exact path
         gp &= rxp != (T)0;
-        gt &= rxt != (T)0;
       } else {
         gp &= !(zlp & (rxp == (T)0));
         gt &= !(zlt & (rxt == (T)0));

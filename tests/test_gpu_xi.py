@@ -170,7 +170,7 @@ def test_single_bin_closed_form_at_scale(lib):
     # FP64 accumulator: rounding grows like sqrt(n) eps ~ 1e-12, hence 1e-10 here
     tol = {"fp64": 1e-10, "fp32": 1e-5}
     for prec in ("fp64", "fp32"):
-        for v in (0, 2):
+        for v in (0, 2, 3):
             out = run_xi(lib, F, G, precision=prec, variant=v, autotune=False)
             print(f"single-bin {prec} v{v}: n={int(out['npairs'][0, 0])} "
                   f"dN/A={abs(out['num'][0, 0] - N_exp) / A_exp:.2e} dW/W={abs(out['wsum'][0, 0] - W_exp) / W_exp:.2e}",
