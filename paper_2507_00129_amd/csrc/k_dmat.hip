@@ -107,6 +107,7 @@ struct DSmem {
   T Q[4][kTileW];
   double wdacc[kTileW];
   int32_t ox[kTileW], oy[kTileW];  // output bin index of each tile row / column
+  int32_t rng[4];                  // pixels of f, g within reach of the other forest: [lo, hi]
   int64_t item;
 };
 
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             int64_t pf, pg;
             int nf, ng;
             double s64, c64;
+            double fdmin, fdmax, gdmin, gdmax;
             {
               const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
               const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
@@ -228,7 +230,45 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
               pg = gi.pix0;
               nf = fi.npix;
               ng = gi.npix;
+              fdmin = fi.dmin;
+              fdmax = fi.dmax;
+              gdmin = gi.dmin;
+              gdmax = gi.dmax;
             }
+            // Only pixels within reach of the other forest's extent can pair in the
+            // grid: r_par = |D_i - D_j| c >= e_par_max once |D_i - D_j| >= reach (the
+            // margin covers the rounding of the FP64 separations).  The first and
+            // last such pixel of each forest bound the rows and lanes of the sweeps.
+            __syncthreads();  // the previous pair's ranges have been read
+            if (tid < 4) sm.rng[tid] = (tid & 1) ? -1 : 0x7fffffff;
+            __syncthreads();
+            {
+              const double reach = a.g.emax_par / c64 * (1.0 + 1e-12) + 1e-9;
+#pragma unroll
+              for (int side = 0; side < 2; ++side) {
+                const int n = side ? ng : nf;
+                const int64_t p0 = side ? pg : pf;
+                const double lo = (side ? fdmin : gdmin) - reach, hi = (side ? fdmax : gdmax) + reach;
+                for (int e0 = wave * 64; e0 < n; e0 += BLOCK) {
+                  const int e = e0 + lane;
+                  bool in = false;
+                  if (e < n) {
+                    double D;
+                    if constexpr (kF32) D = recs[p0 + e].D; else D = recs[p0 + e].d;
+                    in = D > lo && D < hi;
+                  }
+                  const uint64_t m = __ballot(in);
+                  if (m != 0ull && lane == 0) {
+                    atomicMin(&sm.rng[2 * side], e0 + __ffsll((long long)m) - 1);
+                    atomicMax(&sm.rng[2 * side + 1], e0 + 63 - __clzll((long long)m));
+                  }
+                }
+              }
+            }
+            __syncthreads();
+            const int f_lo = sm.rng[0], f_n = sm.rng[1] + 1 - sm.rng[0];
+            const int g_lo = sm.rng[2], g_n = sm.rng[3] + 1 - sm.rng[2];
+            if (f_n <= 0 || g_n <= 0) continue;  // no pixel pair of these forests is in the grid
             // G = R (1 / W, 1 / S) of the forest the lanes sweep (0 where the term is off)
             double gsc[2][2];
             {
@@ -257,8 +297,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             // which are staged in LDS S at a time
             auto sweep = [&](auto rs_tag) {
               constexpr int RS = decltype(rs_tag)::value;
-              const int nr = RS ? ng : nf, no = RS ? nf : ng;
-              const int64_t prow0 = RS ? pg : pf, poth0 = RS ? pf : pg;
+              const int nr = RS ? g_n : f_n, no = RS ? f_n : g_n;
+              const int64_t prow0 = RS ? pg + g_lo : pf + f_lo, poth0 = RS ? pf + f_lo : pg + g_lo;
               const int nchunk = (no + S - 1) / S;
               auto stage = [&](int c0) {
                 __syncthreads();
