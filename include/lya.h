@@ -110,7 +110,9 @@ typedef struct {
   int32_t timing;             /* record per-stage device times (see lya_stats) */
   int32_t variant;            /* >= 0 forces that kernel variant; -1 lets the
                                  autotuner (or the default) choose */
-  int32_t reserved;           /* must be 0 */
+  int32_t counters;           /* lya_dmat: count the work done (in-grid pairs,
+                                 outer-product FMAs, out-of-window pairs; see
+                                 lya_stats); adds a little work to the kernel */
   double dmat_keep_fraction;  /* lya_dmat: keep forest pair (f<g) iff
                                  splitmix64(seed ^ (f<<32 | g)) < floor(p * 2^64);
                                  p in (0, 1], p = 1 keeps all (Sec. 2.2: D on a
@@ -127,12 +129,12 @@ typedef struct {
   int32_t grid_blocks;        /* persistent workgroups launched */
   /* device milliseconds per stage, filled when options.timing != 0 */
   float ms_precompute, ms_worklist, ms_main, ms_finalize;
-  /* lya_dmat with options.timing != 0: pixel pairs inside the grid over the
+  /* lya_dmat with options.counters != 0: pixel pairs inside the grid over the
      kept forest pairs, and multiply-adds spent on the row outer products and
      on the H (x) Q term (the algorithmic work of the factorised form) */
   int64_t ingrid_pairs;
   int64_t outer_fmas;
-  /* lya_dmat with options.timing != 0: in-grid pixel pairs that fell outside
+  /* lya_dmat with options.counters != 0: in-grid pixel pairs that fell outside
      their forest pair's precomputed r_perp window (a consistency check: 0) */
   int64_t lost_pairs;
 } lya_stats;

@@ -382,7 +382,7 @@ void lya_options_default(lya_options* o) {
   o->validate = 1;
   o->timing = 0;
   o->variant = -1;
-  o->reserved = 0;
+  o->counters = 0;
   o->dmat_keep_fraction = 1.0;
   o->seed = 0;
 }
@@ -660,7 +660,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     ctx->stats.variant = variant;
     ctx->stats.grid_blocks = blocks;
     unsigned long long* wc = nullptr;
-    if (tm.on) {
+    if (o->counters) {
       LYA_TRY(wst(ctx, "dm_work_counters", 3, &wc));
       HIP_TRY(launch_zero(wc, 3 * sizeof(unsigned long long), st));
     }

@@ -50,7 +50,7 @@ class lya_options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32), ("eta", ctypes.c_int32), ("project_deltas", ctypes.c_int32),
         ("autotune", ctypes.c_int32), ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
-        ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("variant", ctypes.c_int32), ("counters", ctypes.c_int32),
         ("dmat_keep_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
@@ -189,7 +189,8 @@ class Library:
             pass
 
     def options(self, precision="fp32", eta="mean_slope", project_deltas=False, autotune=True,
-                validate=True, timing=False, keep_fraction=1.0, seed=0, variant=-1) -> lya_options:
+                validate=True, timing=False, keep_fraction=1.0, seed=0, variant=-1,
+                counters=False) -> lya_options:
         o = lya_options()
         self.lib.lya_options_default(ctypes.byref(o))
         o.precision = _PRECISION[precision]
@@ -198,6 +199,7 @@ class Library:
         o.autotune = int(bool(autotune))
         o.validate = int(bool(validate))
         o.timing = int(bool(timing))
+        o.counters = int(bool(counters))
         o.dmat_keep_fraction = float(keep_fraction)
         o.seed = int(seed)
         o.variant = int(variant)

@@ -30,7 +30,7 @@ def lib():
 def run_dmat(lib, F, G, **kw):
     from paper_2507_00129_amd import DeviceForests
     dF = DeviceForests.from_host(F, "cuda:0")
-    out = lib.dmat(dF, G, timing=True, **kw)
+    out = lib.dmat(dF, G, timing=True, counters=True, **kw)
     torch.cuda.synchronize()
     st = lib.last_stats()
     # every in-grid pixel pair must fall inside its forest pair's r_perp window
