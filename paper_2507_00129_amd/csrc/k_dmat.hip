@@ -27,12 +27,12 @@
 // only touches a few runs of bins, so each row records which blocks its R and G
 // reach (one ballot gives every wave's block bits), and a step is issued only
 // for the blocks that one of its two rows reaches on both sides; the work issued
-// stays close to the sparse row outer products.  The tile is 10 x 10 blocks;
-// the waves form a WX x WY grid and wave (wx, wy) owns block rows wx + WX i and
-// block columns wy + WY k, so its operand addresses are one per-wave base plus
-// compile-time offsets.  With 8 waves (2 per SIMD) a wave holds up to 15 FP64
-// blocks; with 4 waves (1 per SIMD, twice the registers) it holds 25 and sweeps
-// four rows per group, which gives the sweep more independent work.
+// stays close to the sparse row outer products.  The tile is 10 x 10 blocks
+// shared by 8 waves (2 per SIMD): wave (wx, wy) = (w & 1, w >> 1) owns block
+// rows wx + 2i (i < 5) in block columns wy and wy + 4, and three (wy < 2: rows
+// i < 3) or two (wy >= 2: rows i >= 3) blocks of column 8 + (wy & 1), i.e. 13
+// or 12 blocks per wave; operand addresses are per-wave bases plus
+// compile-time offsets.
 //
 // Within one forest, q = (u, b) = (w / W, w a / S) is p weighted per pixel and
 // scaled per forest, so the G histograms of a row are its R histograms times
@@ -67,15 +67,21 @@ __device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 constexpr int kTileW = 160;           // window bins per tile side
 constexpr int kBlk = 16;              // MFMA block side
 constexpr int kNBlk = kTileW / kBlk;  // 10 blocks per tile side
-// Wave grid of a workgroup of NW waves: WX x WY waves, BI block rows and BK
-// block columns per wave (slot j = BK i + k), RPW rows swept per wave per group.
-template <int NW> struct WaveGrid;
-template <> struct WaveGrid<8> {
-  static constexpr int WX = 2, WY = 4, BI = 5, BK = 3, RPW = 2;
-};
-template <> struct WaveGrid<4> {
-  static constexpr int WX = 2, WY = 2, BI = 5, BK = 5, RPW = 4;
-};
+constexpr int kNW = 8;    // waves per workgroup
+constexpr int kRPW = 2;   // rows swept per wave per group
+constexpr int kBI = 5;    // block rows per wave
+constexpr int kMB = 13;   // block slots per wave: j < 10 -> (row j / 2, column j % 2),
+                          // j >= 10 -> (row j - 10 or j - 7, third column)
+
+// Block of slot j of the wave (wx, wy): block row index i (operand A), column
+// index k (operand B: 0, 1 -> columns wy, wy + 4; 2 -> column 8 + (wy & 1)).
+__host__ __device__ constexpr int slot_i(int j, bool low) { return j < 10 ? j >> 1 : (low ? j - 10 : j - 7); }
+__host__ __device__ constexpr int slot_k(int j) { return j < 10 ? (j & 1) : 2; }
+__host__ __device__ inline int slot_bx(int wx, bool low, int j) { return wx + 2 * slot_i(j, low); }
+__host__ __device__ inline int slot_by(int wy, int j) {
+  return slot_k(j) == 0 ? wy : (slot_k(j) == 1 ? wy + 4 : 8 + (wy & 1));
+}
+__host__ __device__ constexpr bool slot_ok(int j, bool low) { return j < kMB && slot_i(j, low) < kBI; }
 
 template <int N> struct IC { static constexpr int value = N; };
 
@@ -92,7 +98,7 @@ template <> struct DCfg<double> {
 
 template <typename T, int NW>
 struct DSmem {
-  static constexpr int NR = NW * WaveGrid<NW>::RPW;  // rows per group
+  static constexpr int NR = NW * kRPW;  // rows per group
   static constexpr int S = DCfg<T>::kStage;
   T sd[S], sw[S], sa[S];  // staged pixels of the forest the lanes sweep
   // R^0, R^1 of each row of the group over the tile's x range, and over its y
@@ -134,19 +140,17 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   using Cfg = DCfg<T>;
   using Rec = typename Cfg::Rec;
   constexpr int NW = BLOCK / 64, S = Cfg::kStage, TW = kTileW;
-  using WG = WaveGrid<NW>;
-  constexpr int RPW = WG::RPW, NR = NW * RPW, WX = WG::WX, WY = WG::WY;
-  constexpr int kBI = WG::BI, kBK = WG::BK, kMB = kBI * kBK;
+  constexpr int RPW = kRPW, NR = NW * RPW;
   constexpr int BPW = 128 / NW, WPW = 64 / BPW;  // ballot bits per wave, waves per 64-bit word
   constexpr bool kF32 = sizeof(T) == 4;
-  static_assert(WX * WY == NW && kMB <= BPW && kMB < 32, "wave grid");
+  static_assert(NW == kNW && kMB <= BPW, "wave layout");
   static_assert(NR % 2 == 0, "two rows per MFMA step");
   __shared__ DSmem<T, NW> sm;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lk = lane >> 4, lm = lane & 15;  // MFMA operand coordinates: k, and row/column in the block
-  const int wx = wave % WX, wy = wave / WX;  // the wave's blocks: (wx + WX i, wy + WY k)
-  const bool lastcol = wy + WY * (kBK - 1) < kNBlk;  // the wave's last block column exists
+  const int wx = wave & 1, wy = wave >> 1;
+  const bool low = wy < 2;  // which block rows of the third column the wave owns
 
   BinK<T, ZLO> K;
   K.init(a.g, a.glob, a.edges_par, a.edges_perp);
@@ -159,8 +163,9 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int W = WPW * h + lane / BPW, j = lane % BPW;
-    const int bx = W % WX + WX * (j / kBK), by = W / WX + WY * (j % kBK);
-    const bool ok = j < kMB && bx < kNBlk && by < kNBlk;
+    const bool lw = (W >> 1) < 2;
+    const bool ok = slot_ok(j, lw);
+    const int bx = ok ? slot_bx(W & 1, lw, j) : 0, by = ok ? slot_by(W >> 1, j) : 0;
     bal_x[h] = ok ? bx : 31;
     bal_y[h] = ok ? by : 31;
   }
@@ -421,6 +426,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   const int slot_l = lk >> 1, comp = lk & 1;
                   const double* pa = &sm.rowR[slot_l][comp][wx * kBlk + lm];
                   const double* pb = diag ? &sm.rowR[slot_l][comp][wy * kBlk + lm] : &sm.rowG[slot_l][comp][wy * kBlk + lm];
+                  const int c3 = (8 + (wy & 1) - wy) * kBlk;  // third column, relative to pb
                   const double gs = gsc[1 - RS][comp];
 #pragma unroll 1
                   for (int st = 0; st < NR / 2; ++st) {
@@ -431,15 +437,18 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                     if (bits == 0u) continue;
                     const int so = 2 * st * 2 * TW;  // two rows further per step
                     const double wr = (double)sm.rw[2 * st + slot_l];
-                    double av[kBI], bv[kBK];
+                    double av[kBI], bv[3];
 #pragma unroll
-                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + WX * kBlk * i];
-#pragma unroll
-                    for (int k = 0; k < kBK; ++k) bv[k] = (k < kBK - 1 || lastcol) ? gs * pb[so + WY * kBlk * k] : 0.0;
+                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + 2 * kBlk * i];
+                    bv[0] = gs * pb[so];
+                    bv[1] = gs * pb[so + 4 * kBlk];
+                    bv[2] = gs * pb[so + c3];
 #pragma unroll
                     for (int j = 0; j < kMB; ++j)
-                      if ((bits >> j) & 1u)
-                        cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
+                      if ((bits >> j) & 1u) {
+                        const double aj = j < 10 ? av[j >> 1] : (low ? av[j - 10] : av[j - 7 < kBI ? j - 7 : kBI - 1]);
+                        cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj, bv[slot_k(j)], cacc[j], 0, 0, 0);
+                      }
                   }
                 }
                 if (RS == 0 && hq_on) {
@@ -510,17 +519,17 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             __syncthreads();
             // ---- H (x) Q: one more step; the Kronecker term on the diagonal; w_A
             {
-              double av[kBI], bv[kBK];
+              double av[kBI], bv[3];
 #pragma unroll
-              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + WX * i) * kBlk + lm];
+              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + 2 * i) * kBlk + lm];
 #pragma unroll
-              for (int k = 0; k < kBK; ++k)
-                bv[k] = (k < kBK - 1 || lastcol) ? (double)sm.Q[lk][(wy + WY * k) * kBlk + lm] : 0.0;
+              for (int k = 0; k < 3; ++k) bv[k] = (double)sm.Q[lk][slot_by(wy, k < 2 ? k : 10) * kBlk + lm];
 #pragma unroll
               for (int j = 0; j < kMB; ++j) {
-                const int bx = wx + WX * (j / kBK), by = wy + WY * (j % kBK);
-                if (bx < nbx && by < nby) {
-                  cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j / kBK], bv[j % kBK], cacc[j], 0, 0, 0);
+                const int bx = slot_bx(wx, low, j), by = slot_by(wy, j);
+                if (slot_ok(j, low) && bx < nbx && by < nby) {
+                  const double aj = j < 10 ? av[j >> 1] : (low ? av[j - 10] : av[j - 7 < kBI ? j - 7 : kBI - 1]);
+                  cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj, bv[slot_k(j)], cacc[j], 0, 0, 0);
                   if (a0 == b0 && bx == by) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
@@ -548,8 +557,8 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           // ---- add the wave's blocks to the global numerator (and w_A)
 #pragma unroll
           for (int j = 0; j < kMB; ++j) {
-            const int bx = wx + WX * (j / kBK), by = wy + WY * (j % kBK);
-            if (bx < nbx && by < nby) {
+            const int bx = slot_bx(wx, low, j), by = slot_by(wy, j);
+            if (slot_ok(j, low) && bx < nbx && by < nby) {
               const int oy = sm.oy[by * kBlk + lm];
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
@@ -607,8 +616,8 @@ __global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
   idx[q] = (int32_t)q;
 }
 
-constexpr int kNumVariants = 2;
-const char* const kNames[kNumVariants] = {"b512-mfma64", "b256-mfma64"};
+constexpr int kNumVariants = 1;
+const char* const kNames[kNumVariants] = {"b512-mfma64"};
 
 template <typename T, int BLOCK>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
@@ -647,14 +656,13 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  if (precision == LYA_FP64)
-    return variant == 0 ? launch_one<double, 512>(a, blocks, st) : launch_one<double, 256>(a, blocks, st);
-  return variant == 0 ? launch_one<float, 512>(a, blocks, st) : launch_one<float, 256>(a, blocks, st);
+  (void)variant;
+  return precision == LYA_FP64 ? launch_one<double, 512>(a, blocks, st) : launch_one<float, 512>(a, blocks, st);
 }
 
 int dmat_blocks_per_cu(int variant, int precision) {
-  if (precision == LYA_FP64) return variant == 0 ? occupancy<double, 512>() : occupancy<double, 256>();
-  return variant == 0 ? occupancy<float, 512>() : occupancy<float, 256>();
+  (void)variant;
+  return precision == LYA_FP64 ? occupancy<double, 512>() : occupancy<float, 512>();
 }
 
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st) {

@@ -57,7 +57,7 @@ def test_tiny_against_four_nested_sums(lib, prec, eta):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0])
 def test_config0(lib, prec, variant):
     F, G, _ = make_config(0, seed=0)
     ref = O.dmat(F, G, O.dmat_pairs(F, G))
@@ -109,7 +109,7 @@ def test_keep_fraction_subset(lib, prec):
 def test_ragged(lib, prec):
     F = _ragged_forests(7)
     ref = O.dmat(F, G60, O.dmat_pairs(F, G60))
-    for v in (0, 1):
+    for v in (0,):
         out = run_dmat(lib, F, G60, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"ragged-v{v}")
 
@@ -131,7 +131,7 @@ def test_config1_compact_subpatch(lib, prec):
     F, G, _ = make_config(1, seed=0, scale=0.02)
     S = subset_forests(F, nearest_to_centre(F, 60))
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
-    for v in (0, 1):
+    for v in (0,):
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"config1-sub-v{v}")
 
@@ -144,6 +144,6 @@ def test_windows_wider_than_one_tile(lib, prec):
     S = subset_forests(F, nearest_to_centre(F, 40))
     G = uniform_grid(100, 200.0, 12, 60.0)
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
-    for v in (0, 1):
+    for v in (0,):
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"wide-windows-v{v}")
