@@ -164,6 +164,30 @@ lya_status lya_xi(lya_context *ctx, const lya_forests *forests, const lya_grid *
                   const lya_options *opts, void *stream,
                   double *num, double *wsum, int64_t *npairs, double *xi);
 
+/* Pair sums split by subsample, for the subsampling covariance of xi (the
+   paper estimates the errors from subsamples of the forests in sky pixels,
+   Sec. 2.1 and the 3PCF figure).  subsample[f] in [0, n_sub) (device,
+   [n_forests], e.g. the sky pixel of forest f); each unordered pixel pair of
+   forests f, g is credited to the subsample of the one with the smaller input
+   index.  Outputs as lya_xi, each [n_realisations * n_sub * n_bins] row-major
+   (realisation, subsample, bin); summing over subsamples gives lya_xi's sums.
+   An id outside [0, n_sub) returns LYA_E_INVALID before anything is written
+   beyond the zeroed outputs. */
+lya_status lya_xi_subsamples(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                             const lya_options *opts, void *stream,
+                             const int32_t *subsample, int32_t n_sub,
+                             double *num, double *wsum, int64_t *npairs, double *xi);
+
+/* Subsample covariance of xi from one realisation's [n_sub * n_bins] sums
+   (device, as written by lya_xi_subsamples):
+     xi[A]     = N_A / W_A with N_A, W_A summed over subsamples (0 if W_A == 0)
+     cov[A][B] = sum_s W_sA W_sB (xi_sA - xi_A)(xi_sB - xi_B) / (W_A W_B)
+               = sum_s (N_sA - W_sA xi_A)(N_sB - W_sB xi_B) / (W_A W_B),
+   0 where W_A W_B == 0.  Outputs device, xi [n_bins], cov [n_bins * n_bins]. */
+lya_status lya_xi_covariance(lya_context *ctx, const double *num, const double *wsum,
+                             int64_t n_sub, int64_t n_bins, void *stream,
+                             double *xi, double *cov);
+
 /* Distortion matrix (Sec. 2.2, eq. distortion) over the forest pairs kept by
    options.dmat_keep_fraction / seed, with eta of options.eta.  Outputs,
    device:

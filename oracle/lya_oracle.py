@@ -308,15 +308,21 @@ def _chunks_by_pixels(F, g_list, budget):
 
 
 def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
-            edge_tau=1e-12, pairs=None, chunk_elems=2_000_000) -> XiSums:
+            edge_tau=1e-12, pairs=None, chunk_elems=2_000_000, sub=None, n_sub=1) -> XiSums:
     """Pair sums of eq. estimator_two for every realisation.
 
     For each forest f the pixels of all its partners g > f are concatenated
     and the n_f x sum(n_g) separations are binned at once; the per-forest
     partial histograms are combined with Neumaier summation so the result is
     accurate to a few ulps of sum |terms| per bin.
+
+    With `sub` (one subsample id in [0, n_sub) per forest) the sums are split
+    by subsample: every pair (f, g), f < g, goes to slab r * n_sub + sub[f]
+    (the errors of Sec. 2.1 and of the 3PCF figure come from subsamples of the
+    forests in sky pixels); the first axis of the outputs is then R * n_sub.
     """
-    R = max(1, int(F.n_realisations))
+    n_sub = int(n_sub) if sub is not None else 1
+    R = max(1, int(F.n_realisations)) * n_sub
     nb = grid.n_bins
     delta = projected_deltas(F, eta_mode) if project else F.delta
     wd = F.weight * delta
@@ -338,7 +344,7 @@ def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
     for f, a, b in zip(firsts, starts, ends):
         sl = F.forest_slice(int(f))
         nf = sl.stop - sl.start
-        r = int(real[f])
+        r = int(real[f]) * n_sub + (int(sub[f]) if sub is not None else 0)
         budget = max(1, chunk_elems // max(nf, 1))
         for gch in _chunks_by_pixels(F, pairs[a:b, 1], budget):
             idx, s, c = _partner_arrays(F, gch, n_vec, n_vec[f])
@@ -358,6 +364,25 @@ def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
             absn.add(np.bincount(Am, weights=np.abs(prod), minlength=nb), where=(r,))
             npairs[r] += np.bincount(Am, minlength=nb)
     return XiSums(num.value(), wsum.value(), npairs, absn.value(), n_near)
+
+
+def covariance(num, wsum):
+    """Subsample covariance of xi from [n_sub, n_bins] sums: with totals
+    N_A, W_A and xi_A = N_A / W_A (0 where W_A = 0),
+      C_AB = sum_s W_sA W_sB (xi_sA - xi_A)(xi_sB - xi_B) / (W_A W_B),
+    written as sum_s x_sA x_sB / (W_A W_B) with x_sA = N_sA - W_sA xi_A, and 0
+    where W_A W_B = 0.  The paper estimates its errors from subsamples of the
+    forests in sky pixels (Sec. 2.1, the 3PCF figure) without printing the
+    formula; this weighted form is the reading."""
+    num = np.asarray(num, np.float64)
+    wsum = np.asarray(wsum, np.float64)
+    N = num.sum(axis=0)
+    W = wsum.sum(axis=0)
+    xi = np.where(W != 0, N / np.where(W != 0, W, 1.0), 0.0)
+    x = num - wsum * xi[None, :]
+    d = np.outer(W, W)
+    cov = np.where(d != 0, (x.T @ x) / np.where(d != 0, d, 1.0), 0.0)
+    return xi, cov
 
 
 def xi_pairs_brute(F, grid, delta=None):

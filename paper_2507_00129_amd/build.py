@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "liblya.so")
-SOURCES = ["lya_runtime.hip", "k_precompute.hip", "k_worklist.hip", "k_xi.hip",
+SOURCES = ["lya_runtime.hip", "k_precompute.hip", "k_worklist.hip", "k_xi.hip", "k_cov.hip",
            "k_dmat.hip", "k_backward.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

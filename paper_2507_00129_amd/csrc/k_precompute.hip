@@ -11,6 +11,12 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 
+// Subsample ids must lie in [0, n_sub): they index output slabs.
+__global__ void validate_sub_kernel(const int32_t* sub, int64_t n, int32_t n_sub, Globals* glob) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < n && (sub[f] < 0 || sub[f] >= n_sub)) atomicOr(&glob->flag, kBadSub);
+}
+
 // One wave per forest.  Any violation sets a bit in glob->flag.
 __global__ __launch_bounds__(256) void validate_kernel(lya_forests F, Globals* glob) {
   const int lane = threadIdx.x & 63;
@@ -192,6 +198,14 @@ inline unsigned blocks_for(int64_t n_forests) {
 hipError_t launch_validate(const lya_forests* F, Globals* glob, hipStream_t st) {
   if (F->n_forests == 0) return hipSuccess;
   hipLaunchKernelGGL(validate_kernel, dim3(blocks_for(F->n_forests)), dim3(256), 0, st, *F, glob);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_sub(const int32_t* sub, int64_t n_forests, int32_t n_sub, Globals* glob,
+                               hipStream_t st) {
+  if (n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(validate_sub_kernel, dim3((unsigned)((n_forests + 255) / 256)), dim3(256), 0, st, sub,
+                     n_forests, n_sub, glob);
   return hipGetLastError();
 }
 

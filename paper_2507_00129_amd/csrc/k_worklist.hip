@@ -84,7 +84,8 @@ __global__ __launch_bounds__(256) void neighbours_kernel(WorklistArgs a) {
       if (q < hi && q != p) {
         const int g = a.sorted[q];
         const ForestInfo gi = a.finfo[g];
-        ok = gi.npix > 0 && pair_may_bin(fi, gi, a.eperp_max, a.epar_max) && keep_pair(a, f, g);
+        ok = gi.npix > 0 && (!a.own_by_index || g > f) && pair_may_bin(fi, gi, a.eperp_max, a.epar_max) &&
+             keep_pair(a, f, g);
         if (!kFill && ok) pix += (unsigned long long)gi.npix;
       }
       const uint64_t m = __ballot(ok);

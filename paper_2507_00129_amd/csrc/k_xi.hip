@@ -135,7 +135,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   const double invp = a.g.inv_par, invt = a.g.inv_perp, e0t = a.g.e0_perp;
   const T mep = (T)(-a.g.e0_par * a.g.inv_par);
 
-  int cur_real = -1;
+  int cur_key = -1;
   double pending = 0.0;  // upper bound on pairs added to any bin since the last flush
   __syncthreads();
 
@@ -174,12 +174,14 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     __syncthreads();
     const int total = tb.pref[nbc];
 
-    if (fi.real != cur_real || pending + (double)total * fi.npix > 4.0e9) {
-      if (cur_real >= 0) {
-        flush_hist<BLOCK>(a, hNW, hn, cur_real);
+    // output slab: the realisation, or realisation * n_sub + subsample of f
+    const int okey = a.sub ? fi.real * a.n_sub + a.sub[f] : fi.real;
+    if (okey != cur_key || pending + (double)total * fi.npix > 4.0e9) {
+      if (cur_key >= 0) {
+        flush_hist<BLOCK>(a, hNW, hn, cur_key);
         __syncthreads();
       }
-      cur_real = fi.real;
+      cur_key = okey;
       pending = 0.0;
     }
     pending += (double)total * fi.npix;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  if (cur_real >= 0) flush_hist<BLOCK>(a, hNW, hn, cur_real);
+  if (cur_key >= 0) flush_hist<BLOCK>(a, hNW, hn, cur_key);
 }
 
 struct Variant {

@@ -73,7 +73,8 @@ struct GridDev {
 
 // Validation error bits (Globals::flag).
 enum : int32_t {
-  kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32
+  kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32,
+  kBadSub = 64
 };
 
 // ---------------------------------------------------------------- geometry
@@ -155,6 +156,12 @@ struct PrecomputeArgs {
   double eperp_max, epar_max, e0_par, e0_perp, inv_par, inv_perp;
 };
 hipError_t launch_validate(const lya_forests* F, Globals* glob, hipStream_t st);
+// flag bit kBadSub when a subsample id lies outside [0, n_sub)
+hipError_t launch_validate_sub(const int32_t* sub, int64_t n_forests, int32_t n_sub, Globals* glob,
+                               hipStream_t st);
+// subsample covariance: totals N_A, W_A, xi_A and cov_AB from [n_sub][nb] sums
+hipError_t launch_covariance(const double* num, const double* wsum, int64_t n_sub, int64_t nb, double* x,
+                             double* tot_w, double* xi, double* cov, hipStream_t st);
 hipError_t launch_forest_stats(const PrecomputeArgs& a, hipStream_t st);
 hipError_t launch_globals(const PrecomputeArgs& a, hipStream_t st);
 hipError_t launch_pack(const PrecomputeArgs& a, hipStream_t st);
@@ -169,6 +176,7 @@ struct WorklistArgs {
   double strip_h;
   double eperp_max, epar_max;
   int symmetric;          // neighbours on both sides (backward)
+  int own_by_index;       // each unordered pair listed under the forest with the smaller input index
   int use_keep;           // distortion subset
   uint64_t keep_thr, seed;
   // outputs / scratch
@@ -216,6 +224,10 @@ struct XiArgs {
   double* num;
   double* wsum;
   unsigned long long* npairs;
+  // optional subsample of each forest (input index): a pair is added to the
+  // output slab realisation * n_sub + sub[f] of its owning forest f
+  const int32_t* sub;
+  int32_t n_sub;
 };
 int xi_num_variants();
 const char* xi_variant_name(int v);

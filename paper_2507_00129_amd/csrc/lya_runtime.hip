@@ -259,7 +259,7 @@ lya_status read_i64(lya_context* ctx, const int64_t* dev, int64_t* host, int cou
 lya_status build_worklist(lya_context* ctx, const lya_forests* F, const GridDev& gd,
                           const Prepared& P, hipStream_t st, bool symmetric, bool use_keep,
                           uint64_t keep_thr, uint64_t seed, bool want_pairs, int chunk,
-                          const char* tag, Worklist& W) {
+                          const char* tag, Worklist& W, bool own_by_index = false) {
   const int64_t N = F->n_forests;
   const int R = F->n_realisations;
   const double dmin = __builtin_bit_cast(double, P.host.dmin_bits);
@@ -282,7 +282,8 @@ lya_status build_worklist(lya_context* ctx, const lya_forests* F, const GridDev&
   a.strip_h = kPi / n_strips;
   a.eperp_max = gd.emax_perp;
   a.epar_max = gd.emax_par;
-  a.symmetric = symmetric;
+  a.symmetric = symmetric || own_by_index;
+  a.own_by_index = own_by_index;
   a.use_keep = use_keep;
   a.keep_thr = keep_thr;
   a.seed = seed;
@@ -436,17 +437,24 @@ lya_status lya_last_stats(const lya_context* ctx, lya_stats* out) {
   return LYA_OK;
 }
 
-lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
-                  void* stream, double* num, double* wsum, int64_t* npairs, double* xi) {
+namespace {
+
+// xi sums, optionally split by the subsample of each pair's owning forest
+// (sub != nullptr: outputs [R][n_sub][n_bins], each unordered pair owned by
+// the forest with the smaller input index).
+lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
+                   void* stream, const int32_t* sub, int32_t n_sub, double* num, double* wsum,
+                   int64_t* npairs, double* xi) {
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
   if (!num || !wsum || !npairs) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or npairs");
+  if (sub && n_sub < 1) return fail(ctx, LYA_E_INVALID, "n_sub must be >= 1");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ctx->err.clear();
   ctx->stats = lya_stats{};
   const int nb = gd.n_par * gd.n_perp;
-  const int64_t nout = (int64_t)F->n_realisations * nb;
+  const int64_t nout = (int64_t)F->n_realisations * (sub ? n_sub : 1) * nb;
   Timer tm{ctx, st, o->timing != 0};
   tm.at(0);
   HIP_TRY(launch_zero(num, nout * sizeof(double), st));
@@ -455,10 +463,16 @@ lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, con
   if (F->n_forests > 0 && F->n_pix > 0) {
     Prepared P;
     LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, o->project_deltas != 0, P));
+    if (sub) {
+      HIP_TRY(launch_validate_sub(sub, F->n_forests, n_sub, P.glob, st));
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (*(int32_t*)ctx->pinned & kBadSub) return fail(ctx, LYA_E_INVALID, "subsample id outside [0, n_sub)");
+    }
     tm.at(1);
     Worklist W;
     const int chunk = xi_chunk(F, 4096);
-    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, false, 0, 0, false, chunk, "xi", W));
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, false, 0, 0, false, chunk, "xi", W, sub != nullptr));
     tm.at(2);
     ctx->stats.forest_pairs = W.n_pairs;
     ctx->stats.work_items = W.n_items;
@@ -482,6 +496,8 @@ lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, con
     a.num = num;
     a.wsum = wsum;
     a.npairs = (unsigned long long*)npairs;
+    a.sub = sub;
+    a.n_sub = sub ? n_sub : 1;
 
     // autotune: time each variant on a prefix of the work list, into scratch outputs
     char key[128];
@@ -544,6 +560,38 @@ lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, con
   HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
   tm.at(5);
   return tm.finish(ctx);
+}
+
+}  // namespace
+
+lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
+                  void* stream, double* num, double* wsum, int64_t* npairs, double* xi) {
+  return xi_impl(ctx, F, G, o, stream, nullptr, 1, num, wsum, npairs, xi);
+}
+
+lya_status lya_xi_subsamples(lya_context* ctx, const lya_forests* F, const lya_grid* G,
+                             const lya_options* o, void* stream, const int32_t* subsample, int32_t n_sub,
+                             double* num, double* wsum, int64_t* npairs, double* xi) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!subsample) return fail(ctx, LYA_E_INVALID, "NULL subsample");
+  return xi_impl(ctx, F, G, o, stream, subsample, n_sub, num, wsum, npairs, xi);
+}
+
+lya_status lya_xi_covariance(lya_context* ctx, const double* num, const double* wsum, int64_t n_sub,
+                             int64_t n_bins, void* stream, double* xi, double* cov) {
+  if (!ctx) return LYA_E_INVALID;
+  ctx->err.clear();
+  if (!num || !wsum || !xi || !cov) return fail(ctx, LYA_E_INVALID, "NULL num, wsum, xi or cov");
+  if (n_sub < 1 || n_bins < 1 || n_bins > kMaxBins)
+    return fail(ctx, LYA_E_INVALID, "n_sub must be >= 1 and n_bins in [1, %d]", kMaxBins);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  double* x;
+  double* tw;
+  LYA_TRY(wst(ctx, "cov_x", (size_t)(n_sub * n_bins), &x));
+  LYA_TRY(wst(ctx, "cov_w", (size_t)n_bins, &tw));
+  HIP_TRY(launch_covariance(num, wsum, n_sub, n_bins, x, tw, xi, cov, st));
+  return LYA_OK;
 }
 
 lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,

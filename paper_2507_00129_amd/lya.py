@@ -95,6 +95,10 @@ def load_library(path: str = LIB_PATH):
     lib.lya_dmat.restype = I32
     lib.lya_xi_backward.argtypes = [P, FP, GP, OP, P, P, P, P, P, P]
     lib.lya_xi_backward.restype = I32
+    lib.lya_xi_subsamples.argtypes = [P, FP, GP, OP, P, P, I32, P, P, P, P]
+    lib.lya_xi_subsamples.restype = I32
+    lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
+    lib.lya_xi_covariance.restype = I32
     _lib = lib
     return lib
 
@@ -236,6 +240,42 @@ class Library:
                                     self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
                                     _ptr(out["npairs"]), _ptr(out.get("xi"))))
         return out
+
+    def xi_subsamples(self, forests: DeviceForests, grid, subsample, n_sub, stream=None, out=None, **opts):
+        """Pair sums split by the subsample of each pair's owning forest (the one
+        with the smaller input index); returns dict of [R, n_sub, n_bins] tensors.
+        `subsample` is an int32 device tensor [n_forests] with ids in [0, n_sub)."""
+        import torch
+        g = HostGrid(grid)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        sub = subsample.to(device=dev, dtype=torch.int32).contiguous()
+        if sub.numel() != forests.n_forests:
+            raise ValueError("subsample must have one entry per forest")
+        shape = (R, int(n_sub), g.n_bins)
+        if out is None:
+            out = dict(num=torch.empty(shape, dtype=torch.float64, device=dev),
+                       wsum=torch.empty(shape, dtype=torch.float64, device=dev),
+                       npairs=torch.empty(shape, dtype=torch.int64, device=dev),
+                       xi=torch.empty(shape, dtype=torch.float64, device=dev))
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi_subsamples(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                               self._stream(stream), _ptr(sub), int(n_sub), _ptr(out["num"]),
+                                               _ptr(out["wsum"]), _ptr(out["npairs"]), _ptr(out.get("xi"))))
+        return out
+
+    def xi_covariance(self, num, wsum, stream=None):
+        """Subsample covariance of xi from one realisation's [n_sub, n_bins] sums;
+        returns (xi [n_bins], cov [n_bins, n_bins])."""
+        import torch
+        num = num.contiguous().to(torch.float64)
+        wsum = wsum.contiguous().to(torch.float64)
+        n_sub, nb = int(num.shape[0]), int(num.shape[1])
+        xi = torch.empty(nb, dtype=torch.float64, device=num.device)
+        cov = torch.empty((nb, nb), dtype=torch.float64, device=num.device)
+        self._check(self.lib.lya_xi_covariance(self.ctx, _ptr(num), _ptr(wsum), n_sub, nb, self._stream(stream),
+                                               _ptr(xi), _ptr(cov)))
+        return xi, cov
 
     def dmat(self, forests: DeviceForests, grid, stream=None, out=None, **opts):
         """Distortion matrix; returns dict(dmat [R, nb, nb], wsum_d [R, nb])."""

@@ -11,6 +11,7 @@ from .survey import (  # noqa: F401
     comoving_distance,
     concat_realisations,
     make_patch,
+    sky_cells,
     subset_forests,
     uniform_grid,
 )

@@ -194,7 +194,7 @@ def _grf_sample(rng, pos, sigma2, R, cell):
     k2 = (kx[:, None, None] ** 2 + ky[None, :, None] ** 2 + kz[None, None, :] ** 2).astype(np.float32)
     fk *= np.exp(-0.5 * k2 * R * R)
     del k2
-    field = np.fft.irfftn(fk, s=shape).astype(np.float32)
+    field = np.fft.irfftn(fk, s=shape, axes=(0, 1, 2)).astype(np.float32)
     del fk
     field *= np.float32(np.sqrt(sigma2) / max(field.std(), 1e-30))
     u = (pos - lo) / cell
@@ -231,6 +231,18 @@ def nearest_to_centre(F: Forests, k: int) -> np.ndarray:
     m = v.mean(0)
     m /= np.linalg.norm(m)
     return np.sort(np.argsort(-(v @ m), kind="stable")[:k])
+
+
+def sky_cells(F: Forests, n_ra: int, n_dec: int) -> np.ndarray:
+    """Subsample id of each forest: an n_ra x n_dec grid of equal-area cells
+    (uniform in RA and in sin(Dec)) over the patch's extent, a stand-in for
+    the sky pixels the paper subsamples in.  int32 in [0, n_ra * n_dec)."""
+    ra, sd = F.ra, np.sin(F.dec)
+    def idx(v, n):
+        lo, hi = float(v.min()), float(v.max())
+        k = np.floor((v - lo) / max(hi - lo, 1e-300) * n).astype(np.int64)
+        return np.clip(k, 0, n - 1)
+    return (idx(ra, n_ra) * n_dec + idx(sd, n_dec)).astype(np.int32)
 
 
 def concat_realisations(parts: List[Forests]) -> Forests:

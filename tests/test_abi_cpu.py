@@ -23,7 +23,8 @@ def test_header_symbols_exported():
         pytest.skip("library not built")
     lib = ctypes.CDLL(L.LIB_PATH)
     names = _declared_functions()
-    assert {"lya_create", "lya_xi", "lya_dmat", "lya_xi_backward", "lya_last_error"} <= set(names)
+    assert {"lya_create", "lya_xi", "lya_dmat", "lya_xi_backward", "lya_last_error",
+            "lya_xi_subsamples", "lya_xi_covariance"} <= set(names)
     for n in names:
         assert hasattr(lib, n), f"{n} declared in lya.h but not exported"
 
@@ -46,5 +47,8 @@ def test_defaults_and_null_arguments():
     assert lib.lya_xi(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_dmat(None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_backward(None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_xi_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_xi_covariance(None, None, None, 1, 1, None, None, None) == L.LYA_E_INVALID
+    assert o.counters == 0
     assert lib.lya_create(None, 0) == L.LYA_E_INVALID
     assert lib.lya_last_error(None) == b"NULL context"

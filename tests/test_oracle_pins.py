@@ -420,3 +420,57 @@ def test_gradient_finite_differences_and_euler():
     xi = X.xi[0]
     assert np.dot(F.delta, gd) == pytest.approx(4.0 * np.sum(xi * (xi - target)), rel=1e-9)
     assert abs(np.dot(F.weight, gw)) < 1e-9 * np.dot(np.abs(F.weight), np.abs(gw))
+
+
+# ---------------------------------------------------------------- subsamples
+G_TINY = uniform_grid(12, 60.0)
+
+
+def test_subsample_sums_partition_the_pairs():
+    """Keying the sums by subsample splits every pair into exactly one slab:
+    the slabs add up to the unsplit sums (counts exactly)."""
+    from synth import sky_cells
+    F = tiny(3, n_forests=9, k=7, width_deg=1.0)
+    sub = sky_cells(F, 2, 2)
+    assert len(np.unique(sub)) > 1
+    whole = O.xi_sums(F, G_TINY)
+    split = O.xi_sums(F, G_TINY, sub=sub, n_sub=4)
+    assert split.npairs.shape == (4, G_TINY.n_bins)
+    np.testing.assert_array_equal(split.npairs.sum(0), whole.npairs[0])
+    np.testing.assert_allclose(split.num.sum(0), whole.num[0], rtol=0, atol=1e-13 * whole.absnum.max())
+    np.testing.assert_allclose(split.wsum.sum(0), whole.wsum[0], rtol=1e-13)
+
+
+def test_subsample_owner_is_smaller_index():
+    """A pair is credited to the subsample of the forest with the smaller input
+    index: with all forests but forest 0 in subsample 1, slab 0 holds exactly
+    forest 0's pairs."""
+    F = tiny(4, n_forests=5, k=6)
+    sub = np.ones(F.n_forests, np.int32)
+    sub[0] = 0
+    split = O.xi_sums(F, G_TINY, sub=sub, n_sub=2)
+    only0 = O.xi_sums(F, G_TINY, pairs=np.array([[0, g] for g in range(1, F.n_forests)]))
+    np.testing.assert_array_equal(split.npairs[0], only0.npairs[0])
+
+
+def test_covariance_hand_worked():
+    d = load_json("covariance_two_subsamples.json")
+    xi, cov = O.covariance(d["num"], d["wsum"])
+    np.testing.assert_allclose(xi, d["xi"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(cov, d["cov"], rtol=0, atol=1e-15)
+
+
+def test_covariance_properties():
+    rng = np.random.default_rng(5)
+    num = rng.normal(size=(12, 7))
+    wsum = rng.uniform(0.5, 2.0, size=(12, 7))
+    wsum[:, 3] = 0.0          # an empty bin
+    num[:, 3] = 0.0
+    xi, cov = O.covariance(num, wsum)
+    assert np.all(cov[3] == 0) and np.all(cov[:, 3] == 0) and xi[3] == 0
+    np.testing.assert_allclose(cov, cov.T, rtol=0, atol=1e-15)
+    assert np.linalg.eigvalsh(cov).min() > -1e-12          # positive semi-definite
+    _, cov2 = O.covariance(3.0 * num, wsum)
+    np.testing.assert_allclose(cov2, 9.0 * cov, rtol=1e-12, atol=0)   # quadratic in N
+    _, cov1 = O.covariance(num[:1], wsum[:1])
+    assert np.abs(cov1).max() < 1e-28                         # one subsample: no scatter (rounding only)
