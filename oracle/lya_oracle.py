@@ -671,6 +671,66 @@ def xi_grad(F, grid, grad_xi, xi, wsum, pairs=None, prune=True):
     return gd, gw
 
 
+def projection_jacobians(delta, w, loglam, mode=MEAN_SLOPE):
+    """Jacobians of one forest's projected deltas delta' = eta(w, Lambda) delta
+    (Sec. 2.2, the eta definition) with respect to delta and to w.
+
+    J_delta = eta.  J_w[i, k] = sum_i' (d eta_ii' / d w_k) delta_i', each
+    entry of eta differentiated as written, with every w-dependent quantity
+    moving: W = sum w, Lambda_bar = sum w Lambda / W (so a_i moves by
+    -a_k / W), S = sum w a^2.  Identity mode, W = 0 and a dropped slope term
+    follow the same readings as the forward projection (the branch in use is
+    differentiated).
+    """
+    delta = np.asarray(delta, np.float64)
+    w = np.asarray(w, np.float64)
+    L = np.asarray(loglam, np.float64)
+    n = delta.shape[0]
+    P = eta_params(w, L, mode)
+    if mode == IDENTITY or n == 0 or P.W == 0.0:
+        return np.eye(n), np.zeros((n, n))
+    W, a, S = P.W, P.a, P.S
+    da = -a[None, :] / W                          # da_i / dw_k (same for every i)
+    dS = a * a + 2.0 * np.sum(w * a) * da[0]      # dS / dw_k = a_k^2 + sum_l 2 w_l a_l da_l/dw_k
+    # mean term: eta_ii' contains -w_i' / W
+    #   d/dw_k (-w_i' / W) = -[i' = k] / W + w_i' / W^2
+    Jw = -np.ones((n, 1)) * delta[None, :] / W + np.sum(w * delta) / (W * W)
+    if P.slope:
+        # slope term: eta_ii' contains -a_i w_i' a_i' / S
+        wad = np.sum(w * a * delta)               # sum_i' w_i' a_i' delta_i'
+        wd = np.sum(w * delta)
+        for k in range(n):
+            d_term = (da[0, k] * wad                        # d a_i
+                      + a * a[k] * delta[k]                 # d w_i' at i' = k
+                      + a * da[0, k] * wd                   # d a_i'
+                      ) / S - a * wad * dS[k] / (S * S)     # d S
+            Jw[:, k] -= d_term
+    return eta_matrix(w, L, mode), Jw
+
+
+def xi_grad_projected(F, grid, grad_xi, xi, wsum, eta_mode=MEAN_SLOPE, pairs=None, prune=True):
+    """Gradient of L(xi) with respect to the raw delta and w when xi is built
+    from the projected deltas delta' = eta delta of each forest (the forward
+    of ``xi_sums(..., project=True)``).
+
+    The chain rule with explicit per-forest Jacobians: with g' = dL/d delta'
+    and h' = dL/dw at fixed delta' (``xi_grad`` on the projected deltas),
+      dL/d delta = J_delta^T g',   dL/dw = h' + J_w^T g'.
+    xi and wsum are those of the projected forward.
+    """
+    Fp = F.copy()
+    Fp.delta = projected_deltas(F, eta_mode)
+    gp, hp = xi_grad(Fp, grid, grad_xi, xi, wsum, pairs=pairs, prune=prune)
+    gd = np.zeros(F.n_pix)
+    gw = hp.copy()
+    for f in range(F.n_forests):
+        sl = F.forest_slice(f)
+        Jd, Jw = projection_jacobians(F.delta[sl], F.weight[sl], F.loglam[sl], eta_mode)
+        gd[sl] = Jd.T @ gp[sl]
+        gw[sl] += Jw.T @ gp[sl]
+    return gd, gw
+
+
 def loss(xi, target):
     """L = sum_A (xi_A - m_A)^2."""
     d = np.asarray(xi, np.float64).ravel() - np.asarray(target, np.float64).ravel()

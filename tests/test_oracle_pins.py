@@ -422,6 +422,79 @@ def test_gradient_finite_differences_and_euler():
     assert abs(np.dot(F.weight, gw)) < 1e-9 * np.dot(np.abs(F.weight), np.abs(gw))
 
 
+def _loss_proj(F, G, target, mode):
+    X = O.xi_sums(F, G, project=True, eta_mode=mode)
+    return O.loss(X.xi, target), X
+
+
+@pytest.mark.parametrize("mode", [O.MEAN, O.MEAN_SLOPE])
+def test_projected_gradient_finite_differences(mode):
+    """Gradient through the projection delta' = eta(w, Lambda) delta (Sec. 2.2)
+    against central differences of the projected forward: exact up to
+    rounding in delta (L stays quadratic in delta), O(eps^2) in w (eta moves
+    with w through W, Lambda_bar and S)."""
+    F = make_patch(12, 1.0, 23, z_range=(2.1, 2.3))
+    G = G60
+    rng = np.random.default_rng(5)
+    target = rng.uniform(-0.01, 0.01, G.n_bins)
+    L0, X = _loss_proj(F, G, target, mode)
+    gxi = O.loss_grad_xi(X.xi, target[None, :])
+    gd, gw = O.xi_grad_projected(F, G, gxi, X.xi, X.wsum, eta_mode=mode)
+    for i in rng.choice(F.n_pix, 10, replace=False):
+        for eps in (0.5, 1e-3):
+            Fp, Fm = F.copy(), F.copy()
+            Fp.delta[i] += eps
+            Fm.delta[i] -= eps
+            fd = (_loss_proj(Fp, G, target, mode)[0] - _loss_proj(Fm, G, target, mode)[0]) / (2 * eps)
+            assert fd == pytest.approx(gd[i], rel=1e-6, abs=1e-9 * np.abs(gd).max())
+    for i in rng.choice(F.n_pix, 10, replace=False):
+        eps = 1e-3
+        Fp, Fm = F.copy(), F.copy()
+        Fp.weight[i] += eps
+        Fm.weight[i] -= eps
+        fd = (_loss_proj(Fp, G, target, mode)[0] - _loss_proj(Fm, G, target, mode)[0]) / (2 * eps)
+        assert fd == pytest.approx(gw[i], rel=1e-4, abs=1e-6 * np.abs(gw).max())
+
+
+@pytest.mark.parametrize("mode", [O.MEAN, O.MEAN_SLOPE])
+def test_projected_gradient_invariances(mode):
+    """delta -> delta + c (and + c Lambda with the slope term) per forest leaves
+    delta' unchanged, so the delta-gradient sums to zero over each forest
+    (and against Lambda); xi is homogeneous of degree 2 in delta and 0 in w,
+    also through eta (Euler identities)."""
+    F = make_patch(15, 1.2, 31, z_range=(2.1, 2.4))
+    G = G60
+    rng = np.random.default_rng(8)
+    target = rng.uniform(-0.01, 0.01, G.n_bins)
+    _, X = _loss_proj(F, G, target, mode)
+    gxi = O.loss_grad_xi(X.xi, target[None, :])
+    gd, gw = O.xi_grad_projected(F, G, gxi, X.xi, X.wsum, eta_mode=mode)
+    scale = np.abs(gd).max() * 200
+    for f in range(F.n_forests):
+        sl = F.forest_slice(f)
+        assert abs(np.sum(gd[sl])) <= 1e-12 * scale
+        if mode == O.MEAN_SLOPE:
+            lc = F.loglam[sl] - F.loglam[sl].mean()
+            assert abs(np.dot(lc, gd[sl])) <= 1e-12 * scale
+    xi = X.xi[0]
+    assert np.dot(F.delta, gd) == pytest.approx(4.0 * np.sum(xi * (xi - target)), rel=1e-9)
+    assert abs(np.dot(F.weight, gw)) < 1e-9 * np.dot(np.abs(F.weight), np.abs(gw))
+    # without the projection term the delta-gradient is not orthogonal to 1
+    gp, _ = O.xi_grad(F, G, gxi, X.xi, X.wsum)
+    assert max(abs(np.sum(gp[F.forest_slice(f)])) for f in range(F.n_forests)) > 1e-6 * scale
+
+
+def test_projected_gradient_identity_mode_is_plain():
+    F = make_patch(10, 1.0, 41, z_range=(2.1, 2.3))
+    rng = np.random.default_rng(2)
+    X = O.xi_sums(F, G60)
+    gxi = rng.normal(size=(1, G60.n_bins))
+    a = O.xi_grad(F, G60, gxi, X.xi, X.wsum)
+    b = O.xi_grad_projected(F, G60, gxi, X.xi, X.wsum, eta_mode=O.IDENTITY)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
 # ---------------------------------------------------------------- subsamples
 G_TINY = uniform_grid(12, 60.0)
 
