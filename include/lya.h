@@ -198,14 +198,22 @@ lya_status lya_dmat(lya_context *ctx, const lya_forests *forests, const lya_grid
                     const lya_options *opts, void *stream,
                     double *dmat, double *wsum_d);
 
-/* Gradient of a scalar L(xi) with respect to delta and w (deltas taken as
-   given: project_deltas must be 0).  Inputs grad_xi = dL/dxi, xi and wsum
-   as produced by lya_xi, each [n_realisations * n_bins], device.  Outputs
-   [n_pix], device:
+/* Gradient of a scalar L(xi) with respect to delta and w.  Inputs
+   grad_xi = dL/dxi, xi and wsum as produced by lya_xi with the same options,
+   each [n_realisations * n_bins], device.  Outputs [n_pix], device.
+   Without project_deltas:
      grad_delta[i]  = w_i sum_j gamma_{A(i,j)} w_j delta_j
      grad_weight[i] = sum_j gamma_{A(i,j)} w_j (delta_i delta_j - xi_{A(i,j)})
    with gamma_A = grad_xi[A] / wsum[A] (0 where wsum[A] == 0) and j over every
-   pixel of every other forest of the same realisation. */
+   pixel of every other forest of the same realisation.
+   With project_deltas (xi built from delta' = eta delta, eta of options.eta,
+   Sec. 2.2): the same sums with delta' give g' = dL/d delta' and h' = dL/dw
+   at fixed delta'; eta depends on w through W, the weighted mean of Lambda
+   and S, and the chain rule through it gives, per forest,
+     grad_delta[k]  = g'_k - w_k c_k,   grad_weight[k] = h'_k - delta'_k c_k,
+     c_k = sum_i g'_i / W + (L_k - Lbar) sum_i (L_i - Lbar) g'_i / S
+   (the slope part only where the slope term is in use; c = 0 where eta = I).
+   These are gradients with respect to the raw delta and w. */
 lya_status lya_xi_backward(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
                            const lya_options *opts, void *stream,
                            const double *grad_xi, const double *xi, const double *wsum,

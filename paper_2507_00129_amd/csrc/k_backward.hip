@@ -166,6 +166,41 @@ __global__ void gamma_kernel(const double* grad_xi, const double* xi, const doub
   out[idx] = make_double2(g, g * xi[A]);
 }
 
+// Adjoint of the per-forest projection delta' = eta delta (Sec. 2.2) applied
+// to the gradient.  eta moves with w through W, the weighted mean of Lambda
+// and S; differentiating delta'_i = delta_i - m - a_i t (m = sum w delta / W,
+// t = sum w a delta / S, a = Lambda - Lambda_bar) and collapsing the sums
+// gives, with g'_k = dL/d delta'_k and h'_k = dL/dw_k at fixed delta':
+//   c_k = G0 / W + a_k G1 / S,  G0 = sum_i g'_i,  G1 = sum_i a_i g'_i,
+//   dL/d delta_k = g'_k - w_k c_k,   dL/dw_k = h'_k - delta'_k c_k.
+// The slope part is used only where the forward used the slope term, and
+// c = 0 where eta = I (identity mode, or a forest with W = 0).  One wave per
+// forest, FP64, in place.
+__global__ __launch_bounds__(256) void project_adjoint_kernel(lya_forests F, const EtaInfo* einfo,
+                                                              const double* delta_proj,
+                                                              double* grad_delta, double* grad_weight) {
+  const int lane = threadIdx.x & 63;
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (f >= F.n_forests) return;
+  const EtaInfo e = einfo[f];
+  if (!e.active) return;
+  const int64_t p0 = F.offsets[f], p1 = F.offsets[f + 1];
+  double g0 = 0.0, g1 = 0.0;
+  for (int64_t k = p0 + lane; k < p1; k += 64) {
+    const double g = grad_delta[k];
+    g0 += g;
+    g1 += (F.loglam[k] - e.lbar) * g;
+  }
+  g0 = wave_sum(g0);
+  g1 = wave_sum(g1);
+  const double c0 = g0 / e.W, c1 = e.slope ? g1 / e.S : 0.0;
+  for (int64_t k = p0 + lane; k < p1; k += 64) {
+    const double c = c0 + (F.loglam[k] - e.lbar) * c1;
+    grad_delta[k] -= F.weight[k] * c;
+    grad_weight[k] -= delta_proj[k] * c;
+  }
+}
+
 template <typename T, int BLOCK>
 hipError_t launch_one(const BwdArgs& a, int blocks, hipStream_t st) {
   const size_t smem = 2 * kGroup * sizeof(double) + (size_t)a.g.n_par * a.g.n_perp * 2 * sizeof(T);
@@ -193,6 +228,15 @@ hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* w
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(gamma_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, grad_xi, xi, wsum,
                      out, n, NP, NT);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_adjoint(const lya_forests* F, const EtaInfo* einfo, const double* delta_proj,
+                                  double* grad_delta, double* grad_weight, hipStream_t st) {
+  if (F->n_forests == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((F->n_forests + 3) / 4);
+  hipLaunchKernelGGL(project_adjoint_kernel, dim3(blocks), dim3(256), 0, st, *F, einfo, delta_proj,
+                     grad_delta, grad_weight);
   return hipGetLastError();
 }
 

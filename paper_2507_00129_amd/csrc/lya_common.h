@@ -292,6 +292,8 @@ struct BwdArgs {
 hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* wsum, double2* out,
                         int64_t n, int NP, int NT, hipStream_t st);
 hipError_t launch_xi_bwd(int precision, const BwdArgs& a, int blocks, hipStream_t st);
+hipError_t launch_project_adjoint(const lya_forests* F, const EtaInfo* einfo, const double* delta_proj,
+                                  double* grad_delta, double* grad_weight, hipStream_t st);
 int xi_bwd_blocks_per_cu(int precision, int n_bins);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

@@ -169,6 +169,7 @@ struct Prepared {
   double* edges_par = nullptr;
   double* edges_perp = nullptr;
   EtaInfo* einfo = nullptr;
+  double* delta_proj = nullptr;  // eta delta per forest (project only), FP64
   Globals host{};
 };
 
@@ -231,6 +232,7 @@ lya_status prepare(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
   HIP_TRY(hipStreamSynchronize(st));
   memcpy(&P.host, ctx->pinned, sizeof(Globals));
   P.einfo = einfo;
+  P.delta_proj = a.delta_proj;
   P.rec32 = a.rec32;
   P.rec64 = a.rec64;
   P.drec32 = a.drec32;
@@ -743,8 +745,6 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
   LYA_TRY(check_common(ctx, F, G, o, gd));
   if (!grad_xi || !xi || !wsum) return fail(ctx, LYA_E_INVALID, "NULL grad_xi, xi or wsum");
   if (!grad_delta || !grad_weight) return fail(ctx, LYA_E_INVALID, "NULL output grad_delta or grad_weight");
-  if (o->project_deltas)
-    return fail(ctx, LYA_E_INVALID, "lya_xi_backward differentiates the deltas as given: project_deltas must be 0");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ctx->err.clear();
@@ -757,7 +757,8 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
   HIP_TRY(launch_zero(grad_weight, (size_t)F->n_pix * sizeof(double), st));
   if (F->n_forests > 0 && F->n_pix > 0) {
     Prepared P;
-    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, false, P));
+    const bool project = o->project_deltas != 0;
+    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, project, P));
     tm.at(1);
     Worklist W;
     LYA_TRY(build_worklist(ctx, F, gd, P, st, true, false, 0, 0, false, INT32_MAX, "bw", W));
@@ -781,7 +782,7 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
     a.rec64 = P.rec64;
     a.dist = F->dist;
     a.weight = F->weight;
-    a.delta = F->delta;
+    a.delta = project ? P.delta_proj : F->delta;
     a.edges_par = P.edges_par;
     a.edges_perp = P.edges_perp;
     a.glob = P.glob;
@@ -794,6 +795,7 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
     HIP_TRY(launch_zero(counter, 4, st));
     tm.at(3);
     HIP_TRY(launch_xi_bwd(o->precision, a, blocks, st));
+    if (project) HIP_TRY(launch_project_adjoint(F, P.einfo, P.delta_proj, grad_delta, grad_weight, st));
     tm.at(4);
   } else {
     tm.at(1);

@@ -1,5 +1,6 @@
-"""GPU parity of lya_xi_backward (the hand-written gradient of xi) against the
-FP64 oracle gradient, central finite differences and Euler identities.
+"""GPU parity of lya_xi_backward (the hand-written gradient of xi, also
+through the continuum projection) against the FP64 oracle gradient, central
+finite differences, invariances and Euler identities.
 e_g = max |dg| / max |g| (normwise): 1e-12 for the FP64 form, 1e-5 for FP32."""
 import numpy as np
 import pytest
@@ -146,11 +147,127 @@ def test_autograd_function(lib):
     assert np.allclose(w.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14 * np.abs(gw).max())
 
 
-def test_backward_rejects_projection(lib):
-    from paper_2507_00129_amd import DeviceForests, LyaError, LYA_E_INVALID
-    F, G, _ = make_config(0, seed=0, scale=0.2)
+# ----------------------------------------------- gradient through the projection
+
+
+def gpu_grad_proj(lib, F, G, target, prec, eta):
+    from paper_2507_00129_amd import DeviceForests
     dF = DeviceForests.from_host(F, "cuda:0")
-    out = lib.xi(dF, G)
-    with pytest.raises(LyaError) as ei:
-        lib.xi_backward(dF, G, out["xi"], out["xi"], out["wsum"], project_deltas=True)
-    assert ei.value.status == LYA_E_INVALID
+    opts = dict(precision=prec, project_deltas=True, eta=eta)
+    out = lib.xi(dF, G, **opts)
+    t = torch.as_tensor(target, device="cuda:0").reshape(out["xi"].shape)
+    gd, gw = lib.xi_backward(dF, G, 2.0 * (out["xi"] - t), out["xi"], out["wsum"], **opts)
+    torch.cuda.synchronize()
+    return gd.cpu().numpy(), gw.cpu().numpy(), out["xi"].cpu().numpy()
+
+
+def oracle_grad_proj(F, G, target, eta):
+    mode = {"mean": O.MEAN, "mean_slope": O.MEAN_SLOPE, "identity": O.IDENTITY}[eta]
+    X = O.xi_sums(F, G, project=True, eta_mode=mode)
+    gxi = O.loss_grad_xi(X.xi, np.asarray(target).reshape(X.xi.shape))
+    return O.xi_grad_projected(F, G, gxi, X.xi, X.wsum, eta_mode=mode)
+
+
+@pytest.mark.parametrize("eta", ["mean_slope", "mean"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projected_config4_subset_vs_oracle(lib, prec, eta):
+    """Gradient with respect to the raw delta and w when xi correlates the
+    projected deltas eta delta (eta moving with w), on the 200 forests nearest
+    the centre of the differentiable workload."""
+    F, G, ex = make_config(4, seed=0, scale=0.05)
+    S = subset_forests(F, nearest_to_centre(F, 200))
+    key = ("proj", eta)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = oracle_grad_proj(S, G, ex["target"], eta)
+    rd, rw = _ORACLE_CACHE[key]
+    gd, gw, _ = gpu_grad_proj(lib, S, G, ex["target"], prec, eta)
+    check(gd, gw, rd, rw, prec, f"projected {eta} config4-200")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projected_ragged_and_degenerate(lib, prec):
+    """Empty, one-pixel (slope term dropped) and zero-weight (eta = I) forests,
+    forests of up to 700 pixels, and the identity projection."""
+    F = _ragged_forests(5)
+    target = np.random.default_rng(4).uniform(-0.01, 0.01, G60.n_bins)
+    for eta in ("mean_slope", "identity"):
+        rd, rw = oracle_grad_proj(F, G60, target, eta)
+        gd, gw, _ = gpu_grad_proj(lib, F, G60, target, prec, eta)
+        check(gd, gw, rd, rw, prec, f"projected {eta} ragged")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_projected_invariances_full_size(lib, prec):
+    """Full differentiable workload with projected deltas: adding a constant or
+    a multiple of Lambda to one forest's deltas leaves eta delta unchanged, so
+    the delta-gradient sums to zero over every forest and against Lambda; the
+    Euler identities hold through eta."""
+    F, G, ex = make_config(4, seed=0)
+    gd, gw, xi = gpu_grad_proj(lib, F, G, ex["target"], prec, "mean_slope")
+    c = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+    n = np.maximum(np.bincount(c, minlength=F.n_forests), 1)
+    lc = F.loglam - (np.bincount(c, F.loglam, F.n_forests) / n)[c]
+    s0 = np.abs(np.bincount(c, gd, F.n_forests))
+    s1 = np.abs(np.bincount(c, lc * gd, F.n_forests))
+    a0 = np.bincount(c, np.abs(gd), F.n_forests)
+    a1 = np.bincount(c, np.abs(lc * gd), F.n_forests)
+    e0 = float(np.max(s0 / np.maximum(a0, 1e-300)))
+    e1 = float(np.max(s1 / np.maximum(a1, 1e-300)))
+    lhs = float(np.dot(F.delta, gd))
+    rhs = 4.0 * float(np.sum(xi[0] * (xi[0] - ex["target"])))
+    scale = float(np.dot(np.abs(F.delta), np.abs(gd)))
+    print(f"[projected invariances {prec}] sum={e0:.2e} lambda={e1:.2e} euler={abs(lhs - rhs) / scale:.2e}",
+          flush=True)
+    assert e0 <= 1e-12 and e1 <= 1e-10
+    assert abs(lhs - rhs) <= TOL[prec] * scale * 10
+    assert abs(np.dot(F.weight, gw)) <= TOL[prec] * float(np.dot(np.abs(F.weight), np.abs(gw))) * 10
+
+
+def test_projected_finite_differences_on_gpu(lib):
+    """Central differences of the GPU loss with projected deltas (FP64 form):
+    exact up to rounding in delta, O(eps^2) in w."""
+    from paper_2507_00129_amd import DeviceForests
+    F, G, ex = make_config(4, seed=1, scale=0.02)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    tgt = torch.as_tensor(ex["target"], device="cuda:0")[None, :]
+    opts = dict(precision="fp64", project_deltas=True, eta="mean_slope")
+
+    def loss(d, w):
+        x = lib.xi(dF.with_values(delta=d, weight=w), G, **opts)["xi"]
+        return float(((x - tgt) ** 2).sum())
+
+    out = lib.xi(dF, G, **opts)
+    gd, gw = lib.xi_backward(dF, G, 2.0 * (out["xi"] - tgt), out["xi"], out["wsum"], **opts)
+    gd, gw = gd.cpu().numpy(), gw.cpu().numpy()
+    rng = np.random.default_rng(6)
+    eps = 1e-3
+    for i in rng.choice(F.n_pix, 12, replace=False):
+        d = dF.delta.clone()
+        d[i] += eps
+        lp = loss(d, dF.weight)
+        d[i] -= 2 * eps
+        lm = loss(d, dF.weight)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gd[i]) <= 1e-7 * max(1.0, abs(gd[i])) + 1e-9 * np.abs(gd).max(), (i, fd, gd[i])
+    for i in rng.choice(F.n_pix, 12, replace=False):
+        w = dF.weight.clone()
+        w[i] += eps
+        lp = loss(dF.delta, w)
+        w[i] -= 2 * eps
+        lm = loss(dF.delta, w)
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - gw[i]) <= 1e-4 * abs(gw[i]) + 1e-6 * np.abs(gw).max(), (i, fd, gw[i])
+
+
+def test_projected_autograd_function(lib):
+    from paper_2507_00129_amd import DeviceForests, differentiable_xi
+    F, G, ex = make_config(4, seed=2, scale=0.02)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    d = dF.delta.clone().requires_grad_(True)
+    w = dF.weight.clone().requires_grad_(True)
+    xi = differentiable_xi(d, w, lib, dF, G, "fp64", project_deltas=True)
+    tgt = torch.as_tensor(ex["target"], device="cuda:0")[None, :]
+    ((xi - tgt) ** 2).sum().backward()
+    gd, gw, _ = gpu_grad_proj(lib, F, G, ex["target"], "fp64", "mean_slope")
+    assert np.allclose(d.grad.cpu().numpy(), gd, rtol=1e-12, atol=1e-14 * np.abs(gd).max())
+    assert np.allclose(w.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14 * np.abs(gw).max())
