@@ -269,10 +269,34 @@ class XiSums:
     npairs: np.ndarray   # [R, n_bins]  pair counts (int64)
     absnum: np.ndarray   # [R, n_bins]  sum |w_i d_i w_j d_j| (conditioning)
     n_near_edge: int     # pairs within edge_tau * max(1, r) of an interior or upper edge
+    rpsum: Optional[np.ndarray] = None   # [R, n_bins]  sum w_i w_j r_par      (means=True)
+    rtsum: Optional[np.ndarray] = None   # [R, n_bins]  sum w_i w_j r_perp
+    zsum: Optional[np.ndarray] = None    # [R, n_bins]  sum w_i w_j (z_i + z_j) / 2
 
     @property
     def xi(self):
         return xi_from_sums(self.num, self.wsum)
+
+
+LYA_ALPHA_ANGSTROM = 1215.67   # rest wavelength of the Lyman-alpha transition
+
+
+def pixel_redshift(loglam):
+    """z of a forest pixel: lambda / lambda_Lya - 1 with lambda = exp(loglam) in
+    Angstrom (natural log; only the bin-mean redshift needs the base)."""
+    return np.exp(np.asarray(loglam, np.float64)) / LYA_ALPHA_ANGSTROM - 1.0
+
+
+def bin_means(X: "XiSums"):
+    """Weighted bin-mean coordinates (the r_par, r_perp and z columns of the
+    correlation output that a model fitter reads next to xi):
+    sum w_i w_j r / sum w_i w_j per bin, 0 where the bin is empty."""
+    def mean(t):
+        out = np.zeros_like(t)
+        nz = X.wsum != 0.0
+        out[nz] = t[nz] / X.wsum[nz]
+        return out
+    return mean(X.rpsum), mean(X.rtsum), mean(X.zsum)
 
 
 def xi_from_sums(num, wsum):
@@ -308,7 +332,8 @@ def _chunks_by_pixels(F, g_list, budget):
 
 
 def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
-            edge_tau=1e-12, pairs=None, chunk_elems=2_000_000, sub=None, n_sub=1) -> XiSums:
+            edge_tau=1e-12, pairs=None, chunk_elems=2_000_000, sub=None, n_sub=1,
+            means=False) -> XiSums:
     """Pair sums of eq. estimator_two for every realisation.
 
     For each forest f the pixels of all its partners g > f are concatenated
@@ -320,6 +345,9 @@ def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
     by subsample: every pair (f, g), f < g, goes to slab r * n_sub + sub[f]
     (the errors of Sec. 2.1 and of the 3PCF figure come from subsamples of the
     forests in sky pixels); the first axis of the outputs is then R * n_sub.
+
+    With `means`, also the weighted coordinate sums sum w_i w_j r_par,
+    sum w_i w_j r_perp and sum w_i w_j (z_i + z_j) / 2 per bin (``bin_means``).
     """
     n_sub = int(n_sub) if sub is not None else 1
     R = max(1, int(F.n_realisations)) * n_sub
@@ -332,11 +360,20 @@ def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
     wsum = _Neumaier((R, nb))
     absn = _Neumaier((R, nb))
     npairs = np.zeros((R, nb), np.int64)
+    msum = [_Neumaier((R, nb)) for _ in range(3)] if means else None
+    zpix = pixel_redshift(F.loglam) if means else None
     n_near = 0
+
+    def result():
+        X = XiSums(num.value(), wsum.value(), npairs, absn.value(), n_near)
+        if means:
+            X.rpsum, X.rtsum, X.zsum = (m.value() for m in msum)
+        return X
+
     if pairs is None:
         pairs = forest_pairs(F, grid, prune)
     if pairs.shape[0] == 0:
-        return XiSums(num.value(), wsum.value(), npairs, absn.value(), 0)
+        return result()
     order = np.argsort(pairs[:, 0], kind="stable")
     pairs = pairs[order]
     firsts, starts = np.unique(pairs[:, 0], return_index=True)
@@ -363,7 +400,11 @@ def xi_sums(F, grid, *, project=False, eta_mode=MEAN_SLOPE, prune=True,
             wsum.add(np.bincount(Am, weights=ww, minlength=nb), where=(r,))
             absn.add(np.bincount(Am, weights=np.abs(prod), minlength=nb), where=(r,))
             npairs[r] += np.bincount(Am, minlength=nb)
-    return XiSums(num.value(), wsum.value(), npairs, absn.value(), n_near)
+            if means:
+                zz = (0.5 * (zpix[sl][:, None] + zpix[idx][None, :]))[m]
+                for acc, v in zip(msum, (rpar[m], rperp[m], zz)):
+                    acc.add(np.bincount(Am, weights=ww * v, minlength=nb), where=(r,))
+    return result()
 
 
 def covariance(num, wsum):
@@ -425,6 +466,50 @@ def xi_pairs_brute(F, grid, delta=None):
 # ---------------------------------------------------------------------------
 # distortion matrix (Sec. 2.2, eq. distortion)
 # ---------------------------------------------------------------------------
+
+
+def xi_means_brute(F, grid):
+    """Bin-mean r_par, r_perp and z by a pure-Python loop over pixel pairs
+    (tiny inputs), with the separations taken from the 3-D positions
+    x = D n: r_par = |(x_j - x_i) . m| along the mid line of sight
+    m = (n_f + n_g) / |n_f + n_g| and r_perp the length of the rest."""
+    import math
+    R = max(1, int(F.n_realisations))
+    nb = grid.n_bins
+    real = F.real_of()
+    n = unit_vectors(F.ra, F.dec)
+    z = pixel_redshift(F.loglam)
+    acc = {k: [[[] for _ in range(nb)] for _ in range(R)] for k in ("w", "rp", "rt", "z")}
+    for f in range(F.n_forests):
+        for g in range(f + 1, F.n_forests):
+            if real[f] != real[g]:
+                continue
+            mid = n[f] + n[g]
+            mid = mid / math.sqrt(float(np.dot(mid, mid)))
+            for i in range(F.offsets[f], F.offsets[f + 1]):
+                for j in range(F.offsets[g], F.offsets[g + 1]):
+                    sep = F.dist[j] * n[g] - F.dist[i] * n[f]
+                    along = float(np.dot(sep, mid))
+                    rest = sep - along * mid
+                    rpar, rperp = abs(along), math.sqrt(float(np.dot(rest, rest)))
+                    kp = int(bin_index_1d(np.array([rpar]), grid.edges_par)[0])
+                    kt = int(bin_index_1d(np.array([rperp]), grid.edges_perp)[0])
+                    if kp < 0 or kt < 0:
+                        continue
+                    A, r = kp * grid.n_perp + kt, int(real[f])
+                    ww = float(F.weight[i]) * float(F.weight[j])
+                    acc["w"][r][A].append(ww)
+                    acc["rp"][r][A].append(ww * rpar)
+                    acc["rt"][r][A].append(ww * rperp)
+                    acc["z"][r][A].append(ww * 0.5 * (z[i] + z[j]))
+    tot = {k: np.array([[math.fsum(v) for v in row] for row in a]) for k, a in acc.items()}
+    W = tot["w"]
+    out = []
+    for k in ("rp", "rt", "z"):
+        m = np.zeros_like(W)
+        m[W != 0] = tot[k][W != 0] / W[W != 0]
+        out.append(m)
+    return tuple(out)
 
 
 def splitmix64(x):

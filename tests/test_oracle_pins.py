@@ -73,6 +73,50 @@ def test_golden_handworked_xi():
     assert (Xp.npairs == X.npairs).all()
 
 
+def test_golden_handworked_bin_means():
+    """Bin-mean r_par, r_perp, z of the hand-worked example (values derived by
+    hand in the fixture; z of a pixel is lambda / lambda_Lya - 1)."""
+    d = load_json("xi_handworked_two_forests.json")
+    F, G = forests_from_dict(d["forests"]), grid_from_dict(d["grid"])
+    rp, rt, z = O.bin_means(O.xi_sums(F, G, prune=False, means=True))
+    exp = d["expected_means"]
+    assert np.allclose(rp[0], exp["rpar"], rtol=1e-14, atol=0)
+    assert np.allclose(rt[0], exp["rperp"], rtol=0, atol=1e-9)
+    zl = np.exp(np.asarray(exp["z_loglam"])) / 1215.67 - 1.0
+    assert np.allclose(z[0], np.asarray(exp["z_weights"]) @ zl, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_bin_means_vs_geometric_brute(seed):
+    """Vectorised bin means against a pure-Python pair loop that measures the
+    separations on 3-D positions (projection on the mid line of sight)."""
+    F = tiny(seed, n_forests=4, k=8)
+    X = O.xi_sums(F, G60, means=True)
+    rp, rt, z = O.bin_means(X)
+    brp, brt, bz = O.xi_means_brute(F, G60)
+    assert X.npairs.sum() > 20
+    assert np.allclose(rp, brp, rtol=1e-9, atol=1e-9)
+    assert np.allclose(rt, brt, rtol=1e-9, atol=1e-9)
+    assert np.allclose(z, bz, rtol=1e-13, atol=1e-13)
+
+
+def test_bin_means_lie_in_their_bins():
+    """A weighted mean of values in [e_k, e_k+1) lies in that interval; the
+    mean pair redshift lies within the pixels' redshift range; empty bins are 0."""
+    F = make_patch(40, 2.0, 12)
+    X = O.xi_sums(F, G60, means=True)
+    rp, rt, z = O.bin_means(X)
+    kp, kt = np.divmod(np.arange(G60.n_bins), G60.n_perp)
+    ne = X.wsum[0] > 0
+    assert ne.sum() > 0.9 * G60.n_bins
+    ep, et = G60.edges_par, G60.edges_perp
+    assert np.all(rp[0][ne] >= ep[kp][ne]) and np.all(rp[0][ne] <= ep[kp + 1][ne])
+    assert np.all(rt[0][ne] >= et[kt][ne]) and np.all(rt[0][ne] <= et[kt + 1][ne])
+    zp = O.pixel_redshift(F.loglam)
+    assert np.all(z[0][ne] >= zp.min()) and np.all(z[0][ne] <= zp.max())
+    assert np.all(rp[0][~ne] == 0) and np.all(z[0][~ne] == 0)
+
+
 # ------------------------------------------------------------------ O3 xi sums
 
 
