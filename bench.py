@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the full-size FP32-vs-FP64 comparison")
+    ap.add_argument("--no-means", action="store_true", help="skip timing the bin-means form of the xi kernel")
     ap.add_argument("--cpu-xi-forests", type=int, default=400)
     ap.add_argument("--cpu-d-forests", type=int, default=120)
     ap.add_argument("--xi-variant", type=int, default=3,
@@ -244,6 +245,21 @@ def main():
             f"({xi_pairs / r['ms_xi_kernel'] * 1e3:.3e} pairs/s), D kernel {r['ms_d_kernel']:.2f} ms "
             f"({d_pairs / max(r['ms_d_kernel'], 1e-9) * 1e3:.3e} pairs/s)")
 
+    means = None
+    if not args.no_means:
+        # the xi kernel form that also sums the bin-mean coordinates (FP32),
+        # one warm-up and three timed calls outside the step
+        ms = []
+        for k in range(4):
+            lib.xi_means(dF, G, precision="fp32", timing=True)
+            if k:
+                ms.append(lib.last_stats()["ms_main"])
+        torch.cuda.synchronize()
+        mm = mean(ms)
+        means = dict(ms_kernel=mm, pairs_per_s_kernel=res["fp32"]["xi_pairs"] / (mm / 1e3),
+                     time_over_xi_kernel=mm / res["fp32"]["ms_xi_kernel"])
+        log(f"[bench] xi with bin means (fp32): kernel {mm:.2f} ms")
+
     r32 = res["fp32"]
     # dominant kernel and its roofline (algorithmic work / kernel time from HIP
     # events recorded around the launch on its stream)
@@ -261,6 +277,8 @@ def main():
     line["roofline_xi"] = xi_roofline(r32)
     line["xi_pairs_per_s_kernel"] = r32["xi_pairs"] / (r32["ms_xi_kernel"] / 1e3)
     line["d_pairs_per_s_kernel"] = r32["d_pairs"] / max(r32["ms_d_kernel"] / 1e3, 1e-12)
+    if means is not None:
+        line["xi_means_fp32"] = means
     if "fp64" in res:
         r64 = res["fp64"]
         line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_step"],

@@ -164,6 +164,24 @@ lya_status lya_xi(lya_context *ctx, const lya_forests *forests, const lya_grid *
                   const lya_options *opts, void *stream,
                   double *num, double *wsum, int64_t *npairs, double *xi);
 
+/* lya_xi plus the weighted bin-mean coordinates of the pairs, the r_par,
+   r_perp and z columns that the paper's output carries next to xi for the
+   model fit (Sec. 3.1: the PICCA-format output read by Vega).  Extra outputs,
+   each [n_realisations * n_bins], device:
+     rpar[A]  = sum_A w_i w_j r_par / wsum[A]
+     rperp[A] = sum_A w_i w_j r_perp / wsum[A]
+     z[A]     = sum_A w_i w_j (z_i + z_j) / 2 / wsum[A]
+   (0 where wsum[A] == 0), with the pixel redshift z_i = lambda_i / 1215.67 - 1
+   and lambda_i = exp(loglam_i) Angstrom: for z, loglam must be the NATURAL
+   log of the wavelength in Angstrom (the other outputs accept any base).
+   In the FP32 form the coordinates come from the FP32 bin coordinates that
+   the binning computes, so their error is that of the separations (about
+   1e-4 Mpc/h), not of the FP64 form. */
+lya_status lya_xi_means(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                        const lya_options *opts, void *stream,
+                        double *num, double *wsum, int64_t *npairs, double *xi,
+                        double *rpar, double *rperp, double *z);
+
 /* Pair sums split by subsample, for the subsampling covariance of xi (the
    paper estimates the errors from subsamples of the forests in sky pixels,
    Sec. 2.1 and the 3PCF figure).  subsample[f] in [0, n_sub) (device,

@@ -10,6 +10,7 @@ namespace lya {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
+constexpr double kLyaAlphaAngstrom = 1215.67;  // Lyman-alpha rest wavelength
 
 // Subsample ids must lie in [0, n_sub): they index output slabs.
 __global__ void validate_sub_kernel(const int32_t* sub, int64_t n, int32_t n_sub, Globals* glob) {
@@ -175,8 +176,11 @@ __global__ __launch_bounds__(256) void pack_kernel(PrecomputeArgs a, lya_forests
     const int64_t i = fi.pix0 + k;
     const double D = F.dist[i], w = F.weight[i], de = del[i];
     const double wd = w * de;
-    if (a.want_xi32) a.rec32[i] = Rec32{(float)(D - dc), (float)wd, (float)w, (float)de};
-    if (a.want_xi64) a.rec64[i] = Rec64{D, wd, w, de};
+    // fourth slot: delta, or the pixel redshift lambda / lambda_Lya - 1 with
+    // lambda = exp(loglam) Angstrom (bin means)
+    const double x4 = a.pack_z ? exp(F.loglam[i]) / kLyaAlphaAngstrom - 1.0 : de;
+    if (a.want_xi32) a.rec32[i] = Rec32{(float)(D - dc), (float)wd, (float)w, (float)x4};
+    if (a.want_xi64) a.rec64[i] = Rec64{D, wd, w, x4};
     if (a.want_d32 || a.want_d64) {
       const bool act = e.active != 0;
       const double am = act ? F.loglam[i] - e.lbar : 0.0;

@@ -24,6 +24,12 @@
 // pair of FP32 accumulators); with run-length accumulation, consecutive
 // products of the same bin are first summed in FP32 registers (runs end at
 // every 32nd pixel of f, so a run holds at most 32 products).
+//
+// Bin means.  The MEANS form also sums w_i w_j x_par, w_i w_j x_perp (the bin
+// coordinates x = (r - e0) / dr the binning already computes) and
+// w_i w_j (z_i + z_j), with the pixel redshift z packed in the record's fourth
+// slot; a finalisation turns them into the weighted mean r_par, r_perp and z
+// of each bin, the coordinate columns of the correlation output.
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -87,11 +93,13 @@ template <> struct RecOf<float> { using type = Rec32; };
 template <> struct RecOf<double> { using type = Rec64; };
 
 // LDS histograms: hNW[2 L] = sum w_i d_i w_j d_j, hNW[2 L + 1] = sum w_i w_j
-// (interleaved, so one address serves both), hn[L] = pair count.
-template <int BLOCK>
-__device__ void flush_hist(const XiArgs& a, double* hNW, unsigned* hn, int real) {
+// (interleaved, so one address serves both), hn[L] = pair count; with MEANS,
+// hM[3 L + c] = sum w_i w_j (x_par, x_perp, z_i + z_j)[c].
+template <int BLOCK, bool MEANS>
+__device__ void flush_hist(const XiArgs& a, double* hNW, double* hM, unsigned* hn, int real) {
   const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
   const int64_t base = (int64_t)real * nb;
+  const int64_t nout = a.n_out;
   for (int L = threadIdx.x; L < nb; L += BLOCK) {
     const unsigned c = hn[L];
     if (c) {
@@ -100,15 +108,26 @@ __device__ void flush_hist(const XiArgs& a, double* hNW, unsigned* hn, int real)
       atomicAdd(&a.num[A], hNW[2 * L]);
       atomicAdd(&a.wsum[A], hNW[2 * L + 1]);
       atomicAdd(&a.npairs[A], (unsigned long long)c);
+      if constexpr (MEANS) {
+        atomicAdd(&a.msum[A], hM[3 * L]);
+        atomicAdd(&a.msum[nout + A], hM[3 * L + 1]);
+        atomicAdd(&a.msum[2 * nout + A], hM[3 * L + 2]);
+      }
     }
     hNW[2 * L] = 0.0;
     hNW[2 * L + 1] = 0.0;
+    if constexpr (MEANS) {
+      hM[3 * L] = 0.0;
+      hM[3 * L + 1] = 0.0;
+      hM[3 * L + 2] = 0.0;
+    }
     hn[L] = 0u;
   }
 }
 
-template <typename T, int BLOCK, bool RLE, bool ZLO>
+template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS>
 __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
+  static_assert(RLE || !MEANS, "bin means are accumulated by the run-length form");
   using Rec = typename RecOf<T>::type;
   extern __shared__ double smem[];
   __shared__ NbTable tb;
@@ -116,12 +135,18 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
 
   const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
   double* hNW = smem;
-  unsigned* hn = (unsigned*)(smem + 2 * nb);
+  double* hM = smem + 2 * nb;
+  unsigned* hn = (unsigned*)(smem + (MEANS ? 5 : 2) * nb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   for (int L = threadIdx.x; L < nb; L += BLOCK) {
     hNW[2 * L] = 0.0;
     hNW[2 * L + 1] = 0.0;
+    if constexpr (MEANS) {
+      hM[3 * L] = 0.0;
+      hM[3 * L + 1] = 0.0;
+      hM[3 * L + 2] = 0.0;
+    }
     hn[L] = 0u;
   }
 
@@ -178,7 +203,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     const int okey = a.sub ? fi.real * a.n_sub + a.sub[f] : fi.real;
     if (okey != cur_key || pending + (double)total * fi.npix > 4.0e9) {
       if (cur_key >= 0) {
-        flush_hist<BLOCK>(a, hNW, hn, cur_key);
+        flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
         __syncthreads();
       }
       cur_key = okey;
@@ -200,7 +225,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         }
         k = lo;
       }
-      T dj, wdj, wj, cp, st, bt;
+      T dj, wdj, wj, zj = 0, cp, st, bt;
       double Dj64 = 0.0, s64 = 0.0, c64 = 1.0;
       if (q < total) {
         const int64_t j = tb.pix0[k] + (q - tb.pref[k]);
@@ -208,6 +233,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         dj = rj.d;
         wdj = rj.wd;
         wj = rj.w;
+        zj = rj.del;  // the pixel redshift when the records carry z (MEANS)
         s64 = tb.s64[k];
         c64 = tb.c64[k];
         if constexpr (sizeof(T) == 4) Dj64 = a.dist[j]; else Dj64 = rj.d;
@@ -224,12 +250,12 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         bt = (T)1e30;
       }
 
-      // bin of the pair (pixel i of f, this lane's pixel), or -1
-      auto bin_of = [&](const Rec& ri, int i) -> int {
+      // bin of the pair (pixel i of f, this lane's pixel), or -1; xp, xt are
+      // its coordinates in bin units
+      auto bin_of = [&](const Rec& ri, int i, T& xp, T& xt) -> int {
         const T ad = fabs(ri.d - dj);
-        T xp;
         if constexpr (ZLO) xp = ad * cp; else xp = fma(ad, cp, mep);
-        const T xt = fma(ri.d, st, bt);
+        xt = fma(ri.d, st, bt);
         return K.bin_x(xp, xt, [&](double& rp64, double& rt64) {
           double Di64;
           if constexpr (sizeof(T) == 4) Di64 = load_uniform(a.dist + fi.pix0 + i); else Di64 = ri.d;
@@ -245,22 +271,42 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
         for (int c0 = 0; c0 < nf; c0 += (int)kRunMax) {
           const int c1 = min(nf, c0 + (int)kRunMax);
           int curA = -1, ist = c0;
-          T accN = 0, accW = 0;
+          T accN = 0, accW = 0, accP = 0, accT = 0, accZ = 0;
+          auto add_run = [&](int A, int count) {
+            atomicAdd(&hNW[2 * A], (double)accN);
+            atomicAdd(&hNW[2 * A + 1], (double)accW);
+            atomicAdd(&hn[A], (unsigned)count);
+            if constexpr (MEANS) {
+              atomicAdd(&hM[3 * A], (double)accP);
+              atomicAdd(&hM[3 * A + 1], (double)accT);
+              atomicAdd(&hM[3 * A + 2], (double)accZ);
+            }
+          };
           auto pair = [&](const Rec& ri, int i) {
-            const int A = bin_of(ri, i);
+            T xp, xt;
+            const int A = bin_of(ri, i, xp, xt);
             if (A != curA) {
-              if (curA >= 0) {
-                atomicAdd(&hNW[2 * curA], (double)accN);
-                atomicAdd(&hNW[2 * curA + 1], (double)accW);
-                atomicAdd(&hn[curA], (unsigned)(i - ist));
-              }
+              if (curA >= 0) add_run(curA, i - ist);
               curA = A;
               accN = 0;
               accW = 0;
+              if constexpr (MEANS) {
+                accP = 0;
+                accT = 0;
+                accZ = 0;
+              }
               ist = i;
             }
             accN = fma(ri.wd, wdj, accN);
-            accW = fma(ri.w, wj, accW);
+            if constexpr (MEANS) {
+              const T ww = ri.w * wj;
+              accW += ww;
+              accP = fma(ww, xp, accP);
+              accT = fma(ww, xt, accT);
+              accZ = fma(ww, ri.del + zj, accZ);
+            } else {
+              accW = fma(ri.w, wj, accW);
+            }
           };
           int i = c0;
           for (; i + NB <= c1; i += NB) {
@@ -270,15 +316,12 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
             for (int u = 0; u < NB; ++u) pair(b.r[u], i + u);
           }
           for (; i < c1; ++i) pair(load_uniform(rf + i), i);
-          if (curA >= 0) {
-            atomicAdd(&hNW[2 * curA], (double)accN);
-            atomicAdd(&hNW[2 * curA + 1], (double)accW);
-            atomicAdd(&hn[curA], (unsigned)(c1 - ist));
-          }
+          if (curA >= 0) add_run(curA, c1 - ist);
         }
       } else {
         auto pair = [&](const Rec& ri, int i) {
-          const int A = bin_of(ri, i);
+          T xp, xt;
+          const int A = bin_of(ri, i, xp, xt);
           if (A >= 0) {
             atomicAdd(&hNW[2 * A], (double)(ri.wd * wdj));
             atomicAdd(&hNW[2 * A + 1], (double)(ri.w * wj));
@@ -298,7 +341,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  if (cur_key >= 0) flush_hist<BLOCK>(a, hNW, hn, cur_key);
+  if (cur_key >= 0) flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
 }
 
 struct Variant {
@@ -314,10 +357,15 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <typename T, int BLOCK, bool RLE, bool ZLO>
+template <bool MEANS>
+constexpr size_t smem_per_bin() {
+  return (MEANS ? 5 : 2) * sizeof(double) + sizeof(unsigned);
+}
+
+template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS = false>
 hipError_t launch_one(const XiArgs& a, int blocks, hipStream_t st) {
-  const size_t smem = (size_t)a.g.n_par * a.g.n_perp * (2 * sizeof(double) + sizeof(unsigned));
-  auto kern = xi_kernel<T, BLOCK, RLE, ZLO>;
+  const size_t smem = (size_t)a.g.n_par * a.g.n_perp * smem_per_bin<MEANS>();
+  auto kern = xi_kernel<T, BLOCK, RLE, ZLO, MEANS>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
@@ -341,10 +389,10 @@ hipError_t launch_t(int v, const XiArgs& a, int blocks, hipStream_t st) {
   return zlo ? launch_z<T, true>(v, a, blocks, st) : launch_z<T, false>(v, a, blocks, st);
 }
 
-template <typename T, int BLOCK, bool RLE>
+template <typename T, int BLOCK, bool RLE, bool MEANS = false>
 int occupancy(int n_bins) {
-  const size_t smem = (size_t)n_bins * (2 * sizeof(double) + sizeof(unsigned));
-  auto kern = xi_kernel<T, BLOCK, RLE, true>;
+  const size_t smem = (size_t)n_bins * smem_per_bin<MEANS>();
+  auto kern = xi_kernel<T, BLOCK, RLE, true, MEANS>;
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, BLOCK, smem) != hipSuccess) return 1;
@@ -367,6 +415,19 @@ __global__ void zero_kernel(uint32_t* p, size_t n) {
     p[i] = 0u;
 }
 
+// Bin means from the sums of w_i w_j x (x in bin units) and w_i w_j (z_i + z_j):
+// r = e0 + dr * sum(ww x) / W, z = sum(ww (z_i + z_j)) / (2 W); 0 where W = 0.
+__global__ void finalize_means_kernel(const double* wsum, const double* msum, int64_t n, GridDev g,
+                                      double* rpar, double* rperp, double* z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double w = wsum[i];
+  const bool e = w == 0.0;
+  rpar[i] = e ? 0.0 : g.e0_par + (msum[i] / w) / g.inv_par;
+  rperp[i] = e ? 0.0 : g.e0_perp + (msum[n + i] / w) / g.inv_perp;
+  z[i] = e ? 0.0 : 0.5 * (msum[2 * n + i] / w);
+}
+
 __global__ void finalize_xi_kernel(const double* num, const double* wsum, double* xi, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -387,6 +448,32 @@ hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hi
 
 int xi_blocks_per_cu(int variant, int precision, int n_bins) {
   return precision == LYA_FP64 ? occ_t<double>(variant, n_bins) : occ_t<float>(variant, n_bins);
+}
+
+// The bin-means form: one run-length variant, kMeansBlock threads.
+constexpr int kMeansBlock = 512;
+
+hipError_t launch_xi_means(int precision, const XiArgs& a, int blocks, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  const bool zlo = a.g.zero_lo_par && a.g.zero_lo_perp;
+  if (precision == LYA_FP64)
+    return zlo ? launch_one<double, kMeansBlock, true, true, true>(a, blocks, st)
+               : launch_one<double, kMeansBlock, true, false, true>(a, blocks, st);
+  return zlo ? launch_one<float, kMeansBlock, true, true, true>(a, blocks, st)
+             : launch_one<float, kMeansBlock, true, false, true>(a, blocks, st);
+}
+
+int xi_means_blocks_per_cu(int precision, int n_bins) {
+  return precision == LYA_FP64 ? occupancy<double, kMeansBlock, true, true>(n_bins)
+                               : occupancy<float, kMeansBlock, true, true>(n_bins);
+}
+
+hipError_t launch_finalize_means(const double* wsum, const double* msum, int64_t n, const GridDev& g,
+                                 double* rpar, double* rperp, double* z, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_means_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, wsum, msum,
+                     n, g, rpar, rperp, z);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {

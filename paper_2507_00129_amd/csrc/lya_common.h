@@ -145,6 +145,7 @@ struct PrecomputeArgs {
   int eta_mode;
   int project;
   int want_xi32, want_xi64, want_d32, want_d64;
+  int pack_z;           // xi records carry the pixel redshift in their fourth slot
   ForestInfo* finfo;
   EtaInfo* einfo;
   double* delta_proj;   // [n_pix] when project
@@ -228,6 +229,10 @@ struct XiArgs {
   // output slab realisation * n_sub + sub[f] of its owning forest f
   const int32_t* sub;
   int32_t n_sub;
+  // bin means (MEANS form): msum[c * n_out + A], c = sum w w x_par,
+  // sum w w x_perp (bin units), sum w w (z_i + z_j)
+  double* msum;
+  int64_t n_out;
 };
 int xi_num_variants();
 const char* xi_variant_name(int v);
@@ -292,6 +297,10 @@ struct BwdArgs {
 hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* wsum, double2* out,
                         int64_t n, int NP, int NT, hipStream_t st);
 hipError_t launch_xi_bwd(int precision, const BwdArgs& a, int blocks, hipStream_t st);
+hipError_t launch_xi_means(int precision, const XiArgs& a, int blocks, hipStream_t st);
+int xi_means_blocks_per_cu(int precision, int n_bins);
+hipError_t launch_finalize_means(const double* wsum, const double* msum, int64_t n, const GridDev& g,
+                                 double* rpar, double* rperp, double* z, hipStream_t st);
 hipError_t launch_project_adjoint(const lya_forests* F, const EtaInfo* einfo, const double* delta_proj,
                                   double* grad_delta, double* grad_weight, hipStream_t st);
 int xi_bwd_blocks_per_cu(int precision, int n_bins);

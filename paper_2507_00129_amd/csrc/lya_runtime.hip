@@ -176,7 +176,7 @@ struct Prepared {
 // Validation, per-forest sums and record packing.
 lya_status prepare(lya_context* ctx, const lya_forests* F, const lya_grid* G, const GridDev& gd,
                    const lya_options* o, hipStream_t st, bool xi_rec, bool d_rec, bool project,
-                   Prepared& P) {
+                   Prepared& P, bool pack_z = false) {
   const int64_t N = F->n_forests, npix = F->n_pix;
   LYA_TRY(wst(ctx, "globals", 1, &P.glob));
   LYA_TRY(wst(ctx, "finfo", (size_t)N, &P.finfo));
@@ -211,6 +211,7 @@ lya_status prepare(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
   a.want_xi64 = xi_rec && o->precision == LYA_FP64;
   a.want_d32 = d_rec && o->precision == LYA_FP32_COMP;
   a.want_d64 = d_rec && o->precision == LYA_FP64;
+  a.pack_z = pack_z;
   a.finfo = P.finfo;
   a.einfo = einfo;
   a.glob = P.glob;
@@ -446,7 +447,7 @@ namespace {
 // the forest with the smaller input index).
 lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                    void* stream, const int32_t* sub, int32_t n_sub, double* num, double* wsum,
-                   int64_t* npairs, double* xi) {
+                   int64_t* npairs, double* xi, double* const* means = nullptr) {
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
   if (!num || !wsum || !npairs) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or npairs");
@@ -462,9 +463,14 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
   HIP_TRY(launch_zero(num, nout * sizeof(double), st));
   HIP_TRY(launch_zero(wsum, nout * sizeof(double), st));
   HIP_TRY(launch_zero(npairs, nout * sizeof(int64_t), st));
+  double* msum = nullptr;
+  if (means) {
+    LYA_TRY(wst(ctx, "xi_msum", (size_t)(3 * nout), &msum));
+    HIP_TRY(launch_zero(msum, 3 * nout * sizeof(double), st));
+  }
   if (F->n_forests > 0 && F->n_pix > 0) {
     Prepared P;
-    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, o->project_deltas != 0, P));
+    LYA_TRY(prepare(ctx, F, G, gd, o, st, true, false, o->project_deltas != 0, P, means != nullptr));
     if (sub) {
       HIP_TRY(launch_validate_sub(sub, F->n_forests, n_sub, P.glob, st));
       HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -500,6 +506,23 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
     a.npairs = (unsigned long long*)npairs;
     a.sub = sub;
     a.n_sub = sub ? n_sub : 1;
+    a.msum = msum;
+    a.n_out = nout;
+
+    if (means) {
+      // one run-length form with the coordinate sums; no variant choice
+      const int blocks = xi_means_blocks_per_cu(o->precision, nb) * ctx->n_cu;
+      ctx->stats.variant = -1;
+      ctx->stats.grid_blocks = blocks;
+      HIP_TRY(launch_zero(counter, 4, st));
+      tm.at(3);
+      HIP_TRY(launch_xi_means(o->precision, a, blocks, st));
+      tm.at(4);
+      HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
+      HIP_TRY(launch_finalize_means(wsum, msum, nout, gd, means[0], means[1], means[2], st));
+      tm.at(5);
+      return tm.finish(ctx);
+    }
 
     // autotune: time each variant on a prefix of the work list, into scratch outputs
     char key[128];
@@ -560,6 +583,7 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
     tm.at(4);
   }
   HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
+  if (means) HIP_TRY(launch_finalize_means(wsum, msum, nout, gd, means[0], means[1], means[2], st));
   tm.at(5);
   return tm.finish(ctx);
 }
@@ -569,6 +593,15 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
 lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                   void* stream, double* num, double* wsum, int64_t* npairs, double* xi) {
   return xi_impl(ctx, F, G, o, stream, nullptr, 1, num, wsum, npairs, xi);
+}
+
+lya_status lya_xi_means(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
+                        void* stream, double* num, double* wsum, int64_t* npairs, double* xi,
+                        double* rpar, double* rperp, double* z) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!rpar || !rperp || !z) return fail(ctx, LYA_E_INVALID, "NULL output rpar, rperp or z");
+  double* const means[3] = {rpar, rperp, z};
+  return xi_impl(ctx, F, G, o, stream, nullptr, 1, num, wsum, npairs, xi, means);
 }
 
 lya_status lya_xi_subsamples(lya_context* ctx, const lya_forests* F, const lya_grid* G,

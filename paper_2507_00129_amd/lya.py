@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     lib.lya_xi_backward.restype = I32
     lib.lya_xi_subsamples.argtypes = [P, FP, GP, OP, P, P, I32, P, P, P, P]
     lib.lya_xi_subsamples.restype = I32
+    lib.lya_xi_means.argtypes = [P, FP, GP, OP, P, P, P, P, P, P, P, P]
+    lib.lya_xi_means.restype = I32
     lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
     lib.lya_xi_covariance.restype = I32
     _lib = lib
@@ -239,6 +241,23 @@ class Library:
         self._check(self.lib.lya_xi(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
                                     self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
                                     _ptr(out["npairs"]), _ptr(out.get("xi"))))
+        return out
+
+    def xi_means(self, forests: DeviceForests, grid, stream=None, out=None, **opts):
+        """Pair sums, xi and the weighted bin-mean r_par, r_perp and z (z needs
+        loglam = ln(lambda / Angstrom)); returns dict of [R, n_bins] tensors."""
+        import torch
+        g = HostGrid(grid)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        if out is None:
+            out = {k: torch.empty((R, g.n_bins), dtype=torch.int64 if k == "npairs" else torch.float64, device=dev)
+                   for k in ("num", "wsum", "npairs", "xi", "rpar", "rperp", "z")}
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi_means(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                          self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
+                                          _ptr(out["npairs"]), _ptr(out.get("xi")), _ptr(out["rpar"]),
+                                          _ptr(out["rperp"]), _ptr(out["z"])))
         return out
 
     def xi_subsamples(self, forests: DeviceForests, grid, subsample, n_sub, stream=None, out=None, **opts):

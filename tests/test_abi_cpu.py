@@ -24,7 +24,7 @@ def test_header_symbols_exported():
     lib = ctypes.CDLL(L.LIB_PATH)
     names = _declared_functions()
     assert {"lya_create", "lya_xi", "lya_dmat", "lya_xi_backward", "lya_last_error",
-            "lya_xi_subsamples", "lya_xi_covariance"} <= set(names)
+            "lya_xi_subsamples", "lya_xi_covariance", "lya_xi_means"} <= set(names)
     for n in names:
         assert hasattr(lib, n), f"{n} declared in lya.h but not exported"
 
@@ -49,6 +49,7 @@ def test_defaults_and_null_arguments():
     assert lib.lya_xi_backward(None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_covariance(None, None, None, 1, 1, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_xi_means(None, None, None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert o.counters == 0
     assert lib.lya_create(None, 0) == L.LYA_E_INVALID
     assert lib.lya_last_error(None) == b"NULL context"
