@@ -58,30 +58,56 @@ namespace lya {
 namespace {
 
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
-// Lane layout of the FP64 16x16x4 MFMA: operand A[i][k] and B[k][j] come from
-// lane 16 k + i (resp. 16 k + j); accumulator register r of lane 16 g + j holds
-// row i = g + 4 r, column j.
-__device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
-
-constexpr int kTileW = 160;           // window bins per tile side
-constexpr int kBlk = 16;              // MFMA block side
-constexpr int kNBlk = kTileW / kBlk;  // 10 blocks per tile side
+constexpr int kBlk = 16;  // MFMA block side
 constexpr int kNW = 8;    // waves per workgroup
 constexpr int kRPW = 2;   // rows swept per wave per group
-constexpr int kBI = 5;    // block rows per wave
-constexpr int kMB = 13;   // block slots per wave: j < 10 -> (row j / 2, column j % 2),
-                          // j >= 10 -> (row j - 10 or j - 7, third column)
 
-// Block of slot j of the wave (wx, wy): block row index i (operand A), column
-// index k (operand B: 0, 1 -> columns wy, wy + 4; 2 -> column 8 + (wy & 1)).
-__host__ __device__ constexpr int slot_i(int j, bool low) { return j < 10 ? j >> 1 : (low ? j - 10 : j - 7); }
-__host__ __device__ constexpr int slot_k(int j) { return j < 10 ? (j & 1) : 2; }
-__host__ __device__ inline int slot_bx(int wx, bool low, int j) { return wx + 2 * slot_i(j, low); }
-__host__ __device__ inline int slot_by(int wy, int j) {
-  return slot_k(j) == 0 ? wy : (slot_k(j) == 1 ? wy + 4 : 8 + (wy & 1));
-}
-__host__ __device__ constexpr bool slot_ok(int j, bool low) { return j < kMB && slot_i(j, low) < kBI; }
+// The MFMA of each form.  16x16x4 steps: operand A[i][k] and B[k][j] come from
+// lane 16 k + i (resp. 16 k + j).  FP64 form: FP64 accumulators (8 VGPRs per
+// block), register r of lane 16 g + j holds row g + 4 r, column j; a tile of
+// 10 x 10 blocks.  FP32 form: FP32 accumulators (4 VGPRs per block; the
+// products are of FP32 values and a run of pairs sums at most a few thousand
+// of them per entry), register r of lane 16 g + j holds row 4 g + r; the same
+// registers then hold 14 x 14 blocks, so windows up to 224 bins (four k_perp
+// rows of 50 k_par bins) take one pass.
+template <typename T> struct DTile;
+template <> struct DTile<double> {
+  static constexpr int NB = 10, BI = 5, NFC = 2;
+  using Acc = mf_d4;
+  __device__ __forceinline__ static int row(int g, int r) { return g + 4 * r; }
+  __device__ __forceinline__ static Acc mfma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct DTile<float> {
+  static constexpr int NB = 14, BI = 7, NFC = 3;
+  using Acc = mf_f4;
+  __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+  __device__ __forceinline__ static Acc mfma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+// Block ownership.  The 8 waves (wx, wy) = (w & 1, w >> 1) share NB x NB blocks:
+// wave (wx, wy) owns block rows wx + 2 i (i < BI) of the NFC full block columns
+// wy + 4 k, and rows i < SP (wy < 2) or i >= SP (wy >= 2) of the extra column
+// 4 NFC + (wy & 1).  Slot j < NF is (row j / NFC, column k = j % NFC); slot
+// j >= NF is row j - NF (wy < 2) or j - NF + SP (wy >= 2) of the extra column.
+template <typename T> struct DLay {
+  static constexpr int NB = DTile<T>::NB, BI = DTile<T>::BI, NFC = DTile<T>::NFC;
+  static constexpr int TW = NB * kBlk;                // window bins per tile side
+  static constexpr int NF = BI * NFC;                 // slots in full columns
+  static constexpr int SP = (BI + 1) / 2;             // extra-column rows of waves wy < 2
+  static constexpr int MB = NF + SP;                  // slots per wave (at most)
+  static constexpr int BPW = MB <= 16 ? 16 : 32;      // ballot bits per wave
+  static constexpr int WPW = 64 / BPW, NWORD = kNW * BPW / 64;
+  __host__ __device__ static constexpr int slot_i(int j, bool low) {
+    return j < NF ? j / NFC : (low ? j - NF : j - NF + SP);
+  }
+  __host__ __device__ static constexpr int slot_k(int j) { return j < NF ? j % NFC : NFC; }
+  __host__ __device__ static constexpr bool slot_ok(int j, bool low) { return j < MB && slot_i(j, low) < BI; }
+  __host__ __device__ static constexpr int col(int wy, int k) { return k < NFC ? wy + 4 * k : 4 * NFC + (wy & 1); }
+  __host__ __device__ static constexpr int bx(int wx, bool low, int j) { return wx + 2 * slot_i(j, low); }
+  __host__ __device__ static constexpr int by(int wy, int j) { return col(wy, slot_k(j)); }
+};
 
 template <int N> struct IC { static constexpr int value = N; };
 
@@ -100,6 +126,7 @@ template <typename T, int NW>
 struct DSmem {
   static constexpr int NR = NW * kRPW;  // rows per group
   static constexpr int S = DCfg<T>::kStage;
+  static constexpr int kTileW = DLay<T>::TW;
   T sd[S], sw[S], sa[S];  // staged pixels of the forest the lanes sweep
   // R^0, R^1 of each row of the group over the tile's x range, and over its y
   // range when that differs.  FP64 in both forms: LDS FP64 atomic adds run at
@@ -108,20 +135,24 @@ struct DSmem {
   double rowG[NR][2][kTileW];
   T rw[NR];                 // -w of each row (0: no row)
   T rowc[NR][4];            // w, w a, u, b of each sweep-1 row
-  uint64_t act[NR][2];      // block bits of each row: 128 / NW bits per wave
+  uint64_t act[NR][DLay<T>::NWORD];  // block bits of each row: BPW bits per wave
   T H[4][kTileW];           // pair histograms, written after sweep 1
   T Q[4][kTileW];
-  double wdacc[kTileW];
+  double wdacc[kTileW];     // w_A over the run (first column pass)
+  double dacc[kTileW];      // the Kronecker term w_A [A = B] of diagonal passes
   int32_t ox[kTileW], oy[kTileW];  // output bin index of each tile row / column
   int32_t rng[4];                  // pixels of f, g within reach of the other forest: [lo, hi]
+  uint16_t bal[DLay<T>::NWORD][64];  // (block row | block column << 8) of ballot lane, 31 = none
+  unsigned long long nalg;         // outer-product FMAs counted (statistics)
   int64_t item;
 };
 
-// OR of a kNBlk-bit mask over the wave, one ballot per bit (no LDS round trips).
+// OR of an NB-bit mask over the wave, one ballot per bit (no LDS round trips).
+template <int NB>
 __device__ __forceinline__ uint32_t wave_or_blocks(uint32_t v) {
   uint32_t r = 0;
 #pragma unroll
-  for (int b = 0; b < kNBlk; ++b) r |= (__ballot((v >> b) & 1u) != 0ull) ? (1u << b) : 0u;
+  for (int b = 0; b < NB; ++b) r |= (__ballot((v >> b) & 1u) != 0ull) ? (1u << b) : 0u;
   return r;
 }
 
@@ -139,11 +170,15 @@ template <typename T, int BLOCK, bool ZLO>
 __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   using Cfg = DCfg<T>;
   using Rec = typename Cfg::Rec;
-  constexpr int NW = BLOCK / 64, S = Cfg::kStage, TW = kTileW;
+  using Lay = DLay<T>;
+  using Tile = DTile<T>;
+  using Acc = typename Tile::Acc;
+  constexpr int NW = BLOCK / 64, S = Cfg::kStage, TW = Lay::TW;
   constexpr int RPW = kRPW, NR = NW * RPW;
-  constexpr int BPW = 128 / NW, WPW = 64 / BPW;  // ballot bits per wave, waves per 64-bit word
+  constexpr int BPW = Lay::BPW, WPW = Lay::WPW, NWORD = Lay::NWORD;
+  constexpr int BI = Lay::BI, NF = Lay::NF, NFC = Lay::NFC, SP = Lay::SP, MB = Lay::MB;
   constexpr bool kF32 = sizeof(T) == 4;
-  static_assert(NW == kNW && kMB <= BPW, "wave layout");
+  static_assert(NW == kNW && MB <= BPW && MB < 32, "wave layout");
   static_assert(NR % 2 == 0, "two rows per MFMA step");
   __shared__ DSmem<T, NW> sm;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -158,24 +193,23 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
   const Rec* __restrict__ recs;
   if constexpr (kF32) recs = a.drec32; else recs = a.drec64;
 
-  // this lane's (wave, slot) in the row activity ballots: word h covers waves 4h..4h+3
-  int bal_x[2], bal_y[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int W = WPW * h + lane / BPW, j = lane % BPW;
+  // (wave, slot) of each lane in the row activity ballots: word h covers waves
+  // WPW h .. WPW h + WPW - 1 (a table in LDS rather than registers)
+  for (int e = tid; e < NWORD * 64; e += BLOCK) {
+    const int h = e >> 6, l = e & 63;
+    const int W = WPW * h + l / BPW, j = l % BPW;
     const bool lw = (W >> 1) < 2;
-    const bool ok = slot_ok(j, lw);
-    const int bx = ok ? slot_bx(W & 1, lw, j) : 0, by = ok ? slot_by(W >> 1, j) : 0;
-    bal_x[h] = ok ? bx : 31;
-    bal_y[h] = ok ? by : 31;
+    const bool ok = Lay::slot_ok(j, lw);
+    sm.bal[h][l] = ok ? (uint16_t)(Lay::bx(W & 1, lw, j) | (Lay::by(W >> 1, j) << 8)) : (uint16_t)(31 | (31 << 8));
   }
+  if (tid == 0) sm.nalg = 0;
 
   for (int e = tid; e < NR * 2 * TW; e += BLOCK) {
     (&sm.rowR[0][0][0])[e] = 0;
     (&sm.rowG[0][0][0])[e] = 0;
   }
-  unsigned long long n_in = 0, n_alg = 0, n_lost = 0;  // statistics only
-  mf_d4 cacc[kMB];  // FP64 MFMA accumulators of the wave's blocks
+  unsigned n_in = 0, n_lost = 0;  // statistics only
+  Acc cacc[MB];  // MFMA accumulators of the wave's blocks
 
   for (;;) {
     __syncthreads();  // every thread has read the previous item
@@ -213,10 +247,11 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
           const int nbx = (na + kBlk - 1) / kBlk, nby = (nbk + kBlk - 1) / kBlk;
           const bool diag = a0 == b0;  // both axes cover the same window bins
 #pragma unroll
-          for (int j = 0; j < kMB; ++j) cacc[j] = mf_d4{0.0, 0.0, 0.0, 0.0};
+          for (int j = 0; j < MB; ++j) cacc[j] = Acc{0, 0, 0, 0};
           __syncthreads();  // the previous pass's flush has read the index tables
           for (int x = tid; x < TW; x += BLOCK) {
             sm.wdacc[x] = 0.0;
+            sm.dacc[x] = 0.0;
             sm.ox[x] = x < na ? out_index(a0 + x + base_L, NP, NT) : -1;
             sm.oy[x] = x < nbk ? out_index(b0 + x + base_L, NP, NT) : -1;
           }
@@ -319,28 +354,29 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
               // lane qq < RPW of each wave holds the record of the wave's row qq of
               // the next group (loaded one group ahead)
               T pd = 0, pw = 0, pa = 0, pu = 0, pb = 0;
-              double pD = 0.0;
               auto fetch = [&](int gn) {
                 const int row = gn + wave * RPW + lane;
                 if (lane < RPW && row < nr) {
                   const Rec r = recs[prow0 + row];
                   pd = r.d; pw = r.w; pa = r.a; pu = r.u; pb = r.b;
-                  if constexpr (kF32) pD = r.D;
                 }
               };
               fetch(0);
               for (int g0 = 0; g0 < nr; g0 += NR) {
-                T gd[RPW], gw[RPW], ga[RPW], gu[RPW], gb[RPW];
-                double gD[RPW];
-#pragma unroll
-                for (int qq = 0; qq < RPW; ++qq) {
-                  gd[qq] = lane_val(pd, qq);
-                  gw[qq] = lane_val(pw, qq);
-                  ga[qq] = lane_val(pa, qq);
-                  gu[qq] = lane_val(pu, qq);
-                  gb[qq] = lane_val(pb, qq);
-                  gD[qq] = kF32 ? lane_val(pD, qq) : 0.0;
+                // the group's row factors go to LDS right away (the previous group's
+                // readers finished before the barrier that preceded its clearing)
+                if (lane < RPW) {
+                  const int slot = wave * RPW + lane;
+                  const bool ok = g0 + slot < nr;
+                  sm.rw[slot] = ok ? -pw : (T)0;
+                  sm.rowc[slot][0] = ok ? pw : (T)0;
+                  sm.rowc[slot][1] = ok ? pw * pa : (T)0;
+                  sm.rowc[slot][2] = ok ? pu : (T)0;
+                  sm.rowc[slot][3] = ok ? pb : (T)0;
                 }
+                T gd[RPW];
+#pragma unroll
+                for (int qq = 0; qq < RPW; ++qq) gd[qq] = lane_val(pd, qq);
                 if (g0 + NR < nr) fetch(g0 + NR);
                 uint32_t bx[RPW], by[RPW];
 #pragma unroll
@@ -367,7 +403,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                       if (!K.may_be_in(rp, rt)) continue;
                       const int L = K.bin_near(rp, rt, [&](double& rp64, double& rt64) {
                         if constexpr (kF32) {
-                          separations64(gD[qq], recs[poth0 + c0 + j].D, c64, s64, rp64, rt64);
+                          separations64(recs[prow0 + g0 + slot].D, recs[poth0 + c0 + j].D, c64, s64, rp64, rt64);
                         } else {
                           rp64 = rp;
                           rt64 = rt;
@@ -396,27 +432,15 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 }
 #pragma unroll
                 for (int qq = 0; qq < RPW; ++qq) {
-                  const int slot = wave * RPW + qq, row = g0 + slot;
-                  if (lane == 0) {
-                    if (row < nr) {
-                      sm.rw[slot] = -gw[qq];
-                      sm.rowc[slot][0] = gw[qq];
-                      sm.rowc[slot][1] = gw[qq] * ga[qq];
-                      sm.rowc[slot][2] = gu[qq];
-                      sm.rowc[slot][3] = gb[qq];
-                    } else {
-                      sm.rw[slot] = 0;
-                      sm.rowc[slot][0] = sm.rowc[slot][1] = sm.rowc[slot][2] = sm.rowc[slot][3] = 0;
-                    }
-                  }
-                  const uint32_t bxq = wave_or_blocks(bx[qq]);
-                  const uint32_t byq = diag ? bxq : wave_or_blocks(by[qq]);
+                  const int slot = wave * RPW + qq;
+                  const uint32_t bxq = wave_or_blocks<Lay::NB>(bx[qq]);
+                  const uint32_t byq = diag ? bxq : wave_or_blocks<Lay::NB>(by[qq]);
                   // block bits of every wave for this row
-                  const uint64_t w0 = __ballot(((bxq >> bal_x[0]) & (byq >> bal_y[0]) & 1u) != 0u);
-                  const uint64_t w1 = __ballot(((bxq >> bal_x[1]) & (byq >> bal_y[1]) & 1u) != 0u);
-                  if (lane == 0) {
-                    sm.act[slot][0] = w0;
-                    sm.act[slot][1] = w1;
+#pragma unroll
+                  for (int h = 0; h < NWORD; ++h) {
+                    const unsigned bl = sm.bal[h][lane];
+                    const uint64_t wb = __ballot(((bxq >> (bl & 0xffu)) & (byq >> (bl >> 8)) & 1u) != 0u);
+                    if (lane == 0) sm.act[slot][h] = wb;
                   }
                 }
                 __syncthreads();
@@ -426,28 +450,28 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                   const int slot_l = lk >> 1, comp = lk & 1;
                   const double* pa = &sm.rowR[slot_l][comp][wx * kBlk + lm];
                   const double* pb = diag ? &sm.rowR[slot_l][comp][wy * kBlk + lm] : &sm.rowG[slot_l][comp][wy * kBlk + lm];
-                  const int c3 = (8 + (wy & 1) - wy) * kBlk;  // third column, relative to pb
+                  const int cx = (4 * NFC + (wy & 1) - wy) * kBlk;  // extra column, relative to pb
                   const double gs = gsc[1 - RS][comp];
 #pragma unroll 1
                   for (int st = 0; st < NR / 2; ++st) {
                     const uint32_t bits = __builtin_amdgcn_readfirstlane(
                         (uint32_t)((sm.act[2 * st][wave / WPW] | sm.act[2 * st + 1][wave / WPW]) >>
                                    (BPW * (wave % WPW))) &
-                        ((1u << kMB) - 1u));
+                        ((1u << MB) - 1u));
                     if (bits == 0u) continue;
                     const int so = 2 * st * 2 * TW;  // two rows further per step
                     const double wr = (double)sm.rw[2 * st + slot_l];
-                    double av[kBI], bv[3];
+                    T av[BI], bv[NFC + 1];
 #pragma unroll
-                    for (int i = 0; i < kBI; ++i) av[i] = wr * (double)pa[so + 2 * kBlk * i];
-                    bv[0] = gs * pb[so];
-                    bv[1] = gs * pb[so + 4 * kBlk];
-                    bv[2] = gs * pb[so + c3];
+                    for (int i = 0; i < BI; ++i) av[i] = (T)(wr * pa[so + 2 * kBlk * i]);
 #pragma unroll
-                    for (int j = 0; j < kMB; ++j)
+                    for (int k = 0; k < NFC; ++k) bv[k] = (T)(gs * pb[so + 4 * kBlk * k]);
+                    bv[NFC] = (T)(gs * pb[so + cx]);
+#pragma unroll
+                    for (int j = 0; j < MB; ++j)
                       if ((bits >> j) & 1u) {
-                        const double aj = j < 10 ? av[j >> 1] : (low ? av[j - 10] : av[j - 7 < kBI ? j - 7 : kBI - 1]);
-                        cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj, bv[slot_k(j)], cacc[j], 0, 0, 0);
+                        const T aj = j < NF ? av[j / NFC] : (low ? av[j - NF] : av[j - NF + SP < BI ? j - NF + SP : BI - 1]);
+                        cacc[j] = Tile::mfma(aj, bv[Lay::slot_k(j)], cacc[j]);
                       }
                   }
                 }
@@ -488,7 +512,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                     sm.rowG[slot][0][x] = sm.rowG[slot][1][x] = 0;
                   }
                   if (diag) cy = cx;
-                  if (a.counters && lane == 0) n_alg += 2ull * (unsigned long long)cx * (unsigned long long)cy;
+                  if (a.counters && lane == 0) atomicAdd(&sm.nalg, 2ull * (unsigned long long)cx * (unsigned long long)cy);
                 }
               }
             };
@@ -519,22 +543,17 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
             __syncthreads();
             // ---- H (x) Q: one more step; the Kronecker term on the diagonal; w_A
             {
-              double av[kBI], bv[3];
+              T av[BI], bv[NFC + 1];
 #pragma unroll
-              for (int i = 0; i < kBI; ++i) av[i] = (double)sm.H[lk][(wx + 2 * i) * kBlk + lm];
+              for (int i = 0; i < BI; ++i) av[i] = sm.H[lk][(wx + 2 * i) * kBlk + lm];
 #pragma unroll
-              for (int k = 0; k < 3; ++k) bv[k] = (double)sm.Q[lk][slot_by(wy, k < 2 ? k : 10) * kBlk + lm];
+              for (int k = 0; k <= NFC; ++k) bv[k] = sm.Q[lk][Lay::col(wy, k) * kBlk + lm];
 #pragma unroll
-              for (int j = 0; j < kMB; ++j) {
-                const int bx = slot_bx(wx, low, j), by = slot_by(wy, j);
-                if (slot_ok(j, low) && bx < nbx && by < nby) {
-                  const double aj = j < 10 ? av[j >> 1] : (low ? av[j - 10] : av[j - 7 < kBI ? j - 7 : kBI - 1]);
-                  cacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(aj, bv[slot_k(j)], cacc[j], 0, 0, 0);
-                  if (a0 == b0 && bx == by) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                      if (mfma_row(lk, r) == lm) cacc[j][r] += (double)sm.H[0][bx * kBlk + lm];
-                  }
+              for (int j = 0; j < MB; ++j) {
+                const int bx = Lay::bx(wx, low, j), by = Lay::by(wy, j);
+                if (Lay::slot_ok(j, low) && bx < nbx && by < nby) {
+                  const T aj = j < NF ? av[j / NFC] : (low ? av[j - NF] : av[j - NF + SP < BI ? j - NF + SP : BI - 1]);
+                  cacc[j] = Tile::mfma(aj, bv[Lay::slot_k(j)], cacc[j]);
                 }
               }
             }
@@ -544,10 +563,12 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                 hx += __popcll(__ballot(x < na && sm.H[0][x] != (T)0));
                 qy += __popcll(__ballot(x < nbk && ((sm.Q[0][x] != (T)0) | (sm.Q[3][x] != (T)0))));
               }
-              if (lane == 0) n_alg += 4ull * (unsigned long long)hx * (unsigned long long)qy;
+              if (lane == 0) atomicAdd(&sm.nalg, 4ull * (unsigned long long)hx * (unsigned long long)qy);
             }
-            if (bb == 0)
-              for (int x = tid; x < na; x += BLOCK) sm.wdacc[x] += (double)sm.H[0][x];
+            for (int x = tid; x < na; x += BLOCK) {
+              if (bb == 0) sm.wdacc[x] += (double)sm.H[0][x];
+              if (a0 == b0) sm.dacc[x] += (double)sm.H[0][x];
+            }
 
             // ---- sweep 2: rows j of g
             sweep(IC<1>{});
@@ -556,37 +577,42 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
 
           // ---- add the wave's blocks to the global numerator (and w_A)
 #pragma unroll
-          for (int j = 0; j < kMB; ++j) {
-            const int bx = slot_bx(wx, low, j), by = slot_by(wy, j);
-            if (slot_ok(j, low) && bx < nbx && by < nby) {
+          for (int j = 0; j < MB; ++j) {
+            const int bx = Lay::bx(wx, low, j), by = Lay::by(wy, j);
+            if (Lay::slot_ok(j, low) && bx < nbx && by < nby) {
               const int oy = sm.oy[by * kBlk + lm];
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int ox = sm.ox[bx * kBlk + mfma_row(lk, r)];
-                const double v = cacc[j][r];
+                const int ox = sm.ox[bx * kBlk + Tile::row(lk, r)];
+                const double v = (double)cacc[j][r];
                 if (ox >= 0 && oy >= 0 && v != 0.0) atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
               }
             }
           }
-          if (bb == 0)
-            for (int x = tid; x < na; x += BLOCK)
-              if (sm.wdacc[x] != 0.0) atomicAdd(&a.wd[obase + sm.ox[x]], sm.wdacc[x]);
+          // the Kronecker term w_A [A = B] on the diagonal of diagonal passes, and w_A
+          for (int x = tid; x < na; x += BLOCK) {
+            const int ox = sm.ox[x];
+            if (a0 == b0 && sm.dacc[x] != 0.0) atomicAdd(&a.dnum[(obase + ox) * nb + ox], sm.dacc[x]);
+            if (bb == 0 && sm.wdacc[x] != 0.0) atomicAdd(&a.wd[obase + ox], sm.wdacc[x]);
+          }
         }
       }
       r0 = r1;
     }
   }
   if (a.counters) {
+    unsigned long long ni = n_in, nl = n_lost;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      n_in += __shfl_xor(n_in, o, 64);
-      n_lost += __shfl_xor(n_lost, o, 64);
+      ni += __shfl_xor(ni, o, 64);
+      nl += __shfl_xor(nl, o, 64);
     }
     if (lane == 0) {
-      atomicAdd(&a.counters[0], n_in);
-      atomicAdd(&a.counters[1], n_alg);
-      atomicAdd(&a.counters[2], n_lost);
+      atomicAdd(&a.counters[0], ni);
+      atomicAdd(&a.counters[2], nl);
     }
+    __syncthreads();
+    if (tid == 0) atomicAdd(&a.counters[1], sm.nalg);
   }
 }
 

@@ -137,12 +137,14 @@ def test_config1_compact_subpatch(lib, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_windows_wider_than_one_tile(lib, prec):
-    """100 r_par bins make every r_perp window 100 or 200 bins wide; the
-    wider ones are covered by several tiles (and several passes per run)."""
+@pytest.mark.parametrize("n_par", [100, 120])
+def test_windows_wider_than_one_tile(lib, prec, n_par):
+    """n_par r_par bins of 2 Mpc/h make every r_perp window n_par, 2 n_par or
+    3 n_par bins wide; windows wider than a tile (160 bins in the FP64 form,
+    224 in the FP32 form) are covered by several tiles and passes per run."""
     F, _, _ = make_config(1, seed=3, scale=0.02)
     S = subset_forests(F, nearest_to_centre(F, 40))
-    G = uniform_grid(100, 200.0, 12, 60.0)
+    G = uniform_grid(n_par, 2.0 * n_par, 12, 60.0)
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
     for v in (0,):
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
