@@ -867,3 +867,200 @@ def err_norm(test, ref):
     ref = np.asarray(ref, np.float64)
     s = float(np.max(np.abs(ref)))
     return float(np.max(np.abs(np.asarray(test, np.float64) - ref)) / (s if s else 1.0))
+
+
+# ---------------------------------------------------------------------------
+# anisotropic three-point function (Sec. 2.3, eq. estimator_three)
+# ---------------------------------------------------------------------------
+#
+# xi3_A = sum_A w_i d_i w_j d_j w_k d_k / sum_A w_i w_j w_k over triplets of
+# pixels from three distinct forests (quasars).  A triangle is described from
+# one vertex i by its two sides r1 = x_j - x_i and r2 = x_k - x_i (x = D n):
+# their lengths r1, r2, their angles theta1, theta2 to the line of sight, and
+# the cosine of the opening angle alpha between them (Sec. 2.3 and the 3PCF
+# figure, which bins r in [0, r_max), theta in [0, pi] and cos alpha in
+# [-1, 1]).  Readings where the paper is silent:
+#  * the line of sight is the direction of the vertex's quasar, n_f(i);
+#  * every vertex of a triplet is used (the paper records the same triangle
+#    for each choice of main vertex) and both orders of the two sides, so an
+#    unordered triplet enters six times and the histogram is symmetric under
+#    (r1, theta1) <-> (r2, theta2);
+#  * r bins are half-open [e_k, e_k+1) with r >= r_max outside; theta and
+#    cos alpha bins are half-open except the last, which is closed (theta = pi,
+#    cos alpha = 1 belong to the grid);
+#  * a side of zero length has no direction: such triplets are left out;
+#  * the flat index follows the figure's order (r1, r2, cos alpha, theta1,
+#    theta2): A = (((k_r1 n_r + k_r2) n_c + k_c) n_t + k_t1) n_t + k_t2.
+
+
+@dataclass
+class Grid3:
+    r_edges: np.ndarray      # side lengths, Mpc/h, strictly increasing, r_edges[0] >= 0
+    theta_edges: np.ndarray  # angle of a side to the line of sight, radians, 0 .. pi
+    cos_edges: np.ndarray    # cosine of the opening angle, -1 .. 1
+
+    @property
+    def n_r(self):
+        return len(self.r_edges) - 1
+
+    @property
+    def n_t(self):
+        return len(self.theta_edges) - 1
+
+    @property
+    def n_c(self):
+        return len(self.cos_edges) - 1
+
+    @property
+    def n_bins(self):
+        return self.n_r * self.n_r * self.n_c * self.n_t * self.n_t
+
+    def index(self, kr1, kr2, kc, kt1, kt2):
+        return (((kr1 * self.n_r + kr2) * self.n_c + kc) * self.n_t + kt1) * self.n_t + kt2
+
+
+def closed_bin_index(x, edges):
+    """k with edges[k] <= x < edges[k+1], the last bin closed at edges[-1];
+    -1 outside [edges[0], edges[-1]]."""
+    edges = np.asarray(edges, np.float64)
+    n = edges.shape[0] - 1
+    k = np.searchsorted(edges, x, side="right") - 1
+    k = np.where(np.asarray(x) == edges[-1], n - 1, k)
+    return np.where((k >= 0) & (k < n), k, -1)
+
+
+@dataclass
+class Xi3Sums:
+    num: np.ndarray      # [R, n_bins] sum w_i d_i w_j d_j w_k d_k
+    wsum: np.ndarray     # [R, n_bins] sum w_i w_j w_k
+    ntrip: np.ndarray    # [R, n_bins] number of (vertex, side, side) entries
+    n_near_edge: int     # entries with a coordinate within tau of an interior edge
+
+    @property
+    def xi(self):
+        return xi_from_sums(self.num, self.wsum)
+
+
+def _near(x, e, tau):
+    """True where x lies within tau of one of the edges e."""
+    e = np.asarray(e, np.float64)
+    if e.size == 0:
+        return np.zeros(np.shape(x), bool)
+    return np.any(np.abs(np.asarray(x)[..., None] - e) <= np.asarray(tau)[..., None], axis=-1)
+
+
+def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
+    """Triplet sums of eq. estimator_three, vertex by vertex.
+
+    For a vertex pixel i the partners are the pixels of every other forest of
+    its realisation with side length in [r_edges[0], r_edges[-1]) (and > 0);
+    each ordered pair of partners from two different forests is one entry.
+    The per-vertex histograms are combined with Neumaier summation.
+    """
+    R = max(1, int(F.n_realisations))
+    nb = g3.n_bins
+    rmax = float(g3.r_edges[-1])
+    n_vec = unit_vectors(F.ra, F.dec)
+    fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+    pos = F.dist[:, None] * n_vec[fid]
+    wd = F.weight * F.delta
+    real = F.real_of()
+    num = _Neumaier((R, nb))
+    wsum = _Neumaier((R, nb))
+    cnt = np.zeros((R, nb), np.int64)
+    n_near = 0
+    # candidate forests: pairs that can hold a side shorter than r_max
+    from types import SimpleNamespace
+    box = SimpleNamespace(edges_par=np.array([0.0, rmax]), edges_perp=np.array([0.0, rmax]))
+    nbrs = [[] for _ in range(F.n_forests)]
+    for f, g in forest_pairs(F, box, prune=True):
+        nbrs[int(f)].append(int(g))
+        nbrs[int(g)].append(int(f))
+    for f in range(F.n_forests):
+        if not nbrs[f] or F.offsets[f + 1] == F.offsets[f]:
+            continue
+        g_list = np.array(sorted(nbrs[f]), np.int64)
+        idx = np.concatenate([np.arange(F.offsets[g], F.offsets[g + 1]) for g in g_list])
+        r = int(real[f])
+        los = n_vec[f]
+        for i in range(F.offsets[f], F.offsets[f + 1]):
+            d = pos[idx] - pos[i]
+            rr = np.sqrt(np.sum(d * d, axis=1))
+            kr = bin_index_1d(rr, g3.r_edges)
+            keep = (kr >= 0) & (rr > 0.0)
+            if np.count_nonzero(keep) < 2:
+                continue
+            p = idx[keep]
+            kr = kr[keep]
+            rr = rr[keep]
+            u = d[keep] / rr[:, None]
+            ct = np.clip(u @ los, -1.0, 1.0)
+            th = np.arccos(ct)
+            kt = closed_bin_index(th, g3.theta_edges)
+            ca = np.clip(u @ u.T, -1.0, 1.0)
+            kc = closed_bin_index(ca, g3.cos_edges)
+            ok = fid[p][:, None] != fid[p][None, :]
+            A = g3.index(kr[:, None], kr[None, :], kc, kt[:, None], kt[None, :])[ok]
+            num.add(np.bincount(A, weights=(wd[i] * wd[p][:, None] * wd[p][None, :])[ok], minlength=nb), where=(r,))
+            wsum.add(np.bincount(A, weights=(F.weight[i] * F.weight[p][:, None] * F.weight[p][None, :])[ok],
+                                 minlength=nb), where=(r,))
+            cnt[r] += np.bincount(A, minlength=nb)
+            if edge_tau > 0:
+                re = g3.r_edges if g3.r_edges[0] > 0 else g3.r_edges[1:]
+                side_near = (_near(rr, re, edge_tau * np.maximum(1.0, rr))
+                             | _near(th, g3.theta_edges[1:-1], edge_tau))
+                pair_near = (side_near[:, None] | side_near[None, :]
+                             | _near(ca, g3.cos_edges[1:-1], edge_tau))
+                n_near += int(np.count_nonzero(pair_near[ok]))
+    return Xi3Sums(num.value(), wsum.value(), cnt, n_near)
+
+
+def xi3_brute(F, g3: Grid3):
+    """Pure-Python loop over ordered pixel triplets (i; j, k) of three distinct
+    forests (tiny inputs), with every angle from math.acos and every bin found
+    by scanning the edge list."""
+    import math
+    R = max(1, int(F.n_realisations))
+    nb = g3.n_bins
+    real = F.real_of()
+    fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+    nv = unit_vectors(F.ra, F.dec)
+    P = [[float(F.dist[i]) * float(nv[fid[i]][a]) for a in range(3)] for i in range(F.n_pix)]
+
+    def scan(x, edges, closed):
+        for k in range(len(edges) - 1):
+            if edges[k] <= x < edges[k + 1] or (closed and k == len(edges) - 2 and x == edges[-1]):
+                return k
+        return -1
+
+    num = [[[] for _ in range(nb)] for _ in range(R)]
+    ws = [[[] for _ in range(nb)] for _ in range(R)]
+    cnt = np.zeros((R, nb), np.int64)
+    for i in range(F.n_pix):
+        los = [float(v) for v in nv[fid[i]]]
+        side = {}
+        for j in range(F.n_pix):
+            if fid[j] == fid[i] or real[fid[j]] != real[fid[i]]:
+                continue
+            d = [P[j][a] - P[i][a] for a in range(3)]
+            r = math.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+            kr = scan(r, list(g3.r_edges), False)
+            if kr < 0 or r == 0.0:
+                continue
+            u = [v / r for v in d]
+            th = math.acos(max(-1.0, min(1.0, sum(u[a] * los[a] for a in range(3)))))
+            side[j] = (kr, scan(th, list(g3.theta_edges), True), u)
+        for j, (kr1, kt1, u1) in side.items():
+            for k, (kr2, kt2, u2) in side.items():
+                if fid[j] == fid[k]:
+                    continue
+                ca = max(-1.0, min(1.0, sum(u1[a] * u2[a] for a in range(3))))
+                kc = scan(ca, list(g3.cos_edges), True)
+                A = (((kr1 * g3.n_r + kr2) * g3.n_c + kc) * g3.n_t + kt1) * g3.n_t + kt2
+                r = int(real[fid[i]])
+                num[r][A].append(float(F.weight[i] * F.delta[i] * F.weight[j] * F.delta[j] * F.weight[k] * F.delta[k]))
+                ws[r][A].append(float(F.weight[i] * F.weight[j] * F.weight[k]))
+                cnt[r, A] += 1
+    N_ = np.array([[math.fsum(v) for v in row] for row in num])
+    W_ = np.array([[math.fsum(v) for v in row] for row in ws])
+    return N_, W_, cnt

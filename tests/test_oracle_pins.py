@@ -591,3 +591,85 @@ def test_covariance_properties():
     np.testing.assert_allclose(cov2, 9.0 * cov, rtol=1e-12, atol=0)   # quadratic in N
     _, cov1 = O.covariance(num[:1], wsum[:1])
     assert np.abs(cov1).max() < 1e-28                         # one subsample: no scatter (rounding only)
+
+
+# ------------------------------------------------------ anisotropic 3PCF
+
+
+def _grid3(r_max=30.0, n_r=3, n_t=4, n_c=5):
+    return O.Grid3(np.linspace(0.0, r_max, n_r + 1), np.linspace(0.0, np.pi, n_t + 1),
+                   np.linspace(-1.0, 1.0, n_c + 1))
+
+
+def test_xi3_golden_handworked():
+    """One triplet of single-pixel forests binned by hand from each vertex and
+    both side orders (derivation in the fixture)."""
+    d = load_json("xi3_handworked_three_forests.json")
+    F = forests_from_dict(d["forests"])
+    g = d["grid3"]
+    G3 = O.Grid3(np.array(g["r_edges"]), np.array(g["theta_edges"]), np.array(g["cos_edges"]))
+    X = O.xi3_sums(F, G3)
+    exp = d["expected"]
+    assert G3.n_bins == exp["n_bins"]
+    assert np.nonzero(X.ntrip[0])[0].tolist() == exp["bins"]
+    assert np.all(X.ntrip[0][exp["bins"]] == exp["ntrip"])
+    assert np.allclose(X.num[0][exp["bins"]], exp["num"], rtol=1e-15)
+    assert np.allclose(X.wsum[0][exp["bins"]], exp["wsum"], rtol=1e-15)
+    assert X.n_near_edge == 0
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_xi3_vs_python_brute(seed):
+    """Vectorised triplet sums against a pure-Python loop over ordered
+    triplets (math.acos, edge scans)."""
+    F = tiny(seed, n_forests=5, k=5, width_deg=0.3)
+    G3 = _grid3()
+    X = O.xi3_sums(F, G3)
+    N_, W_, C_ = O.xi3_brute(F, G3)
+    assert X.n_near_edge == 0 and C_.sum() > 200
+    assert (X.ntrip == C_).all()
+    assert np.allclose(X.num, N_, rtol=1e-13, atol=1e-13 * np.abs(N_).max())
+    assert np.allclose(X.wsum, W_, rtol=1e-13, atol=1e-13 * np.abs(W_).max())
+
+
+def test_xi3_single_bin_closed_form():
+    """With one bin holding every triangle, the sums run over all ordered
+    triples of distinct forests: sum S_f S_g S_h = S1^3 - 3 S1 S2 + 2 S3 with
+    the power sums S_p = sum_f S_f^p of the per-forest sums S_f."""
+    F = tiny(4, n_forests=6, k=6, width_deg=0.3)
+    G3 = O.Grid3(np.array([0.0, 1e6]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
+    X = O.xi3_sums(F, G3)
+    fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+
+    def triple(a):
+        S = np.bincount(fid, weights=a, minlength=F.n_forests)
+        return S.sum() ** 3 - 3 * S.sum() * np.sum(S ** 2) + 2 * np.sum(S ** 3)
+    assert X.num[0, 0] == pytest.approx(triple(F.weight * F.delta), rel=1e-12)
+    assert X.wsum[0, 0] == pytest.approx(triple(F.weight), rel=1e-12)
+    assert X.ntrip[0, 0] == round(triple(np.ones(F.n_pix)))
+
+
+def test_xi3_symmetry_and_invariances():
+    """Both side orders are entered, so the sums are symmetric under
+    (r1, theta1) <-> (r2, theta2); delta -> -delta flips N, w -> 2 w scales N
+    and W by 8 and leaves xi3; a realisation id keeps triplets apart."""
+    F = tiny(2, n_forests=6, k=6, width_deg=0.3)
+    G3 = _grid3()
+    X = O.xi3_sums(F, G3)
+    sh = (G3.n_r, G3.n_r, G3.n_c, G3.n_t, G3.n_t)
+    N = X.num[0].reshape(sh)
+    assert np.allclose(N, N.transpose(1, 0, 2, 4, 3), rtol=1e-13, atol=1e-15 * np.abs(N).max())
+    assert np.array_equal(X.ntrip[0].reshape(sh), X.ntrip[0].reshape(sh).transpose(1, 0, 2, 4, 3))
+    Fm = F.copy()
+    Fm.delta = -Fm.delta
+    assert np.allclose(O.xi3_sums(Fm, G3).num, -X.num, rtol=1e-13, atol=1e-15 * np.abs(X.num).max())
+    F2 = F.copy()
+    F2.weight = 2.0 * F2.weight
+    X2 = O.xi3_sums(F2, G3)
+    assert np.allclose(X2.num, 8 * X.num, rtol=1e-13, atol=1e-15 * np.abs(X.num).max())
+    assert np.allclose(X2.xi, X.xi, rtol=1e-12, atol=1e-15)
+    from synth import concat_realisations
+    Rr = concat_realisations([F, F])
+    XR = O.xi3_sums(Rr, G3)
+    assert XR.ntrip.shape == (2, G3.n_bins)
+    assert np.array_equal(XR.ntrip[0], X.ntrip[0]) and np.array_equal(XR.ntrip[1], X.ntrip[0])
