@@ -935,6 +935,7 @@ class Xi3Sums:
     wsum: np.ndarray     # [R, n_bins] sum w_i w_j w_k
     ntrip: np.ndarray    # [R, n_bins] number of (vertex, side, side) entries
     n_near_edge: int     # entries with a coordinate within tau of an interior edge
+    absnum: Optional[np.ndarray] = None  # [R, n_bins] sum |w d w d w d| (conditioning)
 
     @property
     def xi(self):
@@ -967,6 +968,7 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
     real = F.real_of()
     num = _Neumaier((R, nb))
     wsum = _Neumaier((R, nb))
+    absn = _Neumaier((R, nb))
     cnt = np.zeros((R, nb), np.int64)
     n_near = 0
     # candidate forests: pairs that can hold a side shorter than r_max
@@ -997,11 +999,17 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
             ct = np.clip(u @ los, -1.0, 1.0)
             th = np.arccos(ct)
             kt = closed_bin_index(th, g3.theta_edges)
+            side = kt >= 0          # a side outside the theta range leaves the grid
+            if np.count_nonzero(side) < 2:
+                continue
+            p, kr, rr, u, th, kt = p[side], kr[side], rr[side], u[side], th[side], kt[side]
             ca = np.clip(u @ u.T, -1.0, 1.0)
             kc = closed_bin_index(ca, g3.cos_edges)
-            ok = fid[p][:, None] != fid[p][None, :]
+            ok = (fid[p][:, None] != fid[p][None, :]) & (kc >= 0)
             A = g3.index(kr[:, None], kr[None, :], kc, kt[:, None], kt[None, :])[ok]
-            num.add(np.bincount(A, weights=(wd[i] * wd[p][:, None] * wd[p][None, :])[ok], minlength=nb), where=(r,))
+            prod = (wd[i] * wd[p][:, None] * wd[p][None, :])[ok]
+            num.add(np.bincount(A, weights=prod, minlength=nb), where=(r,))
+            absn.add(np.bincount(A, weights=np.abs(prod), minlength=nb), where=(r,))
             wsum.add(np.bincount(A, weights=(F.weight[i] * F.weight[p][:, None] * F.weight[p][None, :])[ok],
                                  minlength=nb), where=(r,))
             cnt[r] += np.bincount(A, minlength=nb)
@@ -1012,7 +1020,7 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
                 pair_near = (side_near[:, None] | side_near[None, :]
                              | _near(ca, g3.cos_edges[1:-1], edge_tau))
                 n_near += int(np.count_nonzero(pair_near[ok]))
-    return Xi3Sums(num.value(), wsum.value(), cnt, n_near)
+    return Xi3Sums(num.value(), wsum.value(), cnt, n_near, absn.value())
 
 
 def xi3_brute(F, g3: Grid3):
@@ -1049,13 +1057,17 @@ def xi3_brute(F, g3: Grid3):
                 continue
             u = [v / r for v in d]
             th = math.acos(max(-1.0, min(1.0, sum(u[a] * los[a] for a in range(3)))))
-            side[j] = (kr, scan(th, list(g3.theta_edges), True), u)
+            kt = scan(th, list(g3.theta_edges), True)
+            if kt >= 0:
+                side[j] = (kr, kt, u)
         for j, (kr1, kt1, u1) in side.items():
             for k, (kr2, kt2, u2) in side.items():
                 if fid[j] == fid[k]:
                     continue
                 ca = max(-1.0, min(1.0, sum(u1[a] * u2[a] for a in range(3))))
                 kc = scan(ca, list(g3.cos_edges), True)
+                if kc < 0:
+                    continue
                 A = (((kr1 * g3.n_r + kr2) * g3.n_c + kc) * g3.n_t + kt1) * g3.n_t + kt2
                 r = int(real[fid[i]])
                 num[r][A].append(float(F.weight[i] * F.delta[i] * F.weight[j] * F.delta[j] * F.weight[k] * F.delta[k]))

@@ -618,12 +618,15 @@ def test_xi3_golden_handworked():
     assert X.n_near_edge == 0
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_xi3_vs_python_brute(seed):
+@pytest.mark.parametrize("seed,partial", [(0, False), (1, False), (1, True)])
+def test_xi3_vs_python_brute(seed, partial):
     """Vectorised triplet sums against a pure-Python loop over ordered
-    triplets (math.acos, edge scans)."""
+    triplets (math.acos, edge scans); also with theta and cos alpha grids that
+    cover only part of their range (sides and triangles outside drop out)."""
     F = tiny(seed, n_forests=5, k=5, width_deg=0.3)
     G3 = _grid3()
+    if partial:
+        G3 = O.Grid3(np.linspace(5.0, 30.0, 4), np.linspace(0.2, 2.0, 4), np.linspace(-0.5, 1.0, 4))
     X = O.xi3_sums(F, G3)
     N_, W_, C_ = O.xi3_brute(F, G3)
     assert X.n_near_edge == 0 and C_.sum() > 200
