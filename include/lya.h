@@ -206,6 +206,41 @@ lya_status lya_xi_covariance(lya_context *ctx, const double *num, const double *
                              int64_t n_sub, int64_t n_bins, void *stream,
                              double *xi, double *cov);
 
+/* Bins of the anisotropic three-point function (HOST pointers).  A triangle
+   is seen from a main vertex i by its sides r1 = x_j - x_i, r2 = x_k - x_i
+   (x = D n): side lengths on r_edges (uniform, r_edges[0] >= 0, half-open,
+   r >= r_max outside), the angles theta1, theta2 of the sides to the line of
+   sight of the vertex's quasar on theta_edges (strictly increasing within
+   [0, pi], any spacing), and the cosine of the inner angle on cos_edges
+   (uniform within [-1, 1]); theta and cos bins are half-open with the last
+   one closed.  Flat index
+     A = (((k_r1 n_r + k_r2) n_cos + k_cos) n_theta + k_theta1) n_theta + k_theta2
+   (the order of the paper's 3PCF figure), n_bins = n_r^2 n_cos n_theta^2 <= 2^30. */
+typedef struct {
+  int32_t n_r;
+  int32_t n_theta;
+  int32_t n_cos;
+  const double *r_edges;      /* [n_r + 1] */
+  const double *theta_edges;  /* [n_theta + 1], radians */
+  const double *cos_edges;    /* [n_cos + 1] */
+} lya_grid3;
+
+/* Triplet sums of the anisotropic 3PCF (Sec. 2.3, eq. estimator_three) over
+   triplets of pixels from three distinct forests of one realisation, every
+   vertex and both side orders entered (six entries per unordered triplet; a
+   side of zero length is left out).  Always FP64 (options.precision is
+   ignored); project_deltas / eta as for lya_xi.  Outputs, each
+   [n_realisations * n_bins], device:
+     num[A]   = sum_A w_i d_i w_j d_j w_k d_k
+     wsum[A]  = sum_A w_i w_j w_k
+     ntrip[A] = number of entries in A (any weight)
+     xi[A]    = num[A] / wsum[A], 0 where wsum[A] == 0   (may be NULL)
+   Returns LYA_E_UNSUPPORTED if a pixel has more than 3072 partner pixels with
+   a side in the r grid (the outputs are then incomplete). */
+lya_status lya_xi3(lya_context *ctx, const lya_forests *forests, const lya_grid3 *grid,
+                   const lya_options *opts, void *stream,
+                   double *num, double *wsum, int64_t *ntrip, double *xi);
+
 /* Distortion matrix (Sec. 2.2, eq. distortion) over the forest pairs kept by
    options.dmat_keep_fraction / seed, with eta of options.eta.  Outputs,
    device:

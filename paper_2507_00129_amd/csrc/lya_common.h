@@ -74,7 +74,7 @@ struct GridDev {
 // Validation error bits (Globals::flag).
 enum : int32_t {
   kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32,
-  kBadSub = 64
+  kBadSub = 64, kBadCap3 = 128
 };
 
 // ---------------------------------------------------------------- geometry
@@ -298,6 +298,33 @@ hipError_t launch_gamma(const double* grad_xi, const double* xi, const double* w
                         int64_t n, int NP, int NT, hipStream_t st);
 hipError_t launch_xi_bwd(int precision, const BwdArgs& a, int blocks, hipStream_t st);
 hipError_t launch_xi_means(int precision, const XiArgs& a, int blocks, hipStream_t st);
+
+// Three-point function (FP64): pixel positions and products, and the kernel.
+struct Point3 { double x, y, z, wd, w, pad; };
+struct Xi3Args {
+  const ForestInfo* finfo;
+  const int32_t* sorted;
+  const int32_t* nbr;
+  const Item* items;
+  int64_t n_items;
+  unsigned int* counter;
+  const Point3* pts;
+  Globals* glob;
+  int32_t n_r, n_t, n_c;
+  int64_t n_bins;
+  const double* r_edges;          // [n_r + 1]
+  const double* cos_theta_edges;  // [n_t + 1] cosines of the theta edges (decreasing)
+  const double* cos_edges;        // [n_c + 1]
+  double r_e0, r_inv, c_e0, c_inv;
+  double* num;
+  double* wsum;
+  unsigned long long* ntrip;
+};
+hipError_t launch_xi3_points(const lya_forests* F, const ForestInfo* finfo, const double* delta, Point3* pts,
+                             hipStream_t st);
+hipError_t launch_xi3(const Xi3Args& a, int blocks, hipStream_t st);
+int xi3_blocks_per_cu();
+int xi3_partner_capacity();
 int xi_means_blocks_per_cu(int precision, int n_bins);
 hipError_t launch_finalize_means(const double* wsum, const double* msum, int64_t n, const GridDev& g,
                                  double* rpar, double* rperp, double* z, hipStream_t st);

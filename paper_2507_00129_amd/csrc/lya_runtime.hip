@@ -629,6 +629,119 @@ lya_status lya_xi_covariance(lya_context* ctx, const double* num, const double* 
   return LYA_OK;
 }
 
+lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, const lya_options* o,
+                   void* stream, double* num, double* wsum, int64_t* ntrip, double* xi) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!G3) return fail(ctx, LYA_E_INVALID, "NULL grid");
+  double r_e0, r_inv, r_max;
+  LYA_TRY(check_axis(ctx, G3->r_edges, G3->n_r, "r", r_e0, r_inv, r_max));
+  const int nt = G3->n_theta, nc = G3->n_cos;
+  const double* te = G3->theta_edges;
+  const double* ce = G3->cos_edges;
+  if (!te || !ce) return fail(ctx, LYA_E_INVALID, "NULL theta_edges or cos_edges");
+  if (nt < 1 || nc < 1) return fail(ctx, LYA_E_INVALID, "n_theta and n_cos must be >= 1");
+  if (nt > 1024) return fail(ctx, LYA_E_UNSUPPORTED, "n_theta = %d exceeds 1024", nt);
+  for (int k = 0; k <= nt; ++k)
+    if (!isfinite(te[k]) || te[k] < 0.0 || te[k] > kPi || (k > 0 && !(te[k] > te[k - 1])))
+      return fail(ctx, LYA_E_INVALID, "theta_edges must increase strictly within [0, pi] (edge %d)", k);
+  for (int k = 0; k <= nc; ++k)
+    if (!isfinite(ce[k]) || ce[k] < -1.0 || ce[k] > 1.0 || (k > 0 && !(ce[k] > ce[k - 1])))
+      return fail(ctx, LYA_E_INVALID, "cos_edges must increase strictly within [-1, 1] (edge %d)", k);
+  const double cd = (ce[nc] - ce[0]) / nc;
+  for (int k = 0; k <= nc; ++k)
+    if (fabs(ce[k] - (ce[0] + k * cd)) > 1e-9 * cd)
+      return fail(ctx, LYA_E_UNSUPPORTED, "cos_edges are not uniformly spaced (edge %d)", k);
+  const int nr = G3->n_r;
+  const int64_t n_bins = (int64_t)nr * nr * nc * nt * nt;
+  if (n_bins > ((int64_t)1 << 30)) return fail(ctx, LYA_E_UNSUPPORTED, "%lld bins exceed 2^30", (long long)n_bins);
+  // forests and options are checked as for a pair grid that boxes every side
+  double box[2] = {0.0, r_max};
+  const lya_grid G{1, 1, box, box};
+  GridDev gd{};
+  LYA_TRY(check_common(ctx, F, &G, o, gd));
+  if (!num || !wsum || !ntrip) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or ntrip");
+  if ((int64_t)F->n_realisations * n_bins > ((int64_t)1 << 40))
+    return fail(ctx, LYA_E_UNSUPPORTED, "outputs too large");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->err.clear();
+  ctx->stats = lya_stats{};
+  const int64_t nout = (int64_t)F->n_realisations * n_bins;
+  Timer tm{ctx, st, o->timing != 0};
+  tm.at(0);
+  HIP_TRY(launch_zero(num, nout * sizeof(double), st));
+  HIP_TRY(launch_zero(wsum, nout * sizeof(double), st));
+  HIP_TRY(launch_zero(ntrip, nout * sizeof(int64_t), st));
+  if (F->n_forests > 0 && F->n_pix > 0) {
+    Prepared P;
+    const bool project = o->project_deltas != 0;
+    LYA_TRY(prepare(ctx, F, &G, gd, o, st, false, false, project, P));
+    Point3* pts;
+    LYA_TRY(wst(ctx, "xi3_pts", (size_t)F->n_pix, &pts));
+    HIP_TRY(launch_xi3_points(F, P.finfo, project ? P.delta_proj : F->delta, pts, st));
+    tm.at(1);
+    Worklist W;
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, true, false, 0, 0, false, INT32_MAX, "x3", W));
+    tm.at(2);
+    ctx->stats.forest_pairs = W.n_pairs;
+    ctx->stats.work_items = W.n_items;
+    ctx->stats.candidate_pairs = W.candidates;
+    // r edges, cosines of the theta edges, cos alpha edges
+    std::vector<double> he;
+    he.insert(he.end(), G3->r_edges, G3->r_edges + nr + 1);
+    for (int k = 0; k <= nt; ++k) he.push_back(k == 0 && te[0] == 0.0 ? 1.0 : (te[k] == kPi ? -1.0 : cos(te[k])));
+    he.insert(he.end(), ce, ce + nc + 1);
+    double* de;
+    LYA_TRY(wst(ctx, "xi3_edges", he.size(), &de));
+    HIP_TRY(hipMemcpyAsync(de, he.data(), he.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    unsigned int* counter;
+    LYA_TRY(wst(ctx, "xi3_counter", 1, &counter));
+    Xi3Args a{};
+    a.finfo = P.finfo;
+    a.sorted = W.sorted;
+    a.nbr = W.nbr;
+    a.items = W.items;
+    a.n_items = W.n_items;
+    a.counter = counter;
+    a.pts = pts;
+    a.glob = P.glob;
+    a.n_r = nr;
+    a.n_t = nt;
+    a.n_c = nc;
+    a.n_bins = n_bins;
+    a.r_edges = de;
+    a.cos_theta_edges = de + nr + 1;
+    a.cos_edges = de + nr + 1 + nt + 1;
+    a.r_e0 = r_e0;
+    a.r_inv = r_inv;
+    a.c_e0 = ce[0];
+    a.c_inv = 1.0 / cd;
+    a.num = num;
+    a.wsum = wsum;
+    a.ntrip = (unsigned long long*)ntrip;
+    const int blocks = xi3_blocks_per_cu() * ctx->n_cu;
+    ctx->stats.grid_blocks = blocks;
+    HIP_TRY(launch_zero(counter, 4, st));
+    tm.at(3);
+    HIP_TRY(launch_xi3(a, blocks, st));
+    tm.at(4);
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (*(int32_t*)ctx->pinned & kBadCap3)
+      return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel",
+                  xi3_partner_capacity());
+  } else {
+    tm.at(1);
+    tm.at(2);
+    tm.at(3);
+    tm.at(4);
+  }
+  HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
+  tm.at(5);
+  return tm.finish(ctx);
+}
+
 lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                     void* stream, double* dmat, double* wsum_d) {
   GridDev gd{};

@@ -46,6 +46,11 @@ class lya_grid(ctypes.Structure):
                 ("edges_par", ctypes.c_void_p), ("edges_perp", ctypes.c_void_p)]
 
 
+class lya_grid3(ctypes.Structure):
+    _fields_ = [("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_cos", ctypes.c_int32),
+                ("r_edges", ctypes.c_void_p), ("theta_edges", ctypes.c_void_p), ("cos_edges", ctypes.c_void_p)]
+
+
 class lya_options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32), ("eta", ctypes.c_int32), ("project_deltas", ctypes.c_int32),
@@ -97,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.lya_xi_backward.restype = I32
     lib.lya_xi_subsamples.argtypes = [P, FP, GP, OP, P, P, I32, P, P, P, P]
     lib.lya_xi_subsamples.restype = I32
+    lib.lya_xi3.argtypes = [P, FP, ctypes.POINTER(lya_grid3), OP, P, P, P, P, P]
+    lib.lya_xi3.restype = I32
     lib.lya_xi_means.argtypes = [P, FP, GP, OP, P, P, P, P, P, P, P, P]
     lib.lya_xi_means.restype = I32
     lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
@@ -170,6 +177,22 @@ class HostGrid:
                         self.ep.ctypes.data, self.et.ctypes.data)
 
 
+class HostGrid3:
+    """Edge arrays of a three-point grid (any object with r_edges, theta_edges
+    and cos_edges), kept alive for the duration of a call."""
+
+    def __init__(self, grid):
+        self.er = np.ascontiguousarray(grid.r_edges, np.float64)
+        self.et = np.ascontiguousarray(grid.theta_edges, np.float64)
+        self.ec = np.ascontiguousarray(grid.cos_edges, np.float64)
+        nr, nt, nc = (e.shape[0] - 1 for e in (self.er, self.et, self.ec))
+        self.n_bins = nr * nr * nc * nt * nt
+
+    def c_struct(self) -> lya_grid3:
+        return lya_grid3(self.er.shape[0] - 1, self.et.shape[0] - 1, self.ec.shape[0] - 1,
+                         self.er.ctypes.data, self.et.ctypes.data, self.ec.ctypes.data)
+
+
 class Library:
     """One lya_context bound to a CUDA device."""
 
@@ -241,6 +264,22 @@ class Library:
         self._check(self.lib.lya_xi(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
                                     self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
                                     _ptr(out["npairs"]), _ptr(out.get("xi"))))
+        return out
+
+    def xi3(self, forests: DeviceForests, grid3, stream=None, out=None, **opts):
+        """Triplet sums and xi3 of the anisotropic three-point function (FP64);
+        returns dict of [n_realisations, n_bins] tensors."""
+        import torch
+        g = HostGrid3(grid3)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        if out is None:
+            out = {k: torch.empty((R, g.n_bins), dtype=torch.int64 if k == "ntrip" else torch.float64, device=dev)
+                   for k in ("num", "wsum", "ntrip", "xi")}
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi3(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                     self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
+                                     _ptr(out["ntrip"]), _ptr(out.get("xi"))))
         return out
 
     def xi_means(self, forests: DeviceForests, grid, stream=None, out=None, **opts):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "lya.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lya_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lya_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_symbols_exported():
@@ -24,7 +24,7 @@ def test_header_symbols_exported():
     lib = ctypes.CDLL(L.LIB_PATH)
     names = _declared_functions()
     assert {"lya_create", "lya_xi", "lya_dmat", "lya_xi_backward", "lya_last_error",
-            "lya_xi_subsamples", "lya_xi_covariance", "lya_xi_means"} <= set(names)
+            "lya_xi_subsamples", "lya_xi_covariance", "lya_xi_means", "lya_xi3"} <= set(names)
     for n in names:
         assert hasattr(lib, n), f"{n} declared in lya.h but not exported"
 
@@ -32,6 +32,7 @@ def test_header_symbols_exported():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.lya_forests) == 8 * 10 + 8
     assert ctypes.sizeof(L.lya_grid) == 24
+    assert ctypes.sizeof(L.lya_grid3) == 4 * 3 + 4 + 3 * 8
     assert ctypes.sizeof(L.lya_options) == 4 * 8 + 8 + 8
     assert L.lya_options.dmat_keep_fraction.offset == 32
 
@@ -50,6 +51,7 @@ def test_defaults_and_null_arguments():
     assert lib.lya_xi_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_covariance(None, None, None, 1, 1, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_means(None, None, None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_xi3(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert o.counters == 0
     assert lib.lya_create(None, 0) == L.LYA_E_INVALID
     assert lib.lya_last_error(None) == b"NULL context"

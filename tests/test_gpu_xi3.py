@@ -1,0 +1,153 @@
+"""GPU parity of lya_xi3 (the anisotropic three-point function of Sec. 2.3,
+eq. estimator_three) against the FP64 oracle.  Entry counts must match
+exactly; N and W to 1e-12 of the bin's absolute sum (FP64 throughout, only
+the summation order differs)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import concat_realisations, make_config, make_patch, subset_forests
+from synth.survey import nearest_to_centre
+
+from helpers import forests_from_dict, load_json, tiny, truncate
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2507_00129_amd import Library
+    L = Library(0)
+    yield L
+    L.close()
+
+
+def grid3(r_max=30.0, n_r=3, n_t=4, n_c=5, r0=0.0, t=(0.0, np.pi), c=(-1.0, 1.0)):
+    return O.Grid3(np.linspace(r0, r_max, n_r + 1), np.linspace(t[0], t[1], n_t + 1),
+                   np.linspace(c[0], c[1], n_c + 1))
+
+
+def run3(lib, F, G3, **kw):
+    from paper_2507_00129_amd import DeviceForests
+    out = lib.xi3(DeviceForests.from_host(F, "cuda:0"), G3, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def check3(out, ref, what):
+    print(f"[xi3 {what}] entries={int(ref.ntrip.sum())} bins={int((ref.ntrip > 0).sum())} "
+          f"near_edge={ref.n_near_edge}", flush=True)
+    assert ref.n_near_edge == 0, "input has entries within 1e-12 of an edge; choose another seed"
+    np.testing.assert_array_equal(out["ntrip"], ref.ntrip)
+    m = ref.absnum > 0
+    e_n = float(np.max(np.abs(out["num"] - ref.num)[m] / ref.absnum[m])) if m.any() else 0.0
+    e_w = O.err_rel(out["wsum"], ref.wsum)
+    print(f"    e_N={e_n:.2e} e_W={e_w:.2e}", flush=True)
+    assert e_n <= TOL and e_w <= TOL
+    np.testing.assert_allclose(out["xi"], ref.xi, rtol=0, atol=TOL * max(1.0, float(np.abs(ref.xi).max())) * 1e3)
+
+
+def test_xi3_golden_handworked(lib):
+    d = load_json("xi3_handworked_three_forests.json")
+    F = forests_from_dict(d["forests"])
+    g = d["grid3"]
+    G3 = O.Grid3(np.array(g["r_edges"]), np.array(g["theta_edges"]), np.array(g["cos_edges"]))
+    out = run3(lib, F, G3)
+    exp = d["expected"]
+    assert out["ntrip"].shape == (1, exp["n_bins"])
+    assert np.nonzero(out["ntrip"][0])[0].tolist() == exp["bins"]
+    assert np.all(out["ntrip"][0][exp["bins"]] == exp["ntrip"])
+    assert np.allclose(out["num"][0][exp["bins"]], exp["num"], rtol=1e-15)
+    assert np.allclose(out["wsum"][0][exp["bins"]], exp["wsum"], rtol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_xi3_tiny_vs_oracle(lib, seed):
+    F = tiny(seed, n_forests=6, k=8, width_deg=0.3)
+    G3 = grid3()
+    check3(run3(lib, F, G3), O.xi3_sums(F, G3), f"tiny{seed}")
+
+
+def test_xi3_partial_ranges_vs_oracle(lib):
+    """r from 5 Mpc/h, theta in [0.2, 2.0], cos alpha in [-0.5, 1]: sides and
+    triangles outside the ranges drop out."""
+    F = tiny(3, n_forests=6, k=8, width_deg=0.3)
+    G3 = grid3(r0=5.0, t=(0.2, 2.0), n_t=3, c=(-0.5, 1.0), n_c=3)
+    check3(run3(lib, F, G3), O.xi3_sums(F, G3), "partial")
+
+
+def test_xi3_patch_with_realisations_vs_oracle(lib):
+    """Two realisations of 15 forests (30 pixels each, several 64-lane blocks of
+    partners per vertex), 6 x 6 x 8 x 5 x 5 bins to 30 Mpc/h."""
+    parts = [truncate(make_patch(15, 0.6, 40 + r, z_range=(2.1, 2.3)), 30) for r in range(2)]
+    F = concat_realisations(parts)
+    G3 = grid3(r_max=30.0, n_r=6, n_t=5, n_c=8)
+    out = run3(lib, F, G3)
+    assert out["ntrip"].shape == (2, G3.n_bins)
+    check3(out, O.xi3_sums(F, G3), "patch")
+
+
+def test_xi3_single_bin_closed_form(lib):
+    """Every triangle in one bin: the sums run over all ordered triples of
+    distinct forests, S1^3 - 3 S1 S2 + 2 S3 with S_p the power sums of the
+    per-forest sums (W, counts alike); tolerance relative to the same form of
+    the absolute values, since ~5e7 entries meet in one FP64 accumulator."""
+    F = truncate(make_patch(10, 0.3, 7, z_range=(2.1, 2.3)), 40)
+    G3 = O.Grid3(np.array([0.0, 1e5]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
+    out = run3(lib, F, G3)
+    fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+
+    def triple(a):
+        S = np.bincount(fid, weights=a, minlength=F.n_forests)
+        return S.sum() ** 3 - 3 * S.sum() * np.sum(S ** 2) + 2 * np.sum(S ** 3)
+    n = round(triple(np.ones(F.n_pix)))
+    assert int(out["ntrip"][0, 0]) == n and n > 4e7
+    assert abs(out["num"][0, 0] - triple(F.weight * F.delta)) <= 1e-10 * triple(np.abs(F.weight * F.delta))
+    assert abs(out["wsum"][0, 0] - triple(F.weight)) <= 1e-10 * triple(F.weight)
+
+
+def test_xi3_eboss_density_properties(lib):
+    """300 forests at the eBOSS-like density, r to 40 Mpc/h on 10 x 10 x 10 x 5
+    x 5 bins (5.6e9 entries): counts symmetric under (r1, theta1) <->
+    (r2, theta2), N and W symmetric to rounding."""
+    F, _, _ = make_config(1, seed=1, scale=0.05)
+    S = subset_forests(F, nearest_to_centre(F, 300))
+    G3 = grid3(r_max=40.0, n_r=10, n_t=5, n_c=10)
+    out = run3(lib, S, G3)
+    sh = (10, 10, 10, 5, 5)
+    c = out["ntrip"][0].reshape(sh)
+    print(f"[xi3 eboss-300] entries={int(c.sum())}", flush=True)
+    assert c.sum() > 1e8
+    np.testing.assert_array_equal(c, c.transpose(1, 0, 2, 4, 3))
+    for k in ("num", "wsum"):
+        v = out[k][0].reshape(sh)
+        assert np.max(np.abs(v - v.transpose(1, 0, 2, 4, 3))) <= 1e-10 * np.abs(v).max()
+
+
+def test_xi3_partner_overflow_is_reported(lib):
+    """More partner pixels within r_max of one pixel than the LDS list holds:
+    the call fails with LYA_E_UNSUPPORTED instead of dropping triangles."""
+    from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
+    F = truncate(make_patch(48, 0.3, 8, z_range=(2.1, 2.3)), 100)
+    G3 = O.Grid3(np.array([0.0, 1e5]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, G3)
+    assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+def test_xi3_invalid_grids(lib):
+    from paper_2507_00129_amd import LyaError, LYA_E_INVALID, LYA_E_UNSUPPORTED
+    F = tiny(0, n_forests=4, k=4, width_deg=0.3)
+
+    def expect(status, G3):
+        with pytest.raises(LyaError) as ei:
+            run3(lib, F, G3)
+        assert ei.value.status == status, str(ei.value)
+    expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 4.0]), np.array([-1.0, 1.0])))
+    expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0, 0.5]), np.array([-1.0, 1.0])))
+    expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.5, 1.0])))
+    expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 0.0, 0.2, 1.0])))
+    expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 1.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 1.0])))
