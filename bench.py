@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 PEAK_ALU_OPS = 256 * 64 * 2.4e9          # one VALU op per lane per clock, non-packed
 PEAK_MFMA_F64 = 78.6e12                   # dense FP64 matrix peak (flop/s)
+PEAK_MFMA_F32 = 157.3e12                  # dense FP32 matrix peak (flop/s)
 PEAK_HBM = 8.0e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 WORKLOADS = {
@@ -114,11 +115,12 @@ def xi_roofline(r):
 def d_roofline(r):
     flops = 2.0 * r["d_fmas"]
     achieved = flops / (r["ms_d_kernel"] / 1e3) / 1e12
-    return dict(kernel="dmat_kernel<float>", bound="mfma", achieved=achieved, peak=PEAK_MFMA_F64 / 1e12,
-                unit="TFLOP/s", frac=achieved / (PEAK_MFMA_F64 / 1e12),
+    # the FP32 form's contraction runs as FP32 MFMA steps: its own dtype's peak
+    return dict(kernel="dmat_kernel<float>", bound="mfma", achieved=achieved, peak=PEAK_MFMA_F32 / 1e12,
+                unit="TFLOP/s", frac=achieved / (PEAK_MFMA_F32 / 1e12),
                 traffic=measured_traffic("dmat_kernel", "k_dmat.hip"),
                 work=f"2 x {r['d_fmas']} FMAs of the sparse row outer products and the rank-4 pair term "
-                     f"(FP64 MFMA accumulation)",
+                     f"(FP32 MFMA steps into FP32 accumulators, added to the FP64 numerator once per run)",
                 ms=r["ms_d_kernel"])
 
 
@@ -183,6 +185,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the full-size FP32-vs-FP64 comparison")
     ap.add_argument("--no-means", action="store_true", help="skip timing the bin-means form of the xi kernel")
+    ap.add_argument("--no-xi3", action="store_true", help="skip timing the three-point kernel")
+    ap.add_argument("--xi3-forests", type=int, default=1500,
+                    help="forests nearest the patch centre used for the three-point timing")
     ap.add_argument("--cpu-xi-forests", type=int, default=400)
     ap.add_argument("--cpu-d-forests", type=int, default=120)
     ap.add_argument("--xi-variant", type=int, default=3,
@@ -260,6 +265,31 @@ def main():
                      time_over_xi_kernel=mm / res["fp32"]["ms_xi_kernel"])
         log(f"[bench] xi with bin means (fp32): kernel {mm:.2f} ms")
 
+    xi3 = None
+    if not args.no_xi3:
+        # anisotropic 3PCF (FP64) on the forests nearest the patch centre, sides to
+        # 40 Mpc/h in 10 bins, theta in 10 bins over [0, pi], cos alpha in 20 bins
+        from types import SimpleNamespace
+        from synth import subset_forests
+        from synth.survey import nearest_to_centre
+        S = subset_forests(F, nearest_to_centre(F, args.xi3_forests))
+        dS = DeviceForests.from_host(S, "cuda:0")
+        g3 = SimpleNamespace(r_edges=np.linspace(0.0, 40.0, 11), theta_edges=np.linspace(0.0, np.pi, 11),
+                             cos_edges=np.linspace(-1.0, 1.0, 21))
+        ms = []
+        for k in range(2):
+            o3 = lib.xi3(dS, g3, timing=True)
+            ms.append(lib.last_stats()["ms_main"])
+        torch.cuda.synchronize()
+        entries = int(o3["ntrip"].sum().item())
+        t3 = ms[-1] / 1e3
+        xi3 = dict(workload=f"{S.n_forests} forests nearest the centre of the eBOSS-like patch "
+                            f"({S.n_pix} pixels); r to 40 Mpc/h (10 bins), theta 10 bins, cos alpha 20 bins",
+                   entries=entries, ms_kernel=ms[-1], entries_per_s=entries / t3,
+                   global_atomics_per_s=3.0 * entries / t3, dtype="f64")
+        log(f"[bench] xi3: {entries:.3e} entries in {ms[-1]:.1f} ms ({entries / t3:.3e} entries/s)")
+        del dS, o3
+
     r32 = res["fp32"]
     # dominant kernel and its roofline (algorithmic work / kernel time from HIP
     # events recorded around the launch on its stream)
@@ -279,11 +309,15 @@ def main():
     line["d_pairs_per_s_kernel"] = r32["d_pairs"] / max(r32["ms_d_kernel"] / 1e3, 1e-12)
     if means is not None:
         line["xi_means_fp32"] = means
+    if xi3 is not None:
+        line["xi3_fp64"] = xi3
     if "fp64" in res:
         r64 = res["fp64"]
+        d64 = 2.0 * r64["d_fmas"] / max(r64["ms_d_kernel"] / 1e3, 1e-12)
         line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_step"],
                             xi_pairs_per_s_kernel=r64["xi_pairs"] / (r64["ms_xi_kernel"] / 1e3),
-                            d_pairs_per_s_kernel=r64["d_pairs"] / max(r64["ms_d_kernel"] / 1e3, 1e-12))
+                            d_pairs_per_s_kernel=r64["d_pairs"] / max(r64["ms_d_kernel"] / 1e3, 1e-12),
+                            d_mfma_tflops=d64 / 1e12, d_mfma_frac_of_f64_peak=d64 / PEAK_MFMA_F64)
         line["fp32_over_fp64"] = r32["value"] / r64["value"]
         if not args.no_check:
             a32, a64 = r32["out_xi"], r64["out_xi"]
