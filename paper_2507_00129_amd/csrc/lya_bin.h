@@ -105,9 +105,11 @@ struct BinK {
         exact(rp64, rt64);
         const int kp = bin_exact(rp64, ep, NP, (int)floor((double)xp));
         const int kt = bin_exact(rt64, et, NT, (int)floor((double)xt));
-        A = (kp >= 0 && kt >= 0) ? kt * NP + kp : -1;
+        A = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
       } else {
-        A = (int)xt * NP + (int)xp;
+        // both factors are below 2^24 (at most 4096 bins per axis): a 24-bit
+        // multiply-add instead of a 64-bit one
+        A = (int)__umul24((unsigned)(int)xt, (unsigned)NP) + (int)xp;
       }
     }
     return A;
