@@ -12,7 +12,12 @@
  *     with eta the per-forest continuum projection built from w and
  *     Lambda = log(lambda) (Sec. 2.2, eq. distortion and the eta definition);
  *   - the gradient of xi with respect to delta and w for a caller-supplied
- *     dL/dxi.
+ *     dL/dxi, also through the continuum projection;
+ *   - the pair sums split by subsample and the subsample covariance of xi,
+ *     and the weighted bin-mean r_par, r_perp and z of each bin;
+ *   - the triplet sums of the anisotropic three-point function
+ *     xi3_A = sum_A w_i d_i w_j d_j w_k d_k / sum_A w_i w_j w_k over pixels of
+ *     three distinct forests (Sec. 2.3, eq. estimator_three).
  *
  * Geometry.  Forest f has a sky direction n_f (from ra, dec).  With
  * s = |n_f - n_g| / 2 = sin(theta/2) and c = sqrt(1 - s^2), a pixel pair at
