@@ -17,22 +17,19 @@
 // rows, so D is banded in k_perp.  Kept pairs are sorted by (realisation,
 // first k_perp, span); a work item is a chunk of consecutive sorted pairs, and
 // all pairs of a chunk that share a window accumulate into one tile of D over
-// that window (in blocks of kTileW x kTileW window bins when the window is
-// wider), added to the global FP64 numerator once per chunk.
+// that window (in blocks of TW x TW window bins when the window is wider),
+// added to the global FP64 numerator once per chunk.
 //
 // The row terms are a contraction over rows: for a group of rows r with
 // weights -w_r, tile[x][y] += sum_r sum_l (-w_r R^l_r[x]) G^l_r[y], a
-// [W x 2n] by [2n x W] product.  It runs on the matrix cores: one FP64
-// 16x16x4 MFMA step takes two rows for one 16 x 16 block of the tile.  A row
-// only touches a few runs of bins, so each row records which blocks its R and G
+// [W x 2n] by [2n x W] product.  It runs on the matrix cores: one 16x16x4
+// MFMA step takes two rows for one 16 x 16 block of the tile.  A row only
+// touches a few runs of bins, so each row records which blocks its R and G
 // reach (one ballot gives every wave's block bits), and a step is issued only
-// for the blocks that one of its two rows reaches on both sides; the work issued
-// stays close to the sparse row outer products.  The tile is 10 x 10 blocks
-// shared by 8 waves (2 per SIMD): wave (wx, wy) = (w & 1, w >> 1) owns block
-// rows wx + 2i (i < 5) in block columns wy and wy + 4, and three (wy < 2: rows
-// i < 3) or two (wy >= 2: rows i >= 3) blocks of column 8 + (wy & 1), i.e. 13
-// or 12 blocks per wave; operand addresses are per-wave bases plus
-// compile-time offsets.
+// for the blocks that one of its two rows reaches on both sides; the work
+// issued stays close to the sparse row outer products.  The tile's blocks are
+// shared by 8 waves (2 per SIMD) as laid out by DLay below; operand addresses
+// are per-wave bases plus compile-time offsets.
 //
 // Within one forest, q = (u, b) = (w / W, w a / S) is p weighted per pixel and
 // scaled per forest, so the G histograms of a row are its R histograms times
@@ -42,14 +39,14 @@
 //
 // The workgroup takes the pairs of a run one at a time.  In each sweep the
 // pixels the lanes run over are staged in LDS (in chunks for long forests),
-// each wave sweeps RPW rows and builds their histograms in LDS with atomics (in
-// the working precision); after a barrier every wave issues the steps of its
-// own blocks.
-// The pair histograms H, Q follow from the sweep-1 rows and their rank-4 product
-// is one more step.  The accumulators are FP64 in both forms (the products of
-// FP32 operands are exact in FP64), so the tile needs no compensation; it is
-// added to the global numerator once per run.  Bins come from the shared binner,
-// so a pixel pair falls in the same bin here as in the xi kernel.
+// each wave sweeps RPW rows and builds their histograms in LDS with FP64
+// atomics; after a barrier every wave issues the steps of its own blocks.  The
+// pair histograms H, Q follow from the sweep-1 rows and their rank-4 product
+// is one more step.  The FP64 form accumulates in FP64; the FP32 form in FP32
+// over a run (at most a chunk of pairs), which its 1e-5 bound allows; either
+// tile is added to the global FP64 numerator once per run, and the Kronecker
+// term and w_A are summed in FP64 on the side.  Bins come from the shared
+// binner, so a pixel pair falls in the same bin here as in the xi kernel.
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -643,7 +640,7 @@ __global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
 }
 
 constexpr int kNumVariants = 1;
-const char* const kNames[kNumVariants] = {"b512-mfma64"};
+const char* const kNames[kNumVariants] = {"b512-mfma"};
 
 template <typename T, int BLOCK>
 hipError_t launch_one(const DmatArgs& a, int blocks, hipStream_t st) {
