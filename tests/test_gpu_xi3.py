@@ -151,3 +151,31 @@ def test_xi3_invalid_grids(lib):
     expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.5, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 0.0, 0.2, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 1.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 1.0])))
+
+
+def test_xi3_projected_deltas_vs_oracle(lib):
+    """project_deltas correlates eta delta (eta of options.eta) per forest: the
+    oracle's sums on deltas it projected itself.  delta' = delta - m - a t is
+    formed by two summation orders, so its absolute error is ~eps (|delta| +
+    |m| + |a t|), which can be large against a small |delta'|: N is compared
+    relative to the sums of w d~ w d~ w d~ with that conditioning d~."""
+    parts = [truncate(make_patch(15, 0.6, 60 + r, z_range=(2.1, 2.3)), 30) for r in range(2)]
+    F = concat_realisations(parts)
+    G3 = grid3(r_max=30.0, n_r=6, n_t=5, n_c=8)
+    Fp, Fc = F.copy(), F.copy()
+    Fp.delta = O.projected_deltas(F, O.MEAN_SLOPE)
+    for f in range(F.n_forests):
+        sl = F.forest_slice(f)
+        P = O.eta_params(F.weight[sl], F.loglam[sl], O.MEAN_SLOPE)
+        m, t = np.sum(P.u * F.delta[sl]), np.sum(P.b * F.delta[sl])
+        Fc.delta[sl] = np.abs(F.delta[sl]) + abs(m) + np.abs(P.a * t)
+    ref = O.xi3_sums(Fp, G3)
+    cond = O.xi3_sums(Fc, G3).num
+    out = run3(lib, F, G3, project_deltas=True, eta="mean_slope")
+    assert ref.n_near_edge == 0
+    np.testing.assert_array_equal(out["ntrip"], ref.ntrip)
+    m = cond > 0
+    e_n = float(np.max(np.abs(out["num"] - ref.num)[m] / cond[m]))
+    e_w = O.err_rel(out["wsum"], ref.wsum)
+    print(f"[xi3 projected] entries={int(ref.ntrip.sum())} e_N={e_n:.2e} e_W={e_w:.2e}", flush=True)
+    assert e_n <= TOL and e_w <= TOL
