@@ -24,11 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_ALU_OPS = 256 * 64 * 2.4e9          # one VALU op per lane per clock, non-packed
+# one non-packed VALU op per lane per clock: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (the
+# 157.3 TFLOP/s FP32 vector figure with an FMA as two flops; a SIMD issues a 64-lane FP32
+# instruction in two clocks, which the instruction counters of the xi kernel confirm)
+PEAK_ALU_OPS = 256 * 4 * 32 * 2.4e9
 PEAK_MFMA_F64 = 78.6e12                   # dense FP64 matrix peak (flop/s)
 PEAK_MFMA_F32 = 157.3e12                  # dense FP32 matrix peak (flop/s)
 PEAK_HBM = 8.0e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
 WORKLOADS = {
     1: "eBOSS-like patch: 30k forests over 400 deg^2, log-lambda pixels (50-150 per forest), "
        "GRF + unit-noise deltas; xi and D on 50x50 bins to 200 Mpc/h",
@@ -102,6 +106,20 @@ def measured_traffic(kernel, source):
     return rec.get("bytes_per_launch")
 
 
+def issued_valu_frac(kernel, source, ms):
+    """Issued VALU lane-ops per second over the peak, from the instruction
+    counters recorded in profiles/counters.json for this kernel source (None
+    when absent or taken on another version of the source)."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != source_digest(source):
+        return None
+    return rec["insts_valu_per_launch"] * 64 / (ms / 1e3) / PEAK_ALU_OPS
+
+
 def xi_roofline(r):
     ops = 6.0 * r["cand"] + 7.0 * r["xi_pairs"]
     achieved = ops / (r["ms_xi_kernel"] / 1e3) / 1e12
@@ -109,6 +127,7 @@ def xi_roofline(r):
                 unit="TFLOP/s", frac=achieved / (PEAK_ALU_OPS / 1e12),
                 traffic=measured_traffic("xi_kernel", "k_xi.hip"),
                 work=f"6 ops x {r['cand']} candidate pairs + 7 ops x {r['xi_pairs']} in-grid pairs",
+                issued_valu_frac=issued_valu_frac("xi_kernel", "k_xi.hip", r["ms_xi_kernel"]),
                 ms=r["ms_xi_kernel"])
 
 

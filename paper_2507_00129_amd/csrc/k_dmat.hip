@@ -127,7 +127,8 @@ struct DSmem {
   T sd[S], sw[S], sa[S];  // staged pixels of the forest the lanes sweep
   // R^0, R^1 of each row of the group over the tile's x range, and over its y
   // range when that differs.  FP64 in both forms: LDS FP64 atomic adds run at
-  // about twice the rate of FP32 ones here.
+  // about twice the rate of FP32 ones here (measured again with the FP32 form's
+  // FP32 steps: FP32 rows make the kernel 12 % slower).
   double rowR[NR][2][kTileW];
   double rowG[NR][2][kTileW];
   T rw[NR];                 // -w of each row (0: no row)
@@ -457,13 +458,15 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
                         ((1u << MB) - 1u));
                     if (bits == 0u) continue;
                     const int so = 2 * st * 2 * TW;  // two rows further per step
-                    const double wr = (double)sm.rw[2 * st + slot_l];
+                    // A[x][k] B[k][y] = (-w_r R[x]) (g_l R[y]): both factors of the
+                    // row and component k go on the A side
+                    const double fa = (double)sm.rw[2 * st + slot_l] * gs;
                     T av[BI], bv[NFC + 1];
 #pragma unroll
-                    for (int i = 0; i < BI; ++i) av[i] = (T)(wr * pa[so + 2 * kBlk * i]);
+                    for (int i = 0; i < BI; ++i) av[i] = (T)(fa * pa[so + 2 * kBlk * i]);
 #pragma unroll
-                    for (int k = 0; k < NFC; ++k) bv[k] = (T)(gs * pb[so + 4 * kBlk * k]);
-                    bv[NFC] = (T)(gs * pb[so + cx]);
+                    for (int k = 0; k < NFC; ++k) bv[k] = (T)pb[so + 4 * kBlk * k];
+                    bv[NFC] = (T)pb[so + cx];
 #pragma unroll
                     for (int j = 0; j < MB; ++j)
                       if ((bits >> j) & 1u) {
