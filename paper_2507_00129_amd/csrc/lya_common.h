@@ -316,10 +316,15 @@ struct Xi3Args {
   const double* cos_theta_edges;  // [n_t + 1] cosines of the theta edges (decreasing)
   const double* cos_edges;        // [n_c + 1]
   double r_e0, r_inv, c_e0, c_inv;
-  double* num;
+  double* num;            // n_copies copies of [R][n_bins], copy c at c * copy_stride
   double* wsum;
   unsigned long long* ntrip;
+  int32_t n_copies;
+  int64_t copy_stride;
 };
+hipError_t launch_xi3_reduce(const double* num_c, const double* wsum_c, const unsigned long long* cnt_c,
+                             int n_copies, int64_t stride, int64_t n, double* num, double* wsum, int64_t* ntrip,
+                             hipStream_t st);
 hipError_t launch_xi3_points(const lya_forests* F, const ForestInfo* finfo, const double* delta, Point3* pts,
                              hipStream_t st);
 hipError_t launch_xi3(const Xi3Args& a, int blocks, hipStream_t st);

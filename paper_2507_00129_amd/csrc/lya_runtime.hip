@@ -717,14 +717,31 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
     a.r_inv = r_inv;
     a.c_e0 = ce[0];
     a.c_inv = 1.0 / cd;
-    a.num = num;
-    a.wsum = wsum;
-    a.ntrip = (unsigned long long*)ntrip;
+    // one copy of the sums per XCD (8 on MI355X) when they fit in 1 GiB of
+    // workspace: the triplet atomics spread over 8 times the addresses
+    const int n_copies = nout * 24 * 8 <= ((int64_t)1 << 30) ? 8 : 1;
+    double* cn = num;
+    double* cw = wsum;
+    unsigned long long* cc = (unsigned long long*)ntrip;
+    if (n_copies > 1) {
+      LYA_TRY(wst(ctx, "xi3_num_c", (size_t)(n_copies * nout), &cn));
+      LYA_TRY(wst(ctx, "xi3_wsum_c", (size_t)(n_copies * nout), &cw));
+      LYA_TRY(wst(ctx, "xi3_cnt_c", (size_t)(n_copies * nout), &cc));
+      HIP_TRY(launch_zero(cn, (size_t)(n_copies * nout) * sizeof(double), st));
+      HIP_TRY(launch_zero(cw, (size_t)(n_copies * nout) * sizeof(double), st));
+      HIP_TRY(launch_zero(cc, (size_t)(n_copies * nout) * sizeof(unsigned long long), st));
+    }
+    a.num = cn;
+    a.wsum = cw;
+    a.ntrip = cc;
+    a.n_copies = n_copies;
+    a.copy_stride = nout;
     const int blocks = xi3_blocks_per_cu() * ctx->n_cu;
     ctx->stats.grid_blocks = blocks;
     HIP_TRY(launch_zero(counter, 4, st));
     tm.at(3);
     HIP_TRY(launch_xi3(a, blocks, st));
+    if (n_copies > 1) HIP_TRY(launch_xi3_reduce(cn, cw, cc, n_copies, nout, nout, num, wsum, ntrip, st));
     tm.at(4);
     HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
