@@ -240,6 +240,14 @@ typedef struct {
      wsum[A]  = sum_A w_i w_j w_k
      ntrip[A] = number of entries in A (any weight)
      xi[A]    = num[A] / wsum[A], 0 where wsum[A] == 0   (may be NULL)
+   Two kernels: variant 0 sums each vertex pixel's entries in LDS per (r,
+   theta) cell of the first side before adding them to the global sums
+   (grids with n_r n_theta <= 1024 and n_cos n_theta <= 2048, up to 2048
+   partner pixels per vertex); variant 1 adds every entry to the global sums.
+   options.variant = -1 takes variant 0 where the grid allows and re-runs the
+   call with variant 1 when a pixel has more partners than variant 0 holds;
+   variant 0 forced on a larger grid, or on a pixel with more than 2048
+   partners, returns LYA_E_UNSUPPORTED.
    Returns LYA_E_UNSUPPORTED if a pixel has more than 3072 partner pixels with
    a side in the r grid (the outputs are then incomplete). */
 lya_status lya_xi3(lya_context *ctx, const lya_forests *forests, const lya_grid3 *grid,

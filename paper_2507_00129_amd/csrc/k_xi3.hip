@@ -26,14 +26,37 @@ namespace lya {
 namespace {
 
 constexpr int kBlock3 = 512;
-constexpr int kCap3 = 3072;  // partner pixels of one vertex held in LDS
+constexpr int kCap3 = 3072;    // partner pixels of one vertex held in LDS (direct kernel)
+constexpr int kCapC = 2048;    // the same for the combining kernel
+constexpr int kSliceC = 2048;  // bins of the combining kernel's LDS histogram slice
+constexpr int kCellC = 1024;   // (r, theta) cells of a side, combining kernel
+
+// Partners of one vertex pixel: unit vector of the side, w d, w, the side's
+// bins k_r | k_t << 16 and the partner's forest.
+template <int CAP>
+struct Partners {
+  double ux[CAP], uy[CAP], uz[CAP];
+  double wd[CAP], w[CAP];
+  int32_t key[CAP];
+  int32_t fid[CAP];
+};
 
 struct Xi3Smem {
-  double ux[kCap3], uy[kCap3], uz[kCap3];  // unit vector of the side to each partner
-  double wd[kCap3], w[kCap3];
-  int32_t key[kCap3];   // k_r | k_t << 16
-  int32_t fid[kCap3];   // partner's forest
-  int32_t m;            // partners appended
+  Partners<kCap3> p;
+  int32_t m;  // partners appended
+  int64_t item;
+};
+
+struct Xi3SmemC {
+  Partners<kCapC> p;
+  double hn[kSliceC], hw[kSliceC];  // slice of the sums: side-2 r bins [r_lo, r_lo + rb) x cos x theta
+  uint32_t hc[kSliceC];
+  uint16_t perm[kCapC];             // partners ordered by cell k_r n_t + k_t
+  uint16_t touched[kSliceC];        // slice bins that are not zero
+  int32_t cstart[kCellC + 1];       // first position of each cell in perm
+  int32_t cfill[kCellC];
+  int32_t m;
+  int32_t ntouch[2];
   int64_t item;
 };
 
@@ -58,10 +81,86 @@ __device__ __forceinline__ int uniform_bin(double x, const double* e, int n, dou
   return k;
 }
 
+// Appends to P every pixel of the item's neighbour forests whose side from the
+// vertex (xi, yi, zi) has its length in the r grid and its angle to the line of
+// sight n of the vertex forest in the theta grid.  A wave per neighbour forest,
+// lanes over its pixels; one LDS atomic per wave reserves the slots.  *m counts
+// every partner, also those beyond CAP (which are not stored).
+template <int CAP>
+__device__ __forceinline__ void gather_partners(const Xi3Args& a, const Item& item, const ForestInfo& fi,
+                                                double xi, double yi, double zi, Partners<CAP>& P,
+                                                int32_t* m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kBlock3 / 64;
+  const int nr = a.n_r, nt = a.n_t;
+  for (int t = wave; t < item.nb_count; t += NW) {
+    const int g = a.sorted[a.nbr[item.nb_begin + t]];
+    const ForestInfo gi = a.finfo[g];
+    for (int e0 = 0; e0 < gi.npix; e0 += 64) {
+      const int e = e0 + lane;
+      bool keep = false;
+      double ux = 0.0, uy = 0.0, uz = 0.0;
+      int kr = -1, kt = 0;
+      const int64_t pj = gi.pix0 + e;
+      if (e < gi.npix) {
+        const double dx = __dsub_rn(a.pts[pj].x, xi), dy = __dsub_rn(a.pts[pj].y, yi),
+                     dz = __dsub_rn(a.pts[pj].z, zi);
+        const double r = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
+        kr = r > 0.0 ? uniform_bin(r, a.r_edges, nr, a.r_e0, a.r_inv, false) : -1;
+        if (kr >= 0) {
+          ux = __ddiv_rn(dx, r);
+          uy = __ddiv_rn(dy, r);
+          uz = __ddiv_rn(dz, r);
+          double ct = __dadd_rn(__dadd_rn(__dmul_rn(ux, fi.nx), __dmul_rn(uy, fi.ny)), __dmul_rn(uz, fi.nz));
+          ct = fmin(1.0, fmax(-1.0, ct));
+          // theta >= t_k  <=>  cos theta <= cos t_k (theta in [0, pi])
+          kt = 0;
+          for (int k = 1; k < nt; ++k) kt += ct <= a.cos_theta_edges[k] ? 1 : 0;
+          keep = ct <= a.cos_theta_edges[0] && ct >= a.cos_theta_edges[nt];
+        }
+      }
+      const uint64_t bal = __ballot(keep);
+      if (bal == 0ull) continue;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(m, __popcll(bal));
+      base = __shfl(base, 0, 64);
+      if (keep) {
+        const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
+        if (slot < CAP) {
+          P.ux[slot] = ux;
+          P.uy[slot] = uy;
+          P.uz[slot] = uz;
+          P.wd[slot] = a.pts[pj].wd;
+          P.w[slot] = a.pts[pj].w;
+          P.key[slot] = kr | (kt << 16);
+          P.fid[slot] = g;
+        }
+      }
+    }
+  }
+}
+
+// cos alpha bin of the partners j, k (-1 outside the grid).
+template <int CAP>
+__device__ __forceinline__ int cos_bin(const Xi3Args& a, const Partners<CAP>& P, int j, int k) {
+  double ca = __dadd_rn(__dadd_rn(__dmul_rn(P.ux[j], P.ux[k]), __dmul_rn(P.uy[j], P.uy[k])),
+                        __dmul_rn(P.uz[j], P.uz[k]));
+  ca = fmin(1.0, fmax(-1.0, ca));
+  return uniform_bin(ca, a.cos_edges, a.n_c, a.c_e0, a.c_inv, true);
+}
+
+// The copy of the sums this workgroup adds to: with one copy per XCD, the copy
+// of its XCD (the copies spread the device-wide atomics over more addresses);
+// a second kernel adds them up.
+__device__ __forceinline__ int64_t sums_base(const Xi3Args& a, const ForestInfo& fi) {
+  const int copy = a.n_copies > 1 ? (int)(xcd_id() % (unsigned)a.n_copies) : 0;
+  return (int64_t)copy * a.copy_stride + (int64_t)fi.real * a.n_bins;
+}
+
+// Direct kernel: every entry goes to the global sums with three atomics.
 __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
   __shared__ Xi3Smem sm;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NW = kBlock3 / 64;
+  const int tid = threadIdx.x;
   const int nr = a.n_r, nt = a.n_t, nc = a.n_c;
 
   for (;;) {
@@ -73,66 +172,15 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
     const Item item = a.items[it];
     const int f = a.sorted[item.p];
     const ForestInfo fi = a.finfo[f];
-    // with one copy of the sums per XCD, the copy of this workgroup's XCD (the
-    // copies spread the device-wide atomics over more addresses: 10 % faster on
-    // the benchmark grid); a second kernel adds them up
-    const int copy = a.n_copies > 1 ? (int)(xcd_id() % (unsigned)a.n_copies) : 0;
-    const int64_t obase = (int64_t)copy * a.copy_stride + (int64_t)fi.real * a.n_bins;
+    const int64_t obase = sums_base(a, fi);
 
     for (int i = 0; i < fi.npix; ++i) {
       const int64_t pi = fi.pix0 + i;
-      const double xi = a.pts[pi].x, yi = a.pts[pi].y, zi = a.pts[pi].z;
       const double wdi = a.pts[pi].wd, wi = a.pts[pi].w;
       __syncthreads();  // the previous vertex's pairs have been read
       if (tid == 0) sm.m = 0;
       __syncthreads();
-
-      // ---- partners of vertex i
-      for (int t = wave; t < item.nb_count; t += NW) {
-        const int g = a.sorted[a.nbr[item.nb_begin + t]];
-        const ForestInfo gi = a.finfo[g];
-        for (int e0 = 0; e0 < gi.npix; e0 += 64) {
-          const int e = e0 + lane;
-          bool keep = false;
-          double ux = 0.0, uy = 0.0, uz = 0.0;
-          int kr = -1, kt = 0;
-          const int64_t pj = gi.pix0 + e;
-          if (e < gi.npix) {
-            const double dx = __dsub_rn(a.pts[pj].x, xi), dy = __dsub_rn(a.pts[pj].y, yi),
-                         dz = __dsub_rn(a.pts[pj].z, zi);
-            const double r = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)));
-            kr = r > 0.0 ? uniform_bin(r, a.r_edges, nr, a.r_e0, a.r_inv, false) : -1;
-            if (kr >= 0) {
-              ux = __ddiv_rn(dx, r);
-              uy = __ddiv_rn(dy, r);
-              uz = __ddiv_rn(dz, r);
-              double ct = __dadd_rn(__dadd_rn(__dmul_rn(ux, fi.nx), __dmul_rn(uy, fi.ny)), __dmul_rn(uz, fi.nz));
-              ct = fmin(1.0, fmax(-1.0, ct));
-              // theta >= t_k  <=>  cos theta <= cos t_k (theta in [0, pi])
-              kt = 0;
-              for (int k = 1; k < nt; ++k) kt += ct <= a.cos_theta_edges[k] ? 1 : 0;
-              keep = ct <= a.cos_theta_edges[0] && ct >= a.cos_theta_edges[nt];
-            }
-          }
-          const uint64_t bal = __ballot(keep);
-          if (bal == 0ull) continue;
-          int base = 0;
-          if (lane == 0) base = atomicAdd(&sm.m, __popcll(bal));
-          base = __shfl(base, 0, 64);
-          if (keep) {
-            const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
-            if (slot < kCap3) {
-              sm.ux[slot] = ux;
-              sm.uy[slot] = uy;
-              sm.uz[slot] = uz;
-              sm.wd[slot] = a.pts[pj].wd;
-              sm.w[slot] = a.pts[pj].w;
-              sm.key[slot] = kr | (kt << 16);
-              sm.fid[slot] = g;
-            }
-          }
-        }
-      }
+      gather_partners<kCap3>(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, sm.p, &sm.m);
       __syncthreads();
       const int m = sm.m;
       if (m > kCap3) {
@@ -147,17 +195,14 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
       int j = tid / m, k = tid - (tid / m) * m;
       const int dj = kBlock3 / m, dk = kBlock3 - dj * m;
       for (int64_t t = tid; t < total; t += kBlock3) {
-        if (sm.fid[j] != sm.fid[k]) {
-          double ca = __dadd_rn(__dadd_rn(__dmul_rn(sm.ux[j], sm.ux[k]), __dmul_rn(sm.uy[j], sm.uy[k])),
-                                __dmul_rn(sm.uz[j], sm.uz[k]));
-          ca = fmin(1.0, fmax(-1.0, ca));
-          const int kc = uniform_bin(ca, a.cos_edges, nc, a.c_e0, a.c_inv, true);
+        if (sm.p.fid[j] != sm.p.fid[k]) {
+          const int kc = cos_bin(a, sm.p, j, k);
           if (kc >= 0) {
-            const int kj = sm.key[j], kk = sm.key[k];
+            const int kj = sm.p.key[j], kk = sm.p.key[k];
             const int64_t A = ((((int64_t)(kj & 0xffff) * nr + (kk & 0xffff)) * nc + kc) * nt + (kj >> 16)) * nt +
                               (kk >> 16);
-            const double pn = __dmul_rn(__dmul_rn(wdi, sm.wd[j]), sm.wd[k]);
-            const double pw = __dmul_rn(__dmul_rn(wi, sm.w[j]), sm.w[k]);
+            const double pn = __dmul_rn(__dmul_rn(wdi, sm.p.wd[j]), sm.p.wd[k]);
+            const double pw = __dmul_rn(__dmul_rn(wi, sm.p.w[j]), sm.p.w[k]);
             atomicAdd(&a.num[obase + A], pn);
             atomicAdd(&a.wsum[obase + A], pw);
             atomicAdd(&a.ntrip[obase + A], 1ull);
@@ -168,6 +213,161 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
         if (k >= m) {
           k -= m;
           ++j;
+        }
+      }
+    }
+  }
+}
+
+// Combining kernel.  Entries of one vertex whose first side lies in one
+// (r, theta) cell differ only in (k_r2, k_c, k_t2): the partners are ordered by
+// cell, and for each cell of the first side (and each block of rb side-2 r
+// bins) the entries are summed in an LDS slice of n_t n_c rb bins, then the
+// slice's non-zero bins go to the global sums with three atomics each.  On the
+// eBOSS-like workload this takes the global atomics down ~7x.
+__global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
+  __shared__ Xi3SmemC sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nr = a.n_r, nt = a.n_t, nc = a.n_c;
+  const int ncell = nr * nt;
+  const int rb = kSliceC / (nc * nt);  // >= 1, checked by the host
+  const int nblk = (nr + rb - 1) / rb;
+  int par = 0;
+
+  for (int s = tid; s < kSliceC; s += kBlock3) {
+    sm.hn[s] = 0.0;
+    sm.hw[s] = 0.0;
+    sm.hc[s] = 0u;
+  }
+  if (tid == 0) sm.ntouch[0] = sm.ntouch[1] = 0;
+
+  for (;;) {
+    __syncthreads();  // every thread has read the previous item
+    if (tid == 0) {
+      // after an overflow the direct kernel redoes the call: stop early
+      const bool over = __hip_atomic_load(&a.glob->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadCapC;
+      sm.item = over ? a.n_items : (int64_t)atomicAdd(a.counter, 1u);
+    }
+    __syncthreads();
+    const int64_t it = sm.item;
+    if (it >= a.n_items) break;
+    const Item item = a.items[it];
+    const int f = a.sorted[item.p];
+    const ForestInfo fi = a.finfo[f];
+    const int64_t obase = sums_base(a, fi);
+
+    for (int i = 0; i < fi.npix; ++i) {
+      const int64_t pi = fi.pix0 + i;
+      const double wdi = a.pts[pi].wd, wi = a.pts[pi].w;
+      __syncthreads();  // the previous vertex's partners have been read
+      if (tid == 0) sm.m = 0;
+      for (int c = tid; c < ncell; c += kBlock3) sm.cfill[c] = 0;
+      __syncthreads();
+      gather_partners<kCapC>(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, sm.p, &sm.m);
+      __syncthreads();
+      const int m = sm.m;
+      if (m > kCapC) {
+        // the host runs the direct kernel instead
+        if (tid == 0) atomicOr(&a.glob->flag, kBadCapC);
+        continue;
+      }
+      if (m < 2) continue;
+
+      // ---- order the partners by cell: counts, exclusive scan, scatter
+      for (int j = tid; j < m; j += kBlock3) {
+        const int key = sm.p.key[j];
+        atomicAdd(&sm.cfill[(key & 0xffff) * nt + (key >> 16)], 1);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int per = (ncell + 63) / 64, c0 = lane * per, c1 = min(ncell, c0 + per);
+        int own = 0;
+        for (int c = c0; c < c1; ++c) own += sm.cfill[c];
+        int incl = own;
+        for (int d = 1; d < 64; d <<= 1) {
+          const int v = __shfl_up(incl, d, 64);
+          if (lane >= d) incl += v;
+        }
+        int run = incl - own;
+        for (int c = c0; c < c1; ++c) {
+          sm.cstart[c] = run;
+          run += sm.cfill[c];
+          sm.cfill[c] = 0;
+        }
+        if (lane == 63) sm.cstart[ncell] = incl;
+      }
+      __syncthreads();
+      for (int j = tid; j < m; j += kBlock3) {
+        const int key = sm.p.key[j];
+        const int c = (key & 0xffff) * nt + (key >> 16);
+        sm.perm[sm.cstart[c] + atomicAdd(&sm.cfill[c], 1)] = (uint16_t)j;
+      }
+      __syncthreads();
+
+      // ---- one pass per (cell of side 1, block of side-2 r bins)
+      for (int c1 = 0; c1 < ncell; ++c1) {
+        const int j0 = sm.cstart[c1], nj = sm.cstart[c1 + 1] - j0;
+        if (nj == 0) continue;
+        const int kr1 = c1 / nt, kt1 = c1 - kr1 * nt;
+        for (int b = 0; b < nblk; ++b) {
+          const int r_lo = b * rb, r_hi = min(nr, r_lo + rb);
+          const int k0 = sm.cstart[r_lo * nt], mk = sm.cstart[r_hi * nt] - k0;
+          if (mk == 0) continue;
+          // the other counter's flush ended before the last barrier
+          if (tid == 0) sm.ntouch[par ^ 1] = 0;
+          const int total = nj * mk;
+          int jj = tid / mk, kk = tid - (tid / mk) * mk;
+          const int dj = kBlock3 / mk, dk = kBlock3 - dj * mk;
+          for (int t0 = 0; t0 < total; t0 += kBlock3) {
+            bool fresh = false;
+            int s = 0;
+            if (t0 + tid < total) {
+              const int j = sm.perm[j0 + jj], k = sm.perm[k0 + kk];
+              if (sm.p.fid[j] != sm.p.fid[k]) {
+                const int kc = cos_bin(a, sm.p, j, k);
+                if (kc >= 0) {
+                  const int kq = sm.p.key[k];
+                  s = (((kq & 0xffff) - r_lo) * nc + kc) * nt + (kq >> 16);
+                  const double pn = __dmul_rn(__dmul_rn(wdi, sm.p.wd[j]), sm.p.wd[k]);
+                  const double pw = __dmul_rn(__dmul_rn(wi, sm.p.w[j]), sm.p.w[k]);
+                  fresh = atomicAdd(&sm.hc[s], 1u) == 0u;
+                  atomicAdd(&sm.hn[s], pn);
+                  atomicAdd(&sm.hw[s], pw);
+                }
+              }
+            }
+            const uint64_t bal = __ballot(fresh);
+            if (bal != 0ull) {
+              int base = 0;
+              if (lane == 0) base = atomicAdd(&sm.ntouch[par], __popcll(bal));
+              base = __shfl(base, 0, 64);
+              if (fresh) sm.touched[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)s;
+            }
+            kk += dk;
+            jj += dj;
+            if (kk >= mk) {
+              kk -= mk;
+              ++jj;
+            }
+          }
+          __syncthreads();
+          // ---- flush the slice's non-zero bins and clear them
+          const int nto = sm.ntouch[par];
+          for (int q = tid; q < nto; q += kBlock3) {
+            const int s = sm.touched[q];
+            const double vn = sm.hn[s], vw = sm.hw[s];
+            const uint32_t vc = sm.hc[s];
+            sm.hn[s] = 0.0;
+            sm.hw[s] = 0.0;
+            sm.hc[s] = 0u;
+            const int kt2 = s % nt, q2 = s / nt, kc = q2 % nc, kr2 = r_lo + q2 / nc;
+            const int64_t A = ((((int64_t)kr1 * nr + kr2) * nc + kc) * nt + kt1) * nt + kt2;
+            atomicAdd(&a.num[obase + A], vn);
+            atomicAdd(&a.wsum[obase + A], vw);
+            atomicAdd(&a.ntrip[obase + A], (unsigned long long)vc);
+          }
+          __syncthreads();
+          par ^= 1;
         }
       }
     }
@@ -234,18 +434,29 @@ hipError_t launch_xi3_reduce(const double* num_c, const double* wsum_c, const un
   return hipGetLastError();
 }
 
-hipError_t launch_xi3(const Xi3Args& a, int blocks, hipStream_t st) {
+hipError_t launch_xi3(const Xi3Args& a, bool combine, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(xi3_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
+  if (combine)
+    hipLaunchKernelGGL(xi3c_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
+  else
+    hipLaunchKernelGGL(xi3_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
   return hipGetLastError();
 }
 
-int xi3_blocks_per_cu() {
+int xi3_blocks_per_cu(bool combine) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3_kernel, kBlock3, 0) != hipSuccess) return 1;
+  const hipError_t e = combine ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3c_kernel, kBlock3, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3_kernel, kBlock3, 0);
+  if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
 int xi3_partner_capacity() { return kCap3; }
+
+int xi3_combine_capacity() { return kCapC; }
+
+bool xi3_can_combine(int n_r, int n_t, int n_c) {
+  return (int64_t)n_r * n_t <= kCellC && (int64_t)n_c * n_t <= kSliceC;
+}
 
 }  // namespace lya

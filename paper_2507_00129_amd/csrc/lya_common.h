@@ -74,7 +74,7 @@ struct GridDev {
 // Validation error bits (Globals::flag).
 enum : int32_t {
   kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32,
-  kBadSub = 64, kBadCap3 = 128
+  kBadSub = 64, kBadCap3 = 128, kBadCapC = 256
 };
 
 // ---------------------------------------------------------------- geometry
@@ -327,8 +327,13 @@ hipError_t launch_xi3_reduce(const double* num_c, const double* wsum_c, const un
                              hipStream_t st);
 hipError_t launch_xi3_points(const lya_forests* F, const ForestInfo* finfo, const double* delta, Point3* pts,
                              hipStream_t st);
-hipError_t launch_xi3(const Xi3Args& a, int blocks, hipStream_t st);
-int xi3_blocks_per_cu();
+// combine: the kernel that sums each vertex's entries in LDS before the global
+// atomics (grids with xi3_can_combine; it flags kBadCapC when a vertex has more
+// partners than it holds, and the direct kernel is run instead)
+hipError_t launch_xi3(const Xi3Args& a, bool combine, int blocks, hipStream_t st);
+int xi3_blocks_per_cu(bool combine);
+bool xi3_can_combine(int n_r, int n_t, int n_c);
+int xi3_combine_capacity();
 int xi3_partner_capacity();
 int xi_means_blocks_per_cu(int precision, int n_bins);
 hipError_t launch_finalize_means(const double* wsum, const double* msum, int64_t n, const GridDev& g,

@@ -736,18 +736,42 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
     a.ntrip = cc;
     a.n_copies = n_copies;
     a.copy_stride = nout;
-    const int blocks = xi3_blocks_per_cu() * ctx->n_cu;
-    ctx->stats.grid_blocks = blocks;
-    HIP_TRY(launch_zero(counter, 4, st));
+    // variant 0: the combining kernel (LDS sums per vertex and side-1 cell),
+    // 1: the direct kernel; by default the combining one where the grid fits
+    // its LDS slice, with the direct one run instead when a pixel has more
+    // partners than the combining kernel holds
+    const bool fits = xi3_can_combine(nr, nt, nc);
+    if (o->variant > 1) return fail(ctx, LYA_E_INVALID, "variant %d out of range (xi3 has 2)", o->variant);
+    if (o->variant == 0 && !fits)
+      return fail(ctx, LYA_E_UNSUPPORTED, "grid too large for the combining kernel (variant 0)");
+    bool combine = o->variant == 0 || (o->variant < 0 && fits);
     tm.at(3);
-    HIP_TRY(launch_xi3(a, blocks, st));
+    for (;;) {
+      const int blocks = xi3_blocks_per_cu(combine) * ctx->n_cu;
+      ctx->stats.grid_blocks = blocks;
+      ctx->stats.variant = combine ? 0 : 1;
+      HIP_TRY(launch_zero(counter, 4, st));
+      HIP_TRY(launch_xi3(a, combine, blocks, st));
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const int32_t flag = *(int32_t*)ctx->pinned;
+      if (flag & kBadCap3)
+        return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel",
+                    xi3_partner_capacity());
+      if (!(flag & kBadCapC)) break;
+      if (o->variant == 0)
+        return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel (variant 0)",
+                    xi3_combine_capacity());
+      // a pixel has more partners than the combining kernel holds: clear the
+      // flag and the sums and run the direct kernel
+      combine = false;
+      HIP_TRY(launch_zero(&P.glob->flag, sizeof(int32_t), st));
+      HIP_TRY(launch_zero(cn, (size_t)(n_copies * nout) * sizeof(double), st));
+      HIP_TRY(launch_zero(cw, (size_t)(n_copies * nout) * sizeof(double), st));
+      HIP_TRY(launch_zero(cc, (size_t)(n_copies * nout) * sizeof(unsigned long long), st));
+    }
     if (n_copies > 1) HIP_TRY(launch_xi3_reduce(cn, cw, cc, n_copies, nout, nout, num, wsum, ntrip, st));
     tm.at(4);
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (*(int32_t*)ctx->pinned & kBadCap3)
-      return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel",
-                  xi3_partner_capacity());
   } else {
     tm.at(1);
     tm.at(2);

@@ -1,7 +1,9 @@
 """GPU parity of lya_xi3 (the anisotropic three-point function of Sec. 2.3,
-eq. estimator_three) against the FP64 oracle.  Entry counts must match
-exactly; N and W to 1e-12 of the bin's absolute sum (FP64 throughout, only
-the summation order differs)."""
+eq. estimator_three) against the FP64 oracle, for both kernels (variant 0
+sums each vertex's entries in LDS before the global atomics, variant 1 adds
+every entry to the global sums).  Entry counts must match exactly; N and W to
+1e-12 of the bin's absolute sum (FP64 throughout, only the summation order
+differs)."""
 import numpy as np
 import pytest
 
@@ -30,10 +32,12 @@ def grid3(r_max=30.0, n_r=3, n_t=4, n_c=5, r0=0.0, t=(0.0, np.pi), c=(-1.0, 1.0)
                    np.linspace(c[0], c[1], n_c + 1))
 
 
-def run3(lib, F, G3, **kw):
+def run3(lib, F, G3, expect_variant=None, **kw):
     from paper_2507_00129_amd import DeviceForests
     out = lib.xi3(DeviceForests.from_host(F, "cuda:0"), G3, **kw)
     torch.cuda.synchronize()
+    if expect_variant is not None:
+        assert lib.last_stats()["variant"] == expect_variant
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
@@ -64,40 +68,84 @@ def test_xi3_golden_handworked(lib):
     assert np.allclose(out["wsum"][0][exp["bins"]], exp["wsum"], rtol=1e-15)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_xi3_tiny_vs_oracle(lib, seed):
+def test_xi3_tiny_vs_oracle(lib, seed, variant):
     F = tiny(seed, n_forests=6, k=8, width_deg=0.3)
     G3 = grid3()
-    check3(run3(lib, F, G3), O.xi3_sums(F, G3), f"tiny{seed}")
+    check3(run3(lib, F, G3, variant=variant, expect_variant=variant), O.xi3_sums(F, G3), f"tiny{seed} v{variant}")
 
 
-def test_xi3_partial_ranges_vs_oracle(lib):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_xi3_partial_ranges_vs_oracle(lib, variant):
     """r from 5 Mpc/h, theta in [0.2, 2.0], cos alpha in [-0.5, 1]: sides and
     triangles outside the ranges drop out."""
     F = tiny(3, n_forests=6, k=8, width_deg=0.3)
     G3 = grid3(r0=5.0, t=(0.2, 2.0), n_t=3, c=(-0.5, 1.0), n_c=3)
-    check3(run3(lib, F, G3), O.xi3_sums(F, G3), "partial")
+    check3(run3(lib, F, G3, variant=variant), O.xi3_sums(F, G3), f"partial v{variant}")
 
 
-def test_xi3_patch_with_realisations_vs_oracle(lib):
+@pytest.mark.parametrize("variant", [-1, 1])
+def test_xi3_patch_with_realisations_vs_oracle(lib, variant):
     """Two realisations of 15 forests (30 pixels each, several 64-lane blocks of
-    partners per vertex), 6 x 6 x 8 x 5 x 5 bins to 30 Mpc/h."""
+    partners per vertex), 6 x 6 x 8 x 5 x 5 bins to 30 Mpc/h; the default
+    picks the combining kernel."""
     parts = [truncate(make_patch(15, 0.6, 40 + r, z_range=(2.1, 2.3)), 30) for r in range(2)]
     F = concat_realisations(parts)
     G3 = grid3(r_max=30.0, n_r=6, n_t=5, n_c=8)
-    out = run3(lib, F, G3)
+    out = run3(lib, F, G3, variant=variant, expect_variant=0 if variant < 0 else variant)
     assert out["ntrip"].shape == (2, G3.n_bins)
-    check3(out, O.xi3_sums(F, G3), "patch")
+    check3(out, O.xi3_sums(F, G3), f"patch v{variant}")
 
 
-def test_xi3_single_bin_closed_form(lib):
+def test_xi3_slice_blocks_vs_oracle(lib):
+    """n_cos n_theta = 400: the combining kernel's LDS slice holds 5 of the 7
+    side-2 r bins, so each side-1 cell takes two passes (as on the paper's
+    3PCF grid, 20 r x 10 theta x 20 cos alpha bins, which takes two)."""
+    parts = [truncate(make_patch(12, 0.6, 70 + r, z_range=(2.1, 2.3)), 24) for r in range(2)]
+    F = concat_realisations(parts)
+    G3 = grid3(r_max=35.0, n_r=7, n_t=20, n_c=20)
+    check3(run3(lib, F, G3, expect_variant=0), O.xi3_sums(F, G3), "slice blocks")
+
+
+def _lopsided(seed=5, n_long=2060, n_short=10):
+    """Three forests side by side: one long (n_long pixels spaced 0.7 Mpc/h)
+    and two short ones in its middle.  A pixel of a short forest has
+    n_long + n_short partners, a pixel of the long one 2 n_short; the entries
+    stay few (the long forest's pixels never pair with each other)."""
+    from synth import Forests
+    P = make_patch(3, 0.3, seed, z_range=(2.1, 2.3))
+    rng = np.random.default_rng(seed)
+    mid = 3800.0 + 0.35 * n_long
+    dist = np.concatenate([3800.0 + 0.7 * np.arange(n_long),
+                           mid + 0.7 * np.arange(n_short) + 0.31, mid + 0.7 * np.arange(n_short) - 0.29])
+    n = dist.size
+    return Forests(np.array([0, n_long, n_long + n_short, n], np.int64), P.ra.copy(), P.dec.copy(), dist,
+                   rng.normal(0.0, 0.3, n), rng.uniform(0.5, 2.0, n), np.full(n, 8.2), None, 1)
+
+
+def test_xi3_combining_overflow_falls_back(lib):
+    """Pixels with 2070 partners: more than the combining kernel holds (2048),
+    fewer than the direct one (3072): the call re-runs with the direct kernel
+    and matches the oracle; variant 0 forced reports the overflow."""
+    from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
+    F = _lopsided()
+    G3 = grid3(r_max=1500.0, n_r=6, n_t=4, n_c=5)
+    check3(run3(lib, F, G3, expect_variant=1), O.xi3_sums(F, G3), "fallback")
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, G3, variant=0)
+    assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_xi3_single_bin_closed_form(lib, variant):
     """Every triangle in one bin: the sums run over all ordered triples of
     distinct forests, S1^3 - 3 S1 S2 + 2 S3 with S_p the power sums of the
     per-forest sums (W, counts alike); tolerance relative to the same form of
     the absolute values, since ~5e7 entries meet in one FP64 accumulator."""
     F = truncate(make_patch(10, 0.3, 7, z_range=(2.1, 2.3)), 40)
     G3 = O.Grid3(np.array([0.0, 1e5]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
-    out = run3(lib, F, G3)
+    out = run3(lib, F, G3, variant=variant, expect_variant=variant)
     fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
 
     def triple(a):
@@ -109,14 +157,15 @@ def test_xi3_single_bin_closed_form(lib):
     assert abs(out["wsum"][0, 0] - triple(F.weight)) <= 1e-10 * triple(F.weight)
 
 
-def test_xi3_eboss_density_properties(lib):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_xi3_eboss_density_properties(lib, variant):
     """300 forests at the eBOSS-like density, r to 40 Mpc/h on 10 x 10 x 10 x 5
     x 5 bins (5.6e9 entries): counts symmetric under (r1, theta1) <->
     (r2, theta2), N and W symmetric to rounding."""
     F, _, _ = make_config(1, seed=1, scale=0.05)
     S = subset_forests(F, nearest_to_centre(F, 300))
     G3 = grid3(r_max=40.0, n_r=10, n_t=5, n_c=10)
-    out = run3(lib, S, G3)
+    out = run3(lib, S, G3, variant=variant)
     sh = (10, 10, 10, 5, 5)
     c = out["ntrip"][0].reshape(sh)
     print(f"[xi3 eboss-300] entries={int(c.sum())}", flush=True)
@@ -151,6 +200,14 @@ def test_xi3_invalid_grids(lib):
     expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.5, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 0.0, 0.2, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 1.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 1.0])))
+    # variant 0 on a grid whose n_cos n_theta exceeds its LDS slice; variant 2
+    wide = O.Grid3(np.array([0.0, 10.0]), np.linspace(0.0, np.pi, 41), np.linspace(-1.0, 1.0, 61))
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, wide, variant=0)
+    assert ei.value.status == LYA_E_UNSUPPORTED
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, grid3(), variant=2)
+    assert ei.value.status == LYA_E_INVALID
 
 
 def test_xi3_projected_deltas_vs_oracle(lib):
