@@ -217,8 +217,8 @@ lya_status lya_xi_covariance(lya_context *ctx, const double *num, const double *
    r >= r_max outside), the angles theta1, theta2 of the sides to the line of
    sight of the vertex's quasar on theta_edges (strictly increasing within
    [0, pi], any spacing), and the cosine of the inner angle on cos_edges
-   (uniform within [-1, 1]); theta and cos bins are half-open with the last
-   one closed.  Flat index
+   (uniform within [-1, 1], n_cos <= 256); theta and cos bins are half-open
+   with the last one closed.  Flat index
      A = (((k_r1 n_r + k_r2) n_cos + k_cos) n_theta + k_theta1) n_theta + k_theta2
    (the order of the paper's 3PCF figure), n_bins = n_r^2 n_cos n_theta^2 <= 2^30. */
 typedef struct {

@@ -25,11 +25,12 @@ namespace lya {
 
 namespace {
 
-constexpr int kBlock3 = 512;
+constexpr int kBlock3 = 1024;
 constexpr int kCap3 = 3072;    // partner pixels of one vertex held in LDS (direct kernel)
 constexpr int kCapC = 2048;    // the same for the combining kernel
 constexpr int kSliceC = 2048;  // bins of the combining kernel's LDS histogram slice
 constexpr int kCellC = 1024;   // (r, theta) cells of a side, combining kernel
+constexpr int kCosC = 256;     // cos alpha bins held in LDS (both kernels)
 
 // Partners of one vertex pixel: unit vector of the side, w d, w, the side's
 // bins k_r | k_t << 16 and the partner's forest.
@@ -43,6 +44,7 @@ struct Partners {
 
 struct Xi3Smem {
   Partners<kCap3> p;
+  double ce[kCosC + 1];  // cos alpha edges
   int32_t m;  // partners appended
   int64_t item;
 };
@@ -52,11 +54,10 @@ struct Xi3SmemC {
   double hn[kSliceC], hw[kSliceC];  // slice of the sums: side-2 r bins [r_lo, r_lo + rb) x cos x theta
   uint32_t hc[kSliceC];
   uint16_t perm[kCapC];             // partners ordered by cell k_r n_t + k_t
-  uint16_t touched[kSliceC];        // slice bins that are not zero
   int32_t cstart[kCellC + 1];       // first position of each cell in perm
   int32_t cfill[kCellC];
+  double ce[kCosC + 1];             // cos alpha edges
   int32_t m;
-  int32_t ntouch[2];
   int64_t item;
 };
 
@@ -140,13 +141,39 @@ __device__ __forceinline__ void gather_partners(const Xi3Args& a, const Item& it
   }
 }
 
+// The cos alpha axis with its edges in LDS and the end edges in registers (a
+// load from the edge array in global memory would be a vector load waited for
+// on every entry: the sums the kernels write could alias it).
+struct CosAxis {
+  const double* e;  // LDS copy, [n + 1]
+  double lo, hi, inv;
+  int n;
+};
+
+// Bin of x on the cos alpha axis, the last bin closed (-1 outside).
+__device__ __forceinline__ int cos_axis_bin(const CosAxis& c, double x) {
+  if (x < c.lo) return -1;
+  if (x >= c.hi) return x == c.hi ? c.n - 1 : -1;
+  int k = (int)__dmul_rn(__dsub_rn(x, c.lo), c.inv);
+  k = k < 0 ? 0 : (k > c.n - 1 ? c.n - 1 : k);
+  while (k > 0 && x < c.e[k]) --k;
+  while (k < c.n - 1 && x >= c.e[k + 1]) ++k;
+  return k;
+}
+
+// Copies the cos alpha edges to LDS (the caller synchronises before use).
+__device__ __forceinline__ CosAxis load_cos_axis(const Xi3Args& a, double* lds) {
+  for (int k = threadIdx.x; k <= a.n_c; k += kBlock3) lds[k] = a.cos_edges[k];
+  return CosAxis{lds, a.cos_edges[0], a.cos_edges[a.n_c], a.c_inv, a.n_c};
+}
+
 // cos alpha bin of the partners j, k (-1 outside the grid).
 template <int CAP>
-__device__ __forceinline__ int cos_bin(const Xi3Args& a, const Partners<CAP>& P, int j, int k) {
+__device__ __forceinline__ int cos_bin(const CosAxis& cx, const Partners<CAP>& P, int j, int k) {
   double ca = __dadd_rn(__dadd_rn(__dmul_rn(P.ux[j], P.ux[k]), __dmul_rn(P.uy[j], P.uy[k])),
                         __dmul_rn(P.uz[j], P.uz[k]));
   ca = fmin(1.0, fmax(-1.0, ca));
-  return uniform_bin(ca, a.cos_edges, a.n_c, a.c_e0, a.c_inv, true);
+  return cos_axis_bin(cx, ca);
 }
 
 // The copy of the sums this workgroup adds to: with one copy per XCD, the copy
@@ -162,6 +189,7 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
   __shared__ Xi3Smem sm;
   const int tid = threadIdx.x;
   const int nr = a.n_r, nt = a.n_t, nc = a.n_c;
+  const CosAxis cx = load_cos_axis(a, sm.ce);
 
   for (;;) {
     __syncthreads();  // every thread has read the previous item
@@ -196,7 +224,7 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
       const int dj = kBlock3 / m, dk = kBlock3 - dj * m;
       for (int64_t t = tid; t < total; t += kBlock3) {
         if (sm.p.fid[j] != sm.p.fid[k]) {
-          const int kc = cos_bin(a, sm.p, j, k);
+          const int kc = cos_bin(cx, sm.p, j, k);
           if (kc >= 0) {
             const int kj = sm.p.key[j], kk = sm.p.key[k];
             const int64_t A = ((((int64_t)(kj & 0xffff) * nr + (kk & 0xffff)) * nc + kc) * nt + (kj >> 16)) * nt +
@@ -222,24 +250,26 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
 // Combining kernel.  Entries of one vertex whose first side lies in one
 // (r, theta) cell differ only in (k_r2, k_c, k_t2): the partners are ordered by
 // cell, and for each cell of the first side (and each block of rb side-2 r
-// bins) the entries are summed in an LDS slice of n_t n_c rb bins, then the
-// slice's non-zero bins go to the global sums with three atomics each.  On the
-// eBOSS-like workload this takes the global atomics down ~7x.
+// bins) the entries are summed in an LDS slice of n_t n_c rb bins with LDS
+// atomics, then the slice's non-zero bins go to the global sums with three
+// atomics each.  On the eBOSS-like workload this takes the global atomics
+// down ~7x.
 __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
   __shared__ Xi3SmemC sm;
   const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int NW = kBlock3 / 64;
   const int nr = a.n_r, nt = a.n_t, nc = a.n_c;
   const int ncell = nr * nt;
   const int rb = kSliceC / (nc * nt);  // >= 1, checked by the host
   const int nblk = (nr + rb - 1) / rb;
-  int par = 0;
+  const CosAxis cx = load_cos_axis(a, sm.ce);
 
   for (int s = tid; s < kSliceC; s += kBlock3) {
     sm.hn[s] = 0.0;
     sm.hw[s] = 0.0;
     sm.hc[s] = 0u;
   }
-  if (tid == 0) sm.ntouch[0] = sm.ntouch[1] = 0;
 
   for (;;) {
     __syncthreads();  // every thread has read the previous item
@@ -313,50 +343,58 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
           const int r_lo = b * rb, r_hi = min(nr, r_lo + rb);
           const int k0 = sm.cstart[r_lo * nt], mk = sm.cstart[r_hi * nt] - k0;
           if (mk == 0) continue;
-          // the other counter's flush ended before the last barrier
-          if (tid == 0) sm.ntouch[par ^ 1] = 0;
-          const int total = nj * mk;
-          int jj = tid / mk, kk = tid - (tid / mk) * mk;
-          const int dj = kBlock3 / mk, dk = kBlock3 - dj * mk;
-          for (int t0 = 0; t0 < total; t0 += kBlock3) {
-            bool fresh = false;
-            int s = 0;
-            if (t0 + tid < total) {
-              const int j = sm.perm[j0 + jj], k = sm.perm[k0 + kk];
-              if (sm.p.fid[j] != sm.p.fid[k]) {
-                const int kc = cos_bin(a, sm.p, j, k);
+          // units of (64 side-2 partners, a part of the side-1 partners), a
+          // wave per unit: the side-2 partners stay in registers while the
+          // wave runs over its side-1 partners, and the lanes take partners
+          // spread over the cells (fewer lanes adding to one LDS bin at once)
+          const int nkc = (mk + 63) >> 6;
+          int P = (2 * NW + nkc - 1) / nkc;
+          P = P < nj ? P : nj;
+          const int U = nkc * P;
+          for (int u = wv; u < U; u += NW) {
+            const int c = u % nkc, pp = u / nkc;
+            const int kk = lane * nkc + c;
+            const bool kon = kk < mk;
+            double kx = 0.0, ky = 0.0, kz = 0.0, kwd = 0.0, kw = 0.0;
+            int kfid = -1, sk = 0;
+            if (kon) {
+              const int k = sm.perm[k0 + kk];
+              kx = sm.p.ux[k];
+              ky = sm.p.uy[k];
+              kz = sm.p.uz[k];
+              kwd = sm.p.wd[k];
+              kw = sm.p.w[k];
+              kfid = sm.p.fid[k];
+              const int kq = sm.p.key[k];
+              sk = ((kq & 0xffff) - r_lo) * nc * nt + (kq >> 16);
+            }
+            const int jb = pp * nj / P, je = (pp + 1) * nj / P;
+            for (int jj = jb; jj < je; ++jj) {
+              const int j = sm.perm[j0 + jj];
+              if (kon && sm.p.fid[j] != kfid) {
+                double ca = __dadd_rn(__dadd_rn(__dmul_rn(sm.p.ux[j], kx), __dmul_rn(sm.p.uy[j], ky)),
+                                      __dmul_rn(sm.p.uz[j], kz));
+                ca = fmin(1.0, fmax(-1.0, ca));
+                const int kc = cos_axis_bin(cx, ca);
                 if (kc >= 0) {
-                  const int kq = sm.p.key[k];
-                  s = (((kq & 0xffff) - r_lo) * nc + kc) * nt + (kq >> 16);
-                  const double pn = __dmul_rn(__dmul_rn(wdi, sm.p.wd[j]), sm.p.wd[k]);
-                  const double pw = __dmul_rn(__dmul_rn(wi, sm.p.w[j]), sm.p.w[k]);
-                  fresh = atomicAdd(&sm.hc[s], 1u) == 0u;
+                  const int s = sk + kc * nt;
+                  const double pn = __dmul_rn(__dmul_rn(wdi, sm.p.wd[j]), kwd);
+                  const double pw = __dmul_rn(__dmul_rn(wi, sm.p.w[j]), kw);
+                  atomicAdd(&sm.hc[s], 1u);
                   atomicAdd(&sm.hn[s], pn);
                   atomicAdd(&sm.hw[s], pw);
                 }
               }
             }
-            const uint64_t bal = __ballot(fresh);
-            if (bal != 0ull) {
-              int base = 0;
-              if (lane == 0) base = atomicAdd(&sm.ntouch[par], __popcll(bal));
-              base = __shfl(base, 0, 64);
-              if (fresh) sm.touched[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)s;
-            }
-            kk += dk;
-            jj += dj;
-            if (kk >= mk) {
-              kk -= mk;
-              ++jj;
-            }
           }
           __syncthreads();
-          // ---- flush the slice's non-zero bins and clear them
-          const int nto = sm.ntouch[par];
-          for (int q = tid; q < nto; q += kBlock3) {
-            const int s = sm.touched[q];
-            const double vn = sm.hn[s], vw = sm.hw[s];
+          // ---- flush the slice's non-zero bins and clear them (a scan of the
+          // slice costs less than keeping a list of the bins touched)
+          const int nsl = min(nr - r_lo, rb) * nc * nt;
+          for (int s = tid; s < nsl; s += kBlock3) {
             const uint32_t vc = sm.hc[s];
+            if (vc == 0u) continue;
+            const double vn = sm.hn[s], vw = sm.hw[s];
             sm.hn[s] = 0.0;
             sm.hw[s] = 0.0;
             sm.hc[s] = 0u;
@@ -367,7 +405,6 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
             atomicAdd(&a.ntrip[obase + A], (unsigned long long)vc);
           }
           __syncthreads();
-          par ^= 1;
         }
       }
     }
@@ -458,5 +495,7 @@ int xi3_combine_capacity() { return kCapC; }
 bool xi3_can_combine(int n_r, int n_t, int n_c) {
   return (int64_t)n_r * n_t <= kCellC && (int64_t)n_c * n_t <= kSliceC;
 }
+
+int xi3_max_cos_bins() { return kCosC; }
 
 }  // namespace lya

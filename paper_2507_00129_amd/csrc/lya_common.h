@@ -334,6 +334,7 @@ hipError_t launch_xi3(const Xi3Args& a, bool combine, int blocks, hipStream_t st
 int xi3_blocks_per_cu(bool combine);
 bool xi3_can_combine(int n_r, int n_t, int n_c);
 int xi3_combine_capacity();
+int xi3_max_cos_bins();
 int xi3_partner_capacity();
 int xi_means_blocks_per_cu(int precision, int n_bins);
 hipError_t launch_finalize_means(const double* wsum, const double* msum, int64_t n, const GridDev& g,

@@ -641,6 +641,8 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
   if (!te || !ce) return fail(ctx, LYA_E_INVALID, "NULL theta_edges or cos_edges");
   if (nt < 1 || nc < 1) return fail(ctx, LYA_E_INVALID, "n_theta and n_cos must be >= 1");
   if (nt > 1024) return fail(ctx, LYA_E_UNSUPPORTED, "n_theta = %d exceeds 1024", nt);
+  if (nc > xi3_max_cos_bins())
+    return fail(ctx, LYA_E_UNSUPPORTED, "n_cos = %d exceeds %d", nc, xi3_max_cos_bins());
   for (int k = 0; k <= nt; ++k)
     if (!isfinite(te[k]) || te[k] < 0.0 || te[k] > kPi || (k > 0 && !(te[k] > te[k - 1])))
       return fail(ctx, LYA_E_INVALID, "theta_edges must increase strictly within [0, pi] (edge %d)", k);

@@ -200,6 +200,7 @@ def test_xi3_invalid_grids(lib):
     expect(LYA_E_INVALID, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.5, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 0.0, 0.2, 1.0])))
     expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 1.0, 10.0]), np.array([0.0, 1.0]), np.array([-1.0, 1.0])))
+    expect(LYA_E_UNSUPPORTED, O.Grid3(np.array([0.0, 10.0]), np.array([0.0, 1.0]), np.linspace(-1.0, 1.0, 258)))
     # variant 0 on a grid whose n_cos n_theta exceeds its LDS slice; variant 2
     wide = O.Grid3(np.array([0.0, 10.0]), np.linspace(0.0, np.pi, 41), np.linspace(-1.0, 1.0, 61))
     with pytest.raises(LyaError) as ei:
