@@ -299,13 +299,16 @@ def main():
         for k in range(2):
             o3 = lib.xi3(dS, g3, timing=True)
             ms.append(lib.last_stats()["ms_main"])
+        variant = lib.last_stats()["variant"]
         torch.cuda.synchronize()
         entries = int(o3["ntrip"].sum().item())
         t3 = ms[-1] / 1e3
+        # ms_kernel: the triplet kernel plus the sum of the per-XCD copies
         xi3 = dict(workload=f"{S.n_forests} forests nearest the centre of the eBOSS-like patch "
                             f"({S.n_pix} pixels); r to 40 Mpc/h (10 bins), theta 10 bins, cos alpha 20 bins",
-                   entries=entries, ms_kernel=ms[-1], entries_per_s=entries / t3,
-                   global_atomics_per_s=3.0 * entries / t3, dtype="f64")
+                   kernel="xi3c_kernel (entries summed in LDS per side-1 cell)" if variant == 0
+                   else "xi3_kernel (global atomics per entry)",
+                   entries=entries, ms_kernel=ms[-1], entries_per_s=entries / t3, dtype="f64")
         log(f"[bench] xi3: {entries:.3e} entries in {ms[-1]:.1f} ms ({entries / t3:.3e} entries/s)")
         del dS, o3
 
