@@ -123,6 +123,21 @@ typedef struct {
                                  p in (0, 1], p = 1 keeps all (Sec. 2.2: D on a
                                  subset of forest pairs) */
   uint64_t seed;
+  int32_t deterministic;      /* lya_xi: bitwise-reproducible sums, independent of
+                                 the order the GPU adds pairs in, and identical
+                                 for a realisation run alone or batched with
+                                 others.  Each pair's products w d w d and w w
+                                 (in the precision's arithmetic) are scaled by
+                                 2^s_r and rounded to an integer q, |q| <= 2^55,
+                                 with s_r per realisation from the largest |w d|
+                                 and w of its pixels; the integers are summed
+                                 exactly (two 64-bit words) and N, W converted
+                                 to FP64 at the end.  The rounding adds at most
+                                 2^-56 max|w d|^2 (max w^2) per pair.  Needs
+                                 fewer than 2^36 pairs per bin and realisation
+                                 (LYA_E_UNSUPPORTED otherwise); one fixed kernel
+                                 variant.  The other calls return
+                                 LYA_E_UNSUPPORTED when it is set. */
 } lya_options;
 
 /* What the last call on a context did. */
@@ -147,7 +162,8 @@ typedef struct {
 typedef struct lya_context lya_context;
 
 /* Fills *opts with defaults: FP32_COMP, MEAN_SLOPE, no projection,
-   autotune on, validate on, timing off, variant -1, keep fraction 1, seed 0. */
+   autotune on, validate on, timing off, variant -1, keep fraction 1, seed 0,
+   deterministic off. */
 void lya_options_default(lya_options *opts);
 
 /* Creates a context bound to HIP device `device`.  The context owns a

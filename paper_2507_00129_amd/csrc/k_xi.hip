@@ -25,6 +25,13 @@
 // products of the same bin are first summed in FP32 registers (runs end at
 // every 32nd pixel of f, so a run holds at most 32 products).
 //
+// Deterministic form (DET).  Each in-grid pair's products, in the form's
+// arithmetic, are scaled by 2^s (s per realisation, from its largest |w d| and
+// w, so that |product| 2^s <= 2^55), rounded to integers and summed exactly as
+// two 64-bit words (low 28 bits and the rest), in LDS and then in global
+// memory; integer addition does not depend on the order, so the sums are
+// bitwise reproducible and identical for a realisation alone or batched.
+//
 // Bin means.  The MEANS form also sums w_i w_j x_par, w_i w_j x_perp (the bin
 // coordinates x = (r - e0) / dr the binning already computes) and
 // w_i w_j (z_i + z_j), with the pixel redshift z packed in the record's fourth
@@ -88,6 +95,28 @@ template <> struct Batch<Rec64> {
   }
 };
 
+// Fixed-point terms of the deterministic form: q = rint(x), |q| <= 2^55, split
+// as q = hi 2^28 + lo with 0 <= lo < 2^28; the two words are summed in separate
+// 64-bit integers (two's complement for hi), exact for fewer than 2^36 terms.
+constexpr int kDetShift = 28;
+constexpr int kDetBits = 55;
+
+__device__ __forceinline__ void det_add(unsigned long long* h, double x) {
+  const long long q = __double2ll_rn(x);
+  atomicAdd(&h[0], (unsigned long long)(q & ((1ll << kDetShift) - 1)));
+  atomicAdd(&h[1], (unsigned long long)(q >> kDetShift));
+}
+
+// s for products below m^2, m given by the bits of a non-negative double:
+// s = 55 - 2 e with m < 2^e (clamped to the double's range).
+__device__ __forceinline__ int det_shift(unsigned long long mbits) {
+  if (mbits == 0ull) return 0;
+  const int E = (int)(mbits >> 52);
+  const int e = (E == 0 ? 1 : E) - 1022;
+  const int sh = kDetBits - 2 * e;
+  return sh > 1000 ? 1000 : (sh < -1000 ? -1000 : sh);
+}
+
 template <typename T> struct RecOf;
 template <> struct RecOf<float> { using type = Rec32; };
 template <> struct RecOf<double> { using type = Rec64; };
@@ -125,9 +154,31 @@ __device__ void flush_hist(const XiArgs& a, double* hNW, double* hM, unsigned* h
   }
 }
 
-template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS>
+// Deterministic form's LDS sums: hq[4 L + c] (N low, N high, W low, W high),
+// hn[L] = pair count.
+template <int BLOCK>
+__device__ void flush_det(const XiArgs& a, unsigned long long* hq, unsigned* hn, int real) {
+  const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
+  const int64_t base = (int64_t)real * nb;
+  for (int L = threadIdx.x; L < nb; L += BLOCK) {
+    const unsigned c = hn[L];
+    if (c) {
+      const int kp = L % NP, kt = L / NP;
+      const int64_t A = base + (int64_t)kp * NT + kt;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) atomicAdd(&a.det_acc[4 * A + w], hq[4 * L + w]);
+      atomicAdd(&a.npairs[A], (unsigned long long)c);
+    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w) hq[4 * L + w] = 0ull;
+    hn[L] = 0u;
+  }
+}
+
+template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS, bool DET = false>
 __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   static_assert(RLE || !MEANS, "bin means are accumulated by the run-length form");
+  static_assert(!(DET && (RLE || MEANS)), "the deterministic form adds every pair");
   using Rec = typename RecOf<T>::type;
   extern __shared__ double smem[];
   __shared__ NbTable tb;
@@ -136,10 +187,16 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   const int NP = a.g.n_par, NT = a.g.n_perp, nb = NP * NT;
   double* hNW = smem;
   double* hM = smem + 2 * nb;
-  unsigned* hn = (unsigned*)(smem + (MEANS ? 5 : 2) * nb);
+  unsigned* hn = (unsigned*)(smem + (DET ? 4 : (MEANS ? 5 : 2)) * nb);
+  unsigned long long* hq = (unsigned long long*)smem;  // DET
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   for (int L = threadIdx.x; L < nb; L += BLOCK) {
+    if constexpr (DET) {
+      hq[4 * L] = hq[4 * L + 1] = hq[4 * L + 2] = hq[4 * L + 3] = 0ull;
+      hn[L] = 0u;
+      continue;
+    }
     hNW[2 * L] = 0.0;
     hNW[2 * L + 1] = 0.0;
     if constexpr (MEANS) {
@@ -162,6 +219,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
 
   int cur_key = -1;
   double pending = 0.0;  // upper bound on pairs added to any bin since the last flush
+  double scN = 1.0, scW = 1.0;  // DET: 2^s of the current realisation
   __syncthreads();
 
   for (;;) {
@@ -203,11 +261,15 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     const int okey = a.sub ? fi.real * a.n_sub + a.sub[f] : fi.real;
     if (okey != cur_key || pending + (double)total * fi.npix > 4.0e9) {
       if (cur_key >= 0) {
-        flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
+        if constexpr (DET) flush_det<BLOCK>(a, hq, hn, cur_key); else flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
         __syncthreads();
       }
       cur_key = okey;
       pending = 0.0;
+      if constexpr (DET) {
+        scN = ldexp(1.0, det_shift(a.det_max[2 * okey]));
+        scW = ldexp(1.0, det_shift(a.det_max[2 * okey + 1]));
+      }
     }
     pending += (double)total * fi.npix;
 
@@ -323,8 +385,13 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
           T xp, xt;
           const int A = bin_of(ri, i, xp, xt);
           if (A >= 0) {
-            atomicAdd(&hNW[2 * A], (double)(ri.wd * wdj));
-            atomicAdd(&hNW[2 * A + 1], (double)(ri.w * wj));
+            if constexpr (DET) {
+              det_add(&hq[4 * A], __dmul_rn((double)(ri.wd * wdj), scN));
+              det_add(&hq[4 * A + 2], __dmul_rn((double)(ri.w * wj), scW));
+            } else {
+              atomicAdd(&hNW[2 * A], (double)(ri.wd * wdj));
+              atomicAdd(&hNW[2 * A + 1], (double)(ri.w * wj));
+            }
             atomicAdd(&hn[A], 1u);
           }
         };
@@ -341,7 +408,9 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
     __syncthreads();
   }
   __syncthreads();
-  if (cur_key >= 0) flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
+  if (cur_key >= 0) {
+    if constexpr (DET) flush_det<BLOCK>(a, hq, hn, cur_key); else flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
+  }
 }
 
 struct Variant {
@@ -357,15 +426,15 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <bool MEANS>
+template <bool MEANS, bool DET = false>
 constexpr size_t smem_per_bin() {
-  return (MEANS ? 5 : 2) * sizeof(double) + sizeof(unsigned);
+  return (DET ? 4 : (MEANS ? 5 : 2)) * sizeof(double) + sizeof(unsigned);
 }
 
-template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS = false>
+template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS = false, bool DET = false>
 hipError_t launch_one(const XiArgs& a, int blocks, hipStream_t st) {
-  const size_t smem = (size_t)a.g.n_par * a.g.n_perp * smem_per_bin<MEANS>();
-  auto kern = xi_kernel<T, BLOCK, RLE, ZLO, MEANS>;
+  const size_t smem = (size_t)a.g.n_par * a.g.n_perp * smem_per_bin<MEANS, DET>();
+  auto kern = xi_kernel<T, BLOCK, RLE, ZLO, MEANS, DET>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(BLOCK), smem, st, a);
@@ -389,10 +458,10 @@ hipError_t launch_t(int v, const XiArgs& a, int blocks, hipStream_t st) {
   return zlo ? launch_z<T, true>(v, a, blocks, st) : launch_z<T, false>(v, a, blocks, st);
 }
 
-template <typename T, int BLOCK, bool RLE, bool MEANS = false>
+template <typename T, int BLOCK, bool RLE, bool MEANS = false, bool DET = false>
 int occupancy(int n_bins) {
-  const size_t smem = (size_t)n_bins * smem_per_bin<MEANS>();
-  auto kern = xi_kernel<T, BLOCK, RLE, true, MEANS>;
+  const size_t smem = (size_t)n_bins * smem_per_bin<MEANS, DET>();
+  auto kern = xi_kernel<T, BLOCK, RLE, true, MEANS, DET>;
   if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 1;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, kern, BLOCK, smem) != hipSuccess) return 1;
@@ -428,6 +497,46 @@ __global__ void finalize_means_kernel(const double* wsum, const double* msum, in
   z[i] = e ? 0.0 : 0.5 * (msum[2 * n + i] / w);
 }
 
+// Largest |w delta| and w of each realisation, as bits of non-negative doubles
+// (their order is the doubles' order), one wave per forest.
+__global__ __launch_bounds__(256) void det_max_kernel(lya_forests F, const ForestInfo* finfo, const double* delta,
+                                                    unsigned long long* det_max) {
+  const int lane = threadIdx.x & 63;
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (f >= F.n_forests) return;
+  const ForestInfo fi = finfo[f];
+  double mwd = 0.0, mw = 0.0;
+  for (int k = lane; k < fi.npix; k += 64) {
+    const int64_t i = fi.pix0 + k;
+    const double w = F.weight[i];
+    mwd = fmax(mwd, fabs(__dmul_rn(w, delta[i])));
+    mw = fmax(mw, w);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mwd = fmax(mwd, __shfl_xor(mwd, o, 64));
+    mw = fmax(mw, __shfl_xor(mw, o, 64));
+  }
+  if (lane == 0) {
+    atomicMax(&det_max[2 * fi.real], (unsigned long long)__double_as_longlong(mwd));
+    atomicMax(&det_max[2 * fi.real + 1], (unsigned long long)__double_as_longlong(mw));
+  }
+}
+
+// N, W from the integer sums: (hi 2^28 + lo) 2^-s.
+__global__ void finalize_det_kernel(const unsigned long long* acc, const unsigned long long* det_max,
+                                    const unsigned long long* npairs, int64_t n, int n_bins, double* num,
+                                    double* wsum, Globals* glob) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = i / n_bins;
+  const int sN = det_shift(det_max[2 * r]), sW = det_shift(det_max[2 * r + 1]);
+  const double vn = __dadd_rn(ldexp((double)(long long)acc[4 * i + 1], kDetShift), (double)acc[4 * i]);
+  const double vw = __dadd_rn(ldexp((double)(long long)acc[4 * i + 3], kDetShift), (double)acc[4 * i + 2]);
+  num[i] = ldexp(vn, -sN);
+  wsum[i] = ldexp(vw, -sW);
+  if (npairs[i] >= (1ull << 36)) atomicOr(&glob->flag, kBadDet);
+}
+
 __global__ void finalize_xi_kernel(const double* num, const double* wsum, double* xi, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -448,6 +557,41 @@ hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hi
 
 int xi_blocks_per_cu(int variant, int precision, int n_bins) {
   return precision == LYA_FP64 ? occ_t<double>(variant, n_bins) : occ_t<float>(variant, n_bins);
+}
+
+// The deterministic form: 512 threads, one pair per lane and step.
+constexpr int kDetBlock = 512;
+
+hipError_t launch_xi_det(int precision, const XiArgs& a, int blocks, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  const bool zlo = a.g.zero_lo_par && a.g.zero_lo_perp;
+  if (precision == LYA_FP64)
+    return zlo ? launch_one<double, kDetBlock, false, true, false, true>(a, blocks, st)
+               : launch_one<double, kDetBlock, false, false, false, true>(a, blocks, st);
+  return zlo ? launch_one<float, kDetBlock, false, true, false, true>(a, blocks, st)
+             : launch_one<float, kDetBlock, false, false, false, true>(a, blocks, st);
+}
+
+int xi_det_blocks_per_cu(int precision, int n_bins) {
+  return precision == LYA_FP64 ? occupancy<double, kDetBlock, false, false, true>(n_bins)
+                               : occupancy<float, kDetBlock, false, false, true>(n_bins);
+}
+
+hipError_t launch_det_max(const lya_forests* F, const ForestInfo* finfo, const double* delta,
+                          unsigned long long* det_max, hipStream_t st) {
+  if (F->n_forests == 0) return hipSuccess;
+  hipLaunchKernelGGL(det_max_kernel, dim3((unsigned)((F->n_forests + 3) / 4)), dim3(256), 0, st, *F, finfo, delta,
+                     det_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_det(const unsigned long long* det_acc, const unsigned long long* det_max,
+                               const unsigned long long* npairs, int64_t n_out, int n_bins, double* num,
+                               double* wsum, Globals* glob, hipStream_t st) {
+  if (n_out == 0) return hipSuccess;
+  hipLaunchKernelGGL(finalize_det_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st, det_acc, det_max,
+                     npairs, n_out, n_bins, num, wsum, glob);
+  return hipGetLastError();
 }
 
 // The bin-means form: one run-length variant, kMeansBlock threads (its

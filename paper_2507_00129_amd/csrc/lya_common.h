@@ -74,7 +74,7 @@ struct GridDev {
 // Validation error bits (Globals::flag).
 enum : int32_t {
   kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32,
-  kBadSub = 64, kBadCap3 = 128, kBadCapC = 256
+  kBadSub = 64, kBadCap3 = 128, kBadCapC = 256, kBadDet = 512
 };
 
 // ---------------------------------------------------------------- geometry
@@ -233,10 +233,25 @@ struct XiArgs {
   // sum w w x_perp (bin units), sum w w (z_i + z_j)
   double* msum;
   int64_t n_out;
+  // deterministic form: det_max[2 r], det_max[2 r + 1] = bit patterns of the
+  // largest |w d| and w of realisation r; det_acc[4 A + c] = exact integer sums
+  // (N low, N high, W low, W high words)
+  const unsigned long long* det_max;
+  unsigned long long* det_acc;
 };
 int xi_num_variants();
 const char* xi_variant_name(int v);
 hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hipStream_t st);
+// deterministic form (fixed-point integer sums, one variant)
+hipError_t launch_xi_det(int precision, const XiArgs& a, int blocks, hipStream_t st);
+int xi_det_blocks_per_cu(int precision, int n_bins);
+// det_max[2 r], [2 r + 1] = largest |w delta| and w of realisation r (as bits)
+hipError_t launch_det_max(const lya_forests* F, const ForestInfo* finfo, const double* delta,
+                          unsigned long long* det_max, hipStream_t st);
+// num, wsum from the integer sums; flags kBadDet where a bin has 2^36 pairs or more
+hipError_t launch_finalize_det(const unsigned long long* det_acc, const unsigned long long* det_max,
+                               const unsigned long long* npairs, int64_t n_out, int n_bins, double* num,
+                               double* wsum, Globals* glob, hipStream_t st);
 int xi_blocks_per_cu(int variant, int precision, int n_bins);
 
 struct DmatArgs {

@@ -389,6 +389,7 @@ void lya_options_default(lya_options* o) {
   o->counters = 0;
   o->dmat_keep_fraction = 1.0;
   o->seed = 0;
+  o->deterministic = 0;
 }
 
 lya_status lya_create(lya_context** out, int device) {
@@ -452,6 +453,8 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
   LYA_TRY(check_common(ctx, F, G, o, gd));
   if (!num || !wsum || !npairs) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or npairs");
   if (sub && n_sub < 1) return fail(ctx, LYA_E_INVALID, "n_sub must be >= 1");
+  if (o->deterministic && (sub || means))
+    return fail(ctx, LYA_E_UNSUPPORTED, "options.deterministic is honoured by lya_xi only");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ctx->err.clear();
@@ -508,6 +511,33 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
     a.n_sub = sub ? n_sub : 1;
     a.msum = msum;
     a.n_out = nout;
+
+    if (o->deterministic) {
+      // fixed-point integer sums with a scale per realisation; one variant
+      unsigned long long *det_max, *det_acc;
+      LYA_TRY(wst(ctx, "xi_det_max", (size_t)(2 * F->n_realisations), &det_max));
+      LYA_TRY(wst(ctx, "xi_det_acc", (size_t)(4 * nout), &det_acc));
+      HIP_TRY(launch_zero(det_max, (size_t)(2 * F->n_realisations) * sizeof(unsigned long long), st));
+      HIP_TRY(launch_zero(det_acc, (size_t)(4 * nout) * sizeof(unsigned long long), st));
+      HIP_TRY(launch_det_max(F, P.finfo, o->project_deltas ? P.delta_proj : F->delta, det_max, st));
+      a.det_max = det_max;
+      a.det_acc = det_acc;
+      const int blocks = xi_det_blocks_per_cu(o->precision, nb) * ctx->n_cu;
+      ctx->stats.variant = -1;
+      ctx->stats.grid_blocks = blocks;
+      HIP_TRY(launch_zero(counter, 4, st));
+      tm.at(3);
+      HIP_TRY(launch_xi_det(o->precision, a, blocks, st));
+      HIP_TRY(launch_finalize_det(det_acc, det_max, a.npairs, nout, nb, num, wsum, P.glob, st));
+      tm.at(4);
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (*(int32_t*)ctx->pinned & kBadDet)
+        return fail(ctx, LYA_E_UNSUPPORTED, "a bin holds 2^36 pairs or more (deterministic sums)");
+      HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
+      tm.at(5);
+      return tm.finish(ctx);
+    }
 
     if (means) {
       // one run-length form with the coordinate sums; no variant choice
@@ -661,6 +691,7 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
   const lya_grid G{1, 1, box, box};
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, &G, o, gd));
+  if (o->deterministic) return fail(ctx, LYA_E_UNSUPPORTED, "options.deterministic is honoured by lya_xi only");
   if (!num || !wsum || !ntrip) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or ntrip");
   if ((int64_t)F->n_realisations * n_bins > ((int64_t)1 << 40))
     return fail(ctx, LYA_E_UNSUPPORTED, "outputs too large");
@@ -789,6 +820,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
                     void* stream, double* dmat, double* wsum_d) {
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
+  if (o->deterministic) return fail(ctx, LYA_E_UNSUPPORTED, "options.deterministic is honoured by lya_xi only");
   if (!dmat || !wsum_d) return fail(ctx, LYA_E_INVALID, "NULL output dmat or wsum_d");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
@@ -932,6 +964,7 @@ lya_status lya_xi_backward(lya_context* ctx, const lya_forests* F, const lya_gri
                            double* grad_weight) {
   GridDev gd{};
   LYA_TRY(check_common(ctx, F, G, o, gd));
+  if (o->deterministic) return fail(ctx, LYA_E_UNSUPPORTED, "options.deterministic is honoured by lya_xi only");
   if (!grad_xi || !xi || !wsum) return fail(ctx, LYA_E_INVALID, "NULL grad_xi, xi or wsum");
   if (!grad_delta || !grad_weight) return fail(ctx, LYA_E_INVALID, "NULL output grad_delta or grad_weight");
   HIP_TRY(hipSetDevice(ctx->device));

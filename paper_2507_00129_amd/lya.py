@@ -57,6 +57,7 @@ class lya_options(ctypes.Structure):
         ("autotune", ctypes.c_int32), ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
         ("variant", ctypes.c_int32), ("counters", ctypes.c_int32),
         ("dmat_keep_fraction", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
@@ -219,7 +220,7 @@ class Library:
 
     def options(self, precision="fp32", eta="mean_slope", project_deltas=False, autotune=True,
                 validate=True, timing=False, keep_fraction=1.0, seed=0, variant=-1,
-                counters=False) -> lya_options:
+                counters=False, deterministic=False) -> lya_options:
         o = lya_options()
         self.lib.lya_options_default(ctypes.byref(o))
         o.precision = _PRECISION[precision]
@@ -232,6 +233,7 @@ class Library:
         o.dmat_keep_fraction = float(keep_fraction)
         o.seed = int(seed)
         o.variant = int(variant)
+        o.deterministic = int(bool(deterministic))
         return o
 
     def _check(self, status):

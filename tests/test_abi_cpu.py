@@ -33,7 +33,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.lya_forests) == 8 * 10 + 8
     assert ctypes.sizeof(L.lya_grid) == 24
     assert ctypes.sizeof(L.lya_grid3) == 4 * 3 + 4 + 3 * 8
-    assert ctypes.sizeof(L.lya_options) == 4 * 8 + 8 + 8
+    assert ctypes.sizeof(L.lya_options) == 4 * 8 + 8 + 8 + 8
+    assert L.lya_options.deterministic.offset == 48
     assert L.lya_options.dmat_keep_fraction.offset == 32
 
 
