@@ -30,7 +30,8 @@ constexpr int kCap3 = 3072;    // partner pixels of one vertex held in LDS (dire
 constexpr int kCapC = 2048;    // the same for the combining kernel
 constexpr int kSliceC = 2048;  // bins of the combining kernel's LDS histogram slice
 constexpr int kCellC = 1024;   // (r, theta) cells of a side, combining kernel
-constexpr int kCosC = 256;     // cos alpha bins held in LDS (both kernels)
+constexpr int kCosC = 256;     // cos alpha bins held in LDS (all kernels)
+constexpr int kJStage = 512;   // side-1 partners staged in LDS at a time (wide kernel)
 
 // Partners of one vertex pixel: unit vector of the side, w d, w, the side's
 // bins k_r | k_t << 16 and the partner's forest.
@@ -61,6 +62,42 @@ struct Xi3SmemC {
   int64_t item;
 };
 
+struct Xi3SmemW {
+  double jx[kJStage], jy[kJStage], jz[kJStage], jwd[kJStage], jw[kJStage];  // staged side-1 partners
+  int32_t jfid[kJStage];
+  double hn[kSliceC], hw[kSliceC];
+  uint32_t hc[kSliceC];
+  int32_t cstart[kCellC + 1];
+  int32_t cfill[kCellC];
+  double ce[kCosC + 1];
+  int32_t m;
+  int64_t item;
+};
+
+// A partner list in global memory (structure of arrays, cap entries each).
+struct GPartners {
+  double *ux, *uy, *uz, *wd, *w;
+  int32_t *key, *fid;
+  __device__ __forceinline__ void operator()(int s, double x, double y, double z, double pwd, double pw, int k,
+                                             int f) const {
+    ux[s] = x;
+    uy[s] = y;
+    uz[s] = z;
+    wd[s] = pwd;
+    w[s] = pw;
+    key[s] = k;
+    fid[s] = f;
+  }
+};
+
+// Workgroup b's two lists (as gathered, and ordered by cell) in the scratch.
+__device__ __forceinline__ GPartners scratch_list(const Xi3Args& a, int which) {
+  const int64_t cap = a.w_cap;
+  double* d = a.w_dbl + ((int64_t)blockIdx.x * 2 + which) * 5 * cap;
+  int32_t* i = a.w_int + ((int64_t)blockIdx.x * 2 + which) * 2 * cap;
+  return GPartners{d, d + cap, d + 2 * cap, d + 3 * cap, d + 4 * cap, i, i + cap};
+}
+
 // The XCD (accelerator complex die) the wave runs on, from the XCC_ID hardware
 // register (any value is correct: it only picks a copy of the sums).
 __device__ __forceinline__ unsigned xcd_id() {
@@ -82,15 +119,16 @@ __device__ __forceinline__ int uniform_bin(double x, const double* e, int n, dou
   return k;
 }
 
-// Appends to P every pixel of the item's neighbour forests whose side from the
+// Stores every pixel of the item's neighbour forests whose side from the
 // vertex (xi, yi, zi) has its length in the r grid and its angle to the line of
-// sight n of the vertex forest in the theta grid.  A wave per neighbour forest,
-// lanes over its pixels; one LDS atomic per wave reserves the slots.  *m counts
-// every partner, also those beyond CAP (which are not stored).
-template <int CAP>
+// sight n of the vertex forest in the theta grid, as
+// store(slot, ux, uy, uz, w d, w, k_r | k_t << 16, forest).  A wave per
+// neighbour forest, lanes over its pixels; one LDS atomic per wave reserves
+// the slots.  *m counts every partner, also those beyond cap (not stored).
+template <typename Store>
 __device__ __forceinline__ void gather_partners(const Xi3Args& a, const Item& item, const ForestInfo& fi,
-                                                double xi, double yi, double zi, Partners<CAP>& P,
-                                                int32_t* m) {
+                                                double xi, double yi, double zi, int cap, int32_t* m,
+                                                Store&& store) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = kBlock3 / 64;
   const int nr = a.n_r, nt = a.n_t;
@@ -127,15 +165,7 @@ __device__ __forceinline__ void gather_partners(const Xi3Args& a, const Item& it
       base = __shfl(base, 0, 64);
       if (keep) {
         const int slot = base + __popcll(bal & ((1ull << lane) - 1ull));
-        if (slot < CAP) {
-          P.ux[slot] = ux;
-          P.uy[slot] = uy;
-          P.uz[slot] = uz;
-          P.wd[slot] = a.pts[pj].wd;
-          P.w[slot] = a.pts[pj].w;
-          P.key[slot] = kr | (kt << 16);
-          P.fid[slot] = g;
-        }
+        if (slot < cap) store(slot, ux, uy, uz, a.pts[pj].wd, a.pts[pj].w, kr | (kt << 16), g);
       }
     }
   }
@@ -166,6 +196,21 @@ __device__ __forceinline__ CosAxis load_cos_axis(const Xi3Args& a, double* lds) 
   for (int k = threadIdx.x; k <= a.n_c; k += kBlock3) lds[k] = a.cos_edges[k];
   return CosAxis{lds, a.cos_edges[0], a.cos_edges[a.n_c], a.c_inv, a.n_c};
 }
+
+template <int CAP>
+struct LdsStore {
+  Partners<CAP>& P;
+  __device__ __forceinline__ void operator()(int s, double ux, double uy, double uz, double wd, double w, int key,
+                                             int fid) const {
+    P.ux[s] = ux;
+    P.uy[s] = uy;
+    P.uz[s] = uz;
+    P.wd[s] = wd;
+    P.w[s] = w;
+    P.key[s] = key;
+    P.fid[s] = fid;
+  }
+};
 
 // cos alpha bin of the partners j, k (-1 outside the grid).
 template <int CAP>
@@ -208,7 +253,7 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
       __syncthreads();  // the previous vertex's pairs have been read
       if (tid == 0) sm.m = 0;
       __syncthreads();
-      gather_partners<kCap3>(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, sm.p, &sm.m);
+      gather_partners(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, kCap3, &sm.m, LdsStore<kCap3>{sm.p});
       __syncthreads();
       const int m = sm.m;
       if (m > kCap3) {
@@ -293,7 +338,7 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
       if (tid == 0) sm.m = 0;
       for (int c = tid; c < ncell; c += kBlock3) sm.cfill[c] = 0;
       __syncthreads();
-      gather_partners<kCapC>(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, sm.p, &sm.m);
+      gather_partners(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, kCapC, &sm.m, LdsStore<kCapC>{sm.p});
       __syncthreads();
       const int m = sm.m;
       if (m > kCapC) {
@@ -411,6 +456,178 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
   }
 }
 
+// Wide kernel: the combining kernel's passes for vertex pixels with more
+// partners than LDS holds (up to a.w_cap).  The partner list is gathered into
+// the workgroup's scratch in global memory and copied there in cell order;
+// each pass stages the side-1 partners of its cell in LDS (kJStage at a time)
+// and the waves read their 64 side-2 partners from the ordered list.
+__global__ __launch_bounds__(kBlock3) void xi3w_kernel(Xi3Args a) {
+  __shared__ Xi3SmemW sm;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int NW = kBlock3 / 64;
+  const int nr = a.n_r, nt = a.n_t, nc = a.n_c;
+  const int ncell = nr * nt;
+  const int rb = kSliceC / (nc * nt);  // >= 1, checked by the host
+  const int nblk = (nr + rb - 1) / rb;
+  const CosAxis cx = load_cos_axis(a, sm.ce);
+  const GPartners L0 = scratch_list(a, 0), L1 = scratch_list(a, 1);
+
+  for (int s = tid; s < kSliceC; s += kBlock3) {
+    sm.hn[s] = 0.0;
+    sm.hw[s] = 0.0;
+    sm.hc[s] = 0u;
+  }
+
+  for (;;) {
+    __syncthreads();  // every thread has read the previous item
+    if (tid == 0) {
+      const bool over = __hip_atomic_load(&a.glob->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadCapW;
+      sm.item = over ? a.n_items : (int64_t)atomicAdd(a.counter, 1u);
+    }
+    __syncthreads();
+    const int64_t it = sm.item;
+    if (it >= a.n_items) break;
+    const Item item = a.items[it];
+    const int f = a.sorted[item.p];
+    const ForestInfo fi = a.finfo[f];
+    const int64_t obase = sums_base(a, fi);
+
+    for (int i = 0; i < fi.npix; ++i) {
+      const int64_t pi = fi.pix0 + i;
+      const double wdi = a.pts[pi].wd, wi = a.pts[pi].w;
+      __syncthreads();  // the previous vertex's partners have been read
+      if (tid == 0) sm.m = 0;
+      for (int c = tid; c < ncell; c += kBlock3) sm.cfill[c] = 0;
+      __syncthreads();
+      gather_partners(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, a.w_cap, &sm.m, L0);
+      __syncthreads();
+      const int m = sm.m;
+      if (m > a.w_cap) {
+        if (tid == 0) atomicOr(&a.glob->flag, kBadCapW);
+        continue;
+      }
+      if (m < 2) continue;
+
+      // ---- order the partners by cell into the second list
+      for (int j = tid; j < m; j += kBlock3) {
+        const int key = L0.key[j];
+        atomicAdd(&sm.cfill[(key & 0xffff) * nt + (key >> 16)], 1);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const int per = (ncell + 63) / 64, c0 = lane * per, c1 = min(ncell, c0 + per);
+        int own = 0;
+        for (int c = c0; c < c1; ++c) own += sm.cfill[c];
+        int incl = own;
+        for (int d = 1; d < 64; d <<= 1) {
+          const int v = __shfl_up(incl, d, 64);
+          if (lane >= d) incl += v;
+        }
+        int run = incl - own;
+        for (int c = c0; c < c1; ++c) {
+          sm.cstart[c] = run;
+          run += sm.cfill[c];
+          sm.cfill[c] = 0;
+        }
+        if (lane == 63) sm.cstart[ncell] = incl;
+      }
+      __syncthreads();
+      for (int j = tid; j < m; j += kBlock3) {
+        const int key = L0.key[j];
+        const int c = (key & 0xffff) * nt + (key >> 16);
+        const int q = sm.cstart[c] + atomicAdd(&sm.cfill[c], 1);
+        L1(q, L0.ux[j], L0.uy[j], L0.uz[j], L0.wd[j], L0.w[j], key, L0.fid[j]);
+      }
+      __syncthreads();  // the ordered list is complete (workgroup-scope fence)
+
+      // ---- one pass per (cell of side 1, block of side-2 r bins)
+      for (int c1 = 0; c1 < ncell; ++c1) {
+        const int j0 = sm.cstart[c1], nj = sm.cstart[c1 + 1] - j0;
+        if (nj == 0) continue;
+        const int kr1 = c1 / nt, kt1 = c1 - kr1 * nt;
+        for (int b = 0; b < nblk; ++b) {
+          const int r_lo = b * rb, r_hi = min(nr, r_lo + rb);
+          const int k0 = sm.cstart[r_lo * nt], mk = sm.cstart[r_hi * nt] - k0;
+          if (mk == 0) continue;
+          for (int jc = 0; jc < nj; jc += kJStage) {
+            const int njc = min(kJStage, nj - jc);
+            __syncthreads();  // the previous stage has been read
+            for (int t = tid; t < njc; t += kBlock3) {
+              const int q = j0 + jc + t;
+              sm.jx[t] = L1.ux[q];
+              sm.jy[t] = L1.uy[q];
+              sm.jz[t] = L1.uz[q];
+              sm.jwd[t] = L1.wd[q];
+              sm.jw[t] = L1.w[q];
+              sm.jfid[t] = L1.fid[q];
+            }
+            __syncthreads();
+            // units of (64 side-2 partners spread over the cells, a part of
+            // the staged side-1 partners), a wave per unit
+            const int nkc = (mk + 63) >> 6;
+            int P = (2 * NW + nkc - 1) / nkc;
+            P = P < njc ? P : njc;
+            const int U = nkc * P;
+            for (int u = wv; u < U; u += NW) {
+              const int c = u % nkc, pp = u / nkc;
+              const int kk = lane * nkc + c;
+              const bool kon = kk < mk;
+              double kx = 0.0, ky = 0.0, kz = 0.0, kwd = 0.0, kw = 0.0;
+              int kfid = -1, sk = 0;
+              if (kon) {
+                const int k = k0 + kk;
+                kx = L1.ux[k];
+                ky = L1.uy[k];
+                kz = L1.uz[k];
+                kwd = L1.wd[k];
+                kw = L1.w[k];
+                kfid = L1.fid[k];
+                const int kq = L1.key[k];
+                sk = ((kq & 0xffff) - r_lo) * nc * nt + (kq >> 16);
+              }
+              const int jb = pp * njc / P, je = (pp + 1) * njc / P;
+              for (int jj = jb; jj < je; ++jj) {
+                if (kon && sm.jfid[jj] != kfid) {
+                  double ca = __dadd_rn(__dadd_rn(__dmul_rn(sm.jx[jj], kx), __dmul_rn(sm.jy[jj], ky)),
+                                        __dmul_rn(sm.jz[jj], kz));
+                  ca = fmin(1.0, fmax(-1.0, ca));
+                  const int kc = cos_axis_bin(cx, ca);
+                  if (kc >= 0) {
+                    const int s = sk + kc * nt;
+                    const double pn = __dmul_rn(__dmul_rn(wdi, sm.jwd[jj]), kwd);
+                    const double pw = __dmul_rn(__dmul_rn(wi, sm.jw[jj]), kw);
+                    atomicAdd(&sm.hc[s], 1u);
+                    atomicAdd(&sm.hn[s], pn);
+                    atomicAdd(&sm.hw[s], pw);
+                  }
+                }
+              }
+            }
+          }
+          __syncthreads();
+          // ---- flush the slice's non-zero bins and clear them
+          const int nsl = (r_hi - r_lo) * nc * nt;
+          for (int s = tid; s < nsl; s += kBlock3) {
+            const uint32_t vc = sm.hc[s];
+            if (vc == 0u) continue;
+            const double vn = sm.hn[s], vw = sm.hw[s];
+            sm.hn[s] = 0.0;
+            sm.hw[s] = 0.0;
+            sm.hc[s] = 0u;
+            const int kt2 = s % nt, q2 = s / nt, kc = q2 % nc, kr2 = r_lo + q2 / nc;
+            const int64_t A = ((((int64_t)kr1 * nr + kr2) * nc + kc) * nt + kt1) * nt + kt2;
+            atomicAdd(&a.num[obase + A], vn);
+            atomicAdd(&a.wsum[obase + A], vw);
+            atomicAdd(&a.ntrip[obase + A], (unsigned long long)vc);
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+}
+
 // out = sum over the copies (copy c at c * stride).
 __global__ void xi3_reduce_kernel(const double* num_c, const double* wsum_c, const unsigned long long* cnt_c,
                                   int n_copies, int64_t stride, int64_t n, double* num, double* wsum,
@@ -471,19 +688,22 @@ hipError_t launch_xi3_reduce(const double* num_c, const double* wsum_c, const un
   return hipGetLastError();
 }
 
-hipError_t launch_xi3(const Xi3Args& a, bool combine, int blocks, hipStream_t st) {
+hipError_t launch_xi3(const Xi3Args& a, int kernel, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  if (combine)
+  if (kernel == 0)
     hipLaunchKernelGGL(xi3c_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
-  else
+  else if (kernel == 1)
     hipLaunchKernelGGL(xi3_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
+  else
+    hipLaunchKernelGGL(xi3w_kernel, dim3(blocks), dim3(kBlock3), 0, st, a);
   return hipGetLastError();
 }
 
-int xi3_blocks_per_cu(bool combine) {
+int xi3_blocks_per_cu(int kernel) {
   int n = 0;
-  const hipError_t e = combine ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3c_kernel, kBlock3, 0)
-                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3_kernel, kBlock3, 0);
+  const hipError_t e = kernel == 0   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3c_kernel, kBlock3, 0)
+                       : kernel == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3_kernel, kBlock3, 0)
+                                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, xi3w_kernel, kBlock3, 0);
   if (e != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }

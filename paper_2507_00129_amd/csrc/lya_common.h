@@ -74,7 +74,7 @@ struct GridDev {
 // Validation error bits (Globals::flag).
 enum : int32_t {
   kBadOffsets = 1, kBadFinite = 2, kBadWeight = 4, kBadDist = 8, kBadReal = 16, kBadNpix = 32,
-  kBadSub = 64, kBadCap3 = 128, kBadCapC = 256, kBadDet = 512
+  kBadSub = 64, kBadCap3 = 128, kBadCapC = 256, kBadDet = 512, kBadCapW = 1024
 };
 
 // ---------------------------------------------------------------- geometry
@@ -336,17 +336,23 @@ struct Xi3Args {
   unsigned long long* ntrip;
   int32_t n_copies;
   int64_t copy_stride;
+  // wide kernel: per workgroup two partner lists of w_cap entries (5 doubles,
+  // 2 ints each) at blockIdx.x * 10 w_cap in w_dbl, blockIdx.x * 4 w_cap in w_int
+  double* w_dbl;
+  int32_t* w_int;
+  int32_t w_cap;
 };
 hipError_t launch_xi3_reduce(const double* num_c, const double* wsum_c, const unsigned long long* cnt_c,
                              int n_copies, int64_t stride, int64_t n, double* num, double* wsum, int64_t* ntrip,
                              hipStream_t st);
 hipError_t launch_xi3_points(const lya_forests* F, const ForestInfo* finfo, const double* delta, Point3* pts,
                              hipStream_t st);
-// combine: the kernel that sums each vertex's entries in LDS before the global
-// atomics (grids with xi3_can_combine; it flags kBadCapC when a vertex has more
-// partners than it holds, and the direct kernel is run instead)
-hipError_t launch_xi3(const Xi3Args& a, bool combine, int blocks, hipStream_t st);
-int xi3_blocks_per_cu(bool combine);
+// kernel 0: sums each vertex's entries in LDS before the global atomics (grids
+// with xi3_can_combine; flags kBadCapC when a vertex has more partners than it
+// holds); 1: global atomics per entry; 2: as 0 with the partner list in global
+// scratch (flags kBadCapW beyond w_cap)
+hipError_t launch_xi3(const Xi3Args& a, int kernel, int blocks, hipStream_t st);
+int xi3_blocks_per_cu(int kernel);
 bool xi3_can_combine(int n_r, int n_t, int n_c);
 int xi3_combine_capacity();
 int xi3_max_cos_bins();

@@ -659,6 +659,9 @@ lya_status lya_xi_covariance(lya_context* ctx, const double* num, const double* 
   return LYA_OK;
 }
 
+// partner pixels per vertex pixel held by the wide 3PCF kernel's scratch lists
+constexpr int kXi3WideCap = 32768;
+
 lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, const lya_options* o,
                    void* stream, double* num, double* wsum, int64_t* ntrip, double* xi) {
   if (!ctx) return LYA_E_INVALID;
@@ -770,34 +773,42 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
     a.n_copies = n_copies;
     a.copy_stride = nout;
     // variant 0: the combining kernel (LDS sums per vertex and side-1 cell),
-    // 1: the direct kernel; by default the combining one where the grid fits
-    // its LDS slice, with the direct one run instead when a pixel has more
-    // partners than the combining kernel holds
+    // 1: the direct kernel, 2: the wide combining kernel (partner lists in
+    // global scratch); by default 0 where the grid fits the LDS slice (else
+    // 1), and 2 instead of 0 when a pixel has more partners than 0 holds
     const bool fits = xi3_can_combine(nr, nt, nc);
-    if (o->variant > 1) return fail(ctx, LYA_E_INVALID, "variant %d out of range (xi3 has 2)", o->variant);
-    if (o->variant == 0 && !fits)
-      return fail(ctx, LYA_E_UNSUPPORTED, "grid too large for the combining kernel (variant 0)");
-    bool combine = o->variant == 0 || (o->variant < 0 && fits);
+    if (o->variant > 2) return fail(ctx, LYA_E_INVALID, "variant %d out of range (xi3 has 3)", o->variant);
+    if ((o->variant == 0 || o->variant == 2) && !fits)
+      return fail(ctx, LYA_E_UNSUPPORTED, "grid too large for the combining kernels (variant %d)", o->variant);
+    int kernel = o->variant >= 0 ? o->variant : (fits ? 0 : 1);
     tm.at(3);
     for (;;) {
-      const int blocks = xi3_blocks_per_cu(combine) * ctx->n_cu;
+      const int blocks = xi3_blocks_per_cu(kernel) * ctx->n_cu;
       ctx->stats.grid_blocks = blocks;
-      ctx->stats.variant = combine ? 0 : 1;
+      ctx->stats.variant = kernel;
+      if (kernel == 2) {
+        a.w_cap = kXi3WideCap;
+        LYA_TRY(wst(ctx, "xi3_wide_dbl", (size_t)blocks * 10 * kXi3WideCap, &a.w_dbl));
+        LYA_TRY(wst(ctx, "xi3_wide_int", (size_t)blocks * 4 * kXi3WideCap, &a.w_int));
+      }
       HIP_TRY(launch_zero(counter, 4, st));
-      HIP_TRY(launch_xi3(a, combine, blocks, st));
+      HIP_TRY(launch_xi3(a, kernel, blocks, st));
       HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       const int32_t flag = *(int32_t*)ctx->pinned;
       if (flag & kBadCap3)
         return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel",
                     xi3_partner_capacity());
+      if (flag & kBadCapW)
+        return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel",
+                    kXi3WideCap);
       if (!(flag & kBadCapC)) break;
       if (o->variant == 0)
         return fail(ctx, LYA_E_UNSUPPORTED, "more than %d partner pixels within r_max of one pixel (variant 0)",
                     xi3_combine_capacity());
       // a pixel has more partners than the combining kernel holds: clear the
-      // flag and the sums and run the direct kernel
-      combine = false;
+      // flag and the sums and run the wide kernel
+      kernel = 2;
       HIP_TRY(launch_zero(&P.glob->flag, sizeof(int32_t), st));
       HIP_TRY(launch_zero(cn, (size_t)(n_copies * nout) * sizeof(double), st));
       HIP_TRY(launch_zero(cw, (size_t)(n_copies * nout) * sizeof(double), st));

@@ -1,7 +1,8 @@
 """GPU parity of lya_xi3 (the anisotropic three-point function of Sec. 2.3,
-eq. estimator_three) against the FP64 oracle, for both kernels (variant 0
+eq. estimator_three) against the FP64 oracle, for the three kernels (variant 0
 sums each vertex's entries in LDS before the global atomics, variant 1 adds
-every entry to the global sums).  Entry counts must match exactly; N and W to
+every entry to the global sums, variant 2 is variant 0 with the partner
+lists in global scratch for vertex pixels with many partners).  Entry counts must match exactly; N and W to
 1e-12 of the bin's absolute sum (FP64 throughout, only the summation order
 differs)."""
 import numpy as np
@@ -68,7 +69,7 @@ def test_xi3_golden_handworked(lib):
     assert np.allclose(out["wsum"][0][exp["bins"]], exp["wsum"], rtol=1e-15)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_xi3_tiny_vs_oracle(lib, seed, variant):
     F = tiny(seed, n_forests=6, k=8, width_deg=0.3)
@@ -76,7 +77,7 @@ def test_xi3_tiny_vs_oracle(lib, seed, variant):
     check3(run3(lib, F, G3, variant=variant, expect_variant=variant), O.xi3_sums(F, G3), f"tiny{seed} v{variant}")
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_xi3_partial_ranges_vs_oracle(lib, variant):
     """r from 5 Mpc/h, theta in [0.2, 2.0], cos alpha in [-0.5, 1]: sides and
     triangles outside the ranges drop out."""
@@ -85,7 +86,7 @@ def test_xi3_partial_ranges_vs_oracle(lib, variant):
     check3(run3(lib, F, G3, variant=variant), O.xi3_sums(F, G3), f"partial v{variant}")
 
 
-@pytest.mark.parametrize("variant", [-1, 1])
+@pytest.mark.parametrize("variant", [-1, 1, 2])
 def test_xi3_patch_with_realisations_vs_oracle(lib, variant):
     """Two realisations of 15 forests (30 pixels each, several 64-lane blocks of
     partners per vertex), 6 x 6 x 8 x 5 x 5 bins to 30 Mpc/h; the default
@@ -98,14 +99,15 @@ def test_xi3_patch_with_realisations_vs_oracle(lib, variant):
     check3(out, O.xi3_sums(F, G3), f"patch v{variant}")
 
 
-def test_xi3_slice_blocks_vs_oracle(lib):
-    """n_cos n_theta = 400: the combining kernel's LDS slice holds 5 of the 7
+@pytest.mark.parametrize("variant", [0, 2])
+def test_xi3_slice_blocks_vs_oracle(lib, variant):
+    """n_cos n_theta = 400: the combining kernels' LDS slice holds 5 of the 7
     side-2 r bins, so each side-1 cell takes two passes (as on the paper's
     3PCF grid, 20 r x 10 theta x 20 cos alpha bins, which takes two)."""
     parts = [truncate(make_patch(12, 0.6, 70 + r, z_range=(2.1, 2.3)), 24) for r in range(2)]
     F = concat_realisations(parts)
     G3 = grid3(r_max=35.0, n_r=7, n_t=20, n_c=20)
-    check3(run3(lib, F, G3, expect_variant=0), O.xi3_sums(F, G3), "slice blocks")
+    check3(run3(lib, F, G3, variant=variant, expect_variant=variant), O.xi3_sums(F, G3), f"slice blocks v{variant}")
 
 
 def _lopsided(seed=5, n_long=2060, n_short=10):
@@ -125,16 +127,72 @@ def _lopsided(seed=5, n_long=2060, n_short=10):
 
 
 def test_xi3_combining_overflow_falls_back(lib):
-    """Pixels with 2070 partners: more than the combining kernel holds (2048),
-    fewer than the direct one (3072): the call re-runs with the direct kernel
-    and matches the oracle; variant 0 forced reports the overflow."""
+    """Pixels with 2070 partners: more than the combining kernel holds (2048):
+    the call re-runs with the wide kernel and matches the oracle, as does the
+    direct kernel (3072); variant 0 forced reports the overflow."""
     from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
     F = _lopsided()
     G3 = grid3(r_max=1500.0, n_r=6, n_t=4, n_c=5)
-    check3(run3(lib, F, G3, expect_variant=1), O.xi3_sums(F, G3), "fallback")
+    ref = O.xi3_sums(F, G3)
+    check3(run3(lib, F, G3, expect_variant=2), ref, "fallback")
+    check3(run3(lib, F, G3, variant=1, expect_variant=1), ref, "fallback direct")
     with pytest.raises(LyaError) as ei:
         run3(lib, F, G3, variant=0)
     assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+def test_xi3_wide_beyond_direct_capacity_vs_oracle(lib):
+    """Pixels with 4010 partners, beyond the direct kernel's 3072: the default
+    runs the wide kernel and matches the oracle; the direct kernel reports
+    LYA_E_UNSUPPORTED."""
+    from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
+    F = _lopsided(seed=6, n_long=4000)
+    G3 = grid3(r_max=3000.0, n_r=6, n_t=4, n_c=5)
+    check3(run3(lib, F, G3, expect_variant=2), O.xi3_sums(F, G3), "wide 4010")
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, G3, variant=1)
+    assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+def test_xi3_wide_overflow_is_reported(lib):
+    """33010 partners for the short forests' pixels: beyond the wide kernel's
+    scratch lists (32768), reported as LYA_E_UNSUPPORTED."""
+    from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
+    F = _lopsided(seed=7, n_long=33000)
+    G3 = O.Grid3(np.array([0.0, 1e5]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
+    with pytest.raises(LyaError) as ei:
+        run3(lib, F, G3)
+    assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+def test_xi3_paper_grid_at_eboss_density(lib):
+    """The grid of the paper's 3PCF figure (r to 80 Mpc/h in 20 bins, theta
+    10 bins, cos alpha 20 bins) on 150 forests nearest the centre of the
+    eBOSS-like patch: vertex pixels have thousands of partners, so the default
+    runs the wide kernel; counts symmetric under (r1, theta1) <-> (r2, theta2),
+    N and W symmetric to rounding; on r to 40 Mpc/h the wide and the
+    combining kernels give the same counts and W."""
+    import time
+    F, _, _ = make_config(1, seed=3, scale=0.05)
+    S = subset_forests(F, nearest_to_centre(F, 150))
+    G3 = O.Grid3(np.linspace(0.0, 80.0, 21), np.linspace(0.0, np.pi, 11), np.linspace(-1.0, 1.0, 21))
+    t = time.perf_counter()
+    out = run3(lib, S, G3, expect_variant=2)
+    sh = (20, 20, 20, 10, 10)
+    c = out["ntrip"][0].reshape(sh)
+    print(f"[xi3 paper grid] entries={int(c.sum())} in {time.perf_counter() - t:.2f} s", flush=True)
+    assert c.sum() > 1e9
+    np.testing.assert_array_equal(c, c.transpose(1, 0, 2, 4, 3))
+    for k in ("num", "wsum"):
+        v = out[k][0].reshape(sh)
+        assert np.max(np.abs(v - v.transpose(1, 0, 2, 4, 3))) <= 1e-10 * np.abs(v).max()
+    # the same call on the direct-kernel-sized r range agrees with variant 0
+    G40 = O.Grid3(np.linspace(0.0, 40.0, 11), np.linspace(0.0, np.pi, 11), np.linspace(-1.0, 1.0, 21))
+    a0 = run3(lib, S, G40, variant=0, expect_variant=0)
+    a2 = run3(lib, S, G40, variant=2, expect_variant=2)
+    np.testing.assert_array_equal(a0["ntrip"], a2["ntrip"])
+    m = np.abs(a0["wsum"]) > 0
+    assert np.max(np.abs(a0["wsum"] - a2["wsum"])[m] / a0["wsum"][m]) <= 1e-12
 
 
 @pytest.mark.parametrize("variant", [0, 1])
@@ -177,13 +235,14 @@ def test_xi3_eboss_density_properties(lib, variant):
 
 
 def test_xi3_partner_overflow_is_reported(lib):
-    """More partner pixels within r_max of one pixel than the LDS list holds:
-    the call fails with LYA_E_UNSUPPORTED instead of dropping triangles."""
+    """More partner pixels within r_max of one pixel than the direct kernel's
+    LDS list holds: the call fails with LYA_E_UNSUPPORTED instead of dropping
+    triangles."""
     from paper_2507_00129_amd import LyaError, LYA_E_UNSUPPORTED
     F = truncate(make_patch(48, 0.3, 8, z_range=(2.1, 2.3)), 100)
     G3 = O.Grid3(np.array([0.0, 1e5]), np.array([0.0, np.pi]), np.array([-1.0, 1.0]))
     with pytest.raises(LyaError) as ei:
-        run3(lib, F, G3)
+        run3(lib, F, G3, variant=1)
     assert ei.value.status == LYA_E_UNSUPPORTED
 
 
@@ -207,7 +266,7 @@ def test_xi3_invalid_grids(lib):
         run3(lib, F, wide, variant=0)
     assert ei.value.status == LYA_E_UNSUPPORTED
     with pytest.raises(LyaError) as ei:
-        run3(lib, F, grid3(), variant=2)
+        run3(lib, F, grid3(), variant=3)
     assert ei.value.status == LYA_E_INVALID
 
 
