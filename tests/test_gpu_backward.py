@@ -271,3 +271,23 @@ def test_projected_autograd_function(lib):
     gd, gw, _ = gpu_grad_proj(lib, F, G, ex["target"], "fp64", "mean_slope")
     assert np.allclose(d.grad.cpu().numpy(), gd, rtol=1e-12, atol=1e-14 * np.abs(gd).max())
     assert np.allclose(w.grad.cpu().numpy(), gw, rtol=1e-12, atol=1e-14 * np.abs(gw).max())
+
+
+@pytest.mark.parametrize("project", [False, True])
+def test_gradcheck_tiny_fp64(lib, project):
+    """torch.autograd.gradcheck of the differentiable xi (FP64 forward and
+    backward kernels) with respect to delta and w on four 6-pixel forests:
+    the backward kernel's Jacobian-vector products against central
+    differences of the forward kernel, with and without the projection."""
+    from helpers import tiny
+    from paper_2507_00129_amd import DeviceForests, differentiable_xi
+    F = tiny(4, n_forests=4, k=6, width_deg=0.3)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    d = dF.delta.clone().requires_grad_(True)
+    w = dF.weight.clone().requires_grad_(True)
+
+    def f(d, w):
+        return differentiable_xi(d, w, lib, dF, G60, "fp64", project_deltas=project)
+    assert f(d, w).abs().sum().item() > 0
+    # FP64 atomics make repeated backward calls differ in the last bits
+    assert torch.autograd.gradcheck(f, (d, w), eps=1e-6, atol=1e-7, rtol=1e-5, nondet_tol=1e-12)
