@@ -256,16 +256,18 @@ typedef struct {
      wsum[A]  = sum_A w_i w_j w_k
      ntrip[A] = number of entries in A (any weight)
      xi[A]    = num[A] / wsum[A], 0 where wsum[A] == 0   (may be NULL)
-   Two kernels: variant 0 sums each vertex pixel's entries in LDS per (r,
+   Three kernels: variant 0 sums each vertex pixel's entries in LDS per (r,
    theta) cell of the first side before adding them to the global sums
    (grids with n_r n_theta <= 1024 and n_cos n_theta <= 2048, up to 2048
-   partner pixels per vertex); variant 1 adds every entry to the global sums.
-   options.variant = -1 takes variant 0 where the grid allows and re-runs the
-   call with variant 1 when a pixel has more partners than variant 0 holds;
-   variant 0 forced on a larger grid, or on a pixel with more than 2048
-   partners, returns LYA_E_UNSUPPORTED.
-   Returns LYA_E_UNSUPPORTED if a pixel has more than 3072 partner pixels with
-   a side in the r grid (the outputs are then incomplete). */
+   partner pixels per vertex); variant 2 does the same with the partner list
+   in a device scratch (up to 32768 partners); variant 1 adds every entry to
+   the global sums (up to 3072 partners, any grid).  options.variant = -1
+   takes variant 0 where the grid allows, else 1, and re-runs the call with
+   variant 2 when a pixel has more partners than variant 0 holds; variants 0
+   and 2 forced on a larger grid, and variant 0 forced on a pixel with more
+   than 2048 partners, return LYA_E_UNSUPPORTED.  Returns LYA_E_UNSUPPORTED
+   if a pixel has more partner pixels with a side in the r grid than the
+   kernel that runs holds (the outputs are then incomplete). */
 lya_status lya_xi3(lya_context *ctx, const lya_forests *forests, const lya_grid3 *grid,
                    const lya_options *opts, void *stream,
                    double *num, double *wsum, int64_t *ntrip, double *xi);
