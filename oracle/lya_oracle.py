@@ -950,15 +950,21 @@ def _near(x, e, tau):
     return np.any(np.abs(np.asarray(x)[..., None] - e) <= np.asarray(tau)[..., None], axis=-1)
 
 
-def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
+def xi3_sums(F, g3: Grid3, edge_tau=1e-12, sub=None, n_sub=1) -> Xi3Sums:
     """Triplet sums of eq. estimator_three, vertex by vertex.
 
     For a vertex pixel i the partners are the pixels of every other forest of
     its realisation with side length in [r_edges[0], r_edges[-1]) (and > 0);
     each ordered pair of partners from two different forests is one entry.
     The per-vertex histograms are combined with Neumaier summation.
+
+    With `sub` (a subsample id in [0, n_sub) per forest) the sums are split
+    by subsample for the dispersion of the 3PCF figure (subsamples of the
+    forests in sky pixels): every entry goes to slab r * n_sub + sub[f] of
+    its main vertex's forest f; the first axis is then R * n_sub.
     """
-    R = max(1, int(F.n_realisations))
+    n_sub = int(n_sub) if sub is not None else 1
+    R = max(1, int(F.n_realisations)) * n_sub
     nb = g3.n_bins
     rmax = float(g3.r_edges[-1])
     n_vec = unit_vectors(F.ra, F.dec)
@@ -983,7 +989,7 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
             continue
         g_list = np.array(sorted(nbrs[f]), np.int64)
         idx = np.concatenate([np.arange(F.offsets[g], F.offsets[g + 1]) for g in g_list])
-        r = int(real[f])
+        r = int(real[f]) * n_sub + (int(sub[f]) if sub is not None else 0)
         los = n_vec[f]
         for i in range(F.offsets[f], F.offsets[f + 1]):
             d = pos[idx] - pos[i]
@@ -1023,12 +1029,14 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12) -> Xi3Sums:
     return Xi3Sums(num.value(), wsum.value(), cnt, n_near, absn.value())
 
 
-def xi3_brute(F, g3: Grid3):
+def xi3_brute(F, g3: Grid3, sub=None, n_sub=1):
     """Pure-Python loop over ordered pixel triplets (i; j, k) of three distinct
     forests (tiny inputs), with every angle from math.acos and every bin found
-    by scanning the edge list."""
+    by scanning the edge list; with `sub`, triplet (i; j, k) goes to slab
+    r * n_sub + sub[forest of i]."""
     import math
-    R = max(1, int(F.n_realisations))
+    n_sub = int(n_sub) if sub is not None else 1
+    R = max(1, int(F.n_realisations)) * n_sub
     nb = g3.n_bins
     real = F.real_of()
     fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
@@ -1069,7 +1077,7 @@ def xi3_brute(F, g3: Grid3):
                 if kc < 0:
                     continue
                 A = (((kr1 * g3.n_r + kr2) * g3.n_c + kc) * g3.n_t + kt1) * g3.n_t + kt2
-                r = int(real[fid[i]])
+                r = int(real[fid[i]]) * n_sub + (int(sub[fid[i]]) if sub is not None else 0)
                 num[r][A].append(float(F.weight[i] * F.delta[i] * F.weight[j] * F.delta[j] * F.weight[k] * F.delta[k]))
                 ws[r][A].append(float(F.weight[i] * F.weight[j] * F.weight[k]))
                 cnt[r, A] += 1

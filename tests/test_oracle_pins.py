@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synth import Grid, make_patch, subset_forests, uniform_grid
+from synth import Grid, concat_realisations, make_patch, subset_forests, uniform_grid
 from synth.survey import Forests
 
 from helpers import forests_from_dict, grid_from_dict, load_json, tiny, truncate
@@ -633,6 +633,31 @@ def test_xi3_vs_python_brute(seed, partial):
     assert (X.ntrip == C_).all()
     assert np.allclose(X.num, N_, rtol=1e-13, atol=1e-13 * np.abs(N_).max())
     assert np.allclose(X.wsum, W_, rtol=1e-13, atol=1e-13 * np.abs(W_).max())
+
+
+def test_xi3_subsample_split_vs_python_brute():
+    """Sums split by the subsample of the main vertex's forest against the
+    pure-Python loop with the same split, over two realisations; the slabs
+    add up to the unsplit sums, and a vertex forest's triplets land only in
+    its own subsample (pins the slab index r * n_sub + sub[f])."""
+    parts = [tiny(10 + r, n_forests=5, k=4, width_deg=0.3) for r in range(2)]
+    F = concat_realisations(parts)
+    G3 = _grid3()
+    sub = np.array([0, 2, 1, 2, 0, 1, 1, 0, 2, 2], np.int32)[:F.n_forests]
+    X = O.xi3_sums(F, G3, sub=sub, n_sub=3)
+    N_, W_, C_ = O.xi3_brute(F, G3, sub=sub, n_sub=3)
+    assert X.ntrip.shape == (2 * 3, G3.n_bins) and C_.sum() > 100
+    assert (X.ntrip == C_).all()
+    assert np.allclose(X.num, N_, rtol=1e-13, atol=1e-13 * np.abs(N_).max())
+    assert np.allclose(X.wsum, W_, rtol=1e-13, atol=1e-13 * np.abs(W_).max())
+    U = O.xi3_sums(F, G3)
+    assert (X.ntrip.reshape(2, 3, -1).sum(axis=1) == U.ntrip).all()
+    assert np.allclose(X.wsum.reshape(2, 3, -1).sum(axis=1), U.wsum, rtol=1e-13, atol=0)
+    # only the vertex forests of subsample 1 contribute to its slabs
+    keep = [f for f in range(F.n_forests) if sub[f] == 1]
+    assert X.ntrip.reshape(2, 3, -1)[:, 1].sum() == sum(
+        int(O.xi3_brute(F, G3, sub=(np.arange(F.n_forests) == f).astype(np.int32), n_sub=2)[2][1::2].sum())
+        for f in keep)
 
 
 def test_xi3_single_bin_closed_form():
