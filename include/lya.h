@@ -272,6 +272,20 @@ lya_status lya_xi3(lya_context *ctx, const lya_forests *forests, const lya_grid3
                    const lya_options *opts, void *stream,
                    double *num, double *wsum, int64_t *ntrip, double *xi);
 
+/* lya_xi3's sums split by subsample, for the dispersion of the 3PCF (the
+   paper's 3PCF figure takes it from subsamples of the forests in sky
+   pixels).  subsample[f] in [0, n_sub) (device, [n_forests]); every entry is
+   credited to the subsample of its main vertex's forest (the vertex the
+   triangle is binned from).  Outputs as lya_xi3, each
+   [n_realisations * n_sub * n_bins] row-major (realisation, subsample, bin);
+   summing over subsamples gives lya_xi3's sums.  An id outside [0, n_sub)
+   returns LYA_E_INVALID before anything is written beyond the zeroed
+   outputs. */
+lya_status lya_xi3_subsamples(lya_context *ctx, const lya_forests *forests, const lya_grid3 *grid,
+                              const lya_options *opts, void *stream,
+                              const int32_t *subsample, int32_t n_sub,
+                              double *num, double *wsum, int64_t *ntrip, double *xi);
+
 /* Distortion matrix (Sec. 2.2, eq. distortion) over the forest pairs kept by
    options.dmat_keep_fraction / seed, with eta of options.eta.  Outputs,
    device:

@@ -221,12 +221,14 @@ __device__ __forceinline__ int cos_bin(const CosAxis& cx, const Partners<CAP>& P
   return cos_axis_bin(cx, ca);
 }
 
-// The copy of the sums this workgroup adds to: with one copy per XCD, the copy
-// of its XCD (the copies spread the device-wide atomics over more addresses);
-// a second kernel adds them up.
-__device__ __forceinline__ int64_t sums_base(const Xi3Args& a, const ForestInfo& fi) {
+// The sums this workgroup adds to for vertex forest f (input index): the slab
+// of f's realisation (and subsample), in the copy of the workgroup's XCD when
+// there is one copy per XCD (the copies spread the device-wide atomics over
+// more addresses; a second kernel adds them up).
+__device__ __forceinline__ int64_t sums_base(const Xi3Args& a, const ForestInfo& fi, int f) {
   const int copy = a.n_copies > 1 ? (int)(xcd_id() % (unsigned)a.n_copies) : 0;
-  return (int64_t)copy * a.copy_stride + (int64_t)fi.real * a.n_bins;
+  const int64_t slab = a.sub ? (int64_t)fi.real * a.n_sub + a.sub[f] : (int64_t)fi.real;
+  return (int64_t)copy * a.copy_stride + slab * a.n_bins;
 }
 
 // Direct kernel: every entry goes to the global sums with three atomics.
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBlock3) void xi3_kernel(Xi3Args a) {
     const Item item = a.items[it];
     const int f = a.sorted[item.p];
     const ForestInfo fi = a.finfo[f];
-    const int64_t obase = sums_base(a, fi);
+    const int64_t obase = sums_base(a, fi, f);
 
     for (int i = 0; i < fi.npix; ++i) {
       const int64_t pi = fi.pix0 + i;
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
     const Item item = a.items[it];
     const int f = a.sorted[item.p];
     const ForestInfo fi = a.finfo[f];
-    const int64_t obase = sums_base(a, fi);
+    const int64_t obase = sums_base(a, fi, f);
 
     for (int i = 0; i < fi.npix; ++i) {
       const int64_t pi = fi.pix0 + i;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(kBlock3) void xi3w_kernel(Xi3Args a) {
     const Item item = a.items[it];
     const int f = a.sorted[item.p];
     const ForestInfo fi = a.finfo[f];
-    const int64_t obase = sums_base(a, fi);
+    const int64_t obase = sums_base(a, fi, f);
 
     for (int i = 0; i < fi.npix; ++i) {
       const int64_t pi = fi.pix0 + i;

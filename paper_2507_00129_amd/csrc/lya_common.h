@@ -336,6 +336,10 @@ struct Xi3Args {
   unsigned long long* ntrip;
   int32_t n_copies;
   int64_t copy_stride;
+  // optional subsample of each forest (input index): entries go to slab
+  // realisation * n_sub + sub[f] of their main vertex's forest f
+  const int32_t* sub;
+  int32_t n_sub;
   // wide kernel: per workgroup two partner lists of w_cap entries (5 doubles,
   // 2 ints each) at blockIdx.x * 10 w_cap in w_dbl, blockIdx.x * 4 w_cap in w_int
   double* w_dbl;

@@ -662,8 +662,13 @@ lya_status lya_xi_covariance(lya_context* ctx, const double* num, const double* 
 // partner pixels per vertex pixel held by the wide 3PCF kernel's scratch lists
 constexpr int kXi3WideCap = 32768;
 
-lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, const lya_options* o,
-                   void* stream, double* num, double* wsum, int64_t* ntrip, double* xi) {
+namespace {
+
+// 3PCF sums, optionally split by the subsample of each entry's main vertex
+// forest (sub != nullptr: outputs [R][n_sub][n_bins]).
+lya_status xi3_impl(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, const lya_options* o,
+                    void* stream, const int32_t* sub, int32_t n_sub, double* num, double* wsum, int64_t* ntrip,
+                    double* xi) {
   if (!ctx) return LYA_E_INVALID;
   if (!G3) return fail(ctx, LYA_E_INVALID, "NULL grid");
   double r_e0, r_inv, r_max;
@@ -696,13 +701,14 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
   LYA_TRY(check_common(ctx, F, &G, o, gd));
   if (o->deterministic) return fail(ctx, LYA_E_UNSUPPORTED, "options.deterministic is honoured by lya_xi only");
   if (!num || !wsum || !ntrip) return fail(ctx, LYA_E_INVALID, "NULL output num, wsum or ntrip");
-  if ((int64_t)F->n_realisations * n_bins > ((int64_t)1 << 40))
-    return fail(ctx, LYA_E_UNSUPPORTED, "outputs too large");
+  if (sub && n_sub < 1) return fail(ctx, LYA_E_INVALID, "n_sub must be >= 1");
+  const int64_t nslab = (int64_t)F->n_realisations * (sub ? n_sub : 1);
+  if (nslab * n_bins > ((int64_t)1 << 40)) return fail(ctx, LYA_E_UNSUPPORTED, "outputs too large");
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ctx->err.clear();
   ctx->stats = lya_stats{};
-  const int64_t nout = (int64_t)F->n_realisations * n_bins;
+  const int64_t nout = nslab * n_bins;
   Timer tm{ctx, st, o->timing != 0};
   tm.at(0);
   HIP_TRY(launch_zero(num, nout * sizeof(double), st));
@@ -712,6 +718,12 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
     Prepared P;
     const bool project = o->project_deltas != 0;
     LYA_TRY(prepare(ctx, F, &G, gd, o, st, false, false, project, P));
+    if (sub) {
+      HIP_TRY(launch_validate_sub(sub, F->n_forests, n_sub, P.glob, st));
+      HIP_TRY(hipMemcpyAsync(ctx->pinned, &P.glob->flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (*(int32_t*)ctx->pinned & kBadSub) return fail(ctx, LYA_E_INVALID, "subsample id outside [0, n_sub)");
+    }
     Point3* pts;
     LYA_TRY(wst(ctx, "xi3_pts", (size_t)F->n_pix, &pts));
     HIP_TRY(launch_xi3_points(F, P.finfo, project ? P.delta_proj : F->delta, pts, st));
@@ -772,6 +784,8 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
     a.ntrip = cc;
     a.n_copies = n_copies;
     a.copy_stride = nout;
+    a.sub = sub;
+    a.n_sub = sub ? n_sub : 1;
     // variant 0: the combining kernel (LDS sums per vertex and side-1 cell),
     // 1: the direct kernel, 2: the wide combining kernel (partner lists in
     // global scratch); by default 0 where the grid fits the LDS slice (else
@@ -825,6 +839,21 @@ lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, 
   HIP_TRY(launch_finalize_xi(num, wsum, xi, nout, st));
   tm.at(5);
   return tm.finish(ctx);
+}
+
+}  // namespace
+
+lya_status lya_xi3(lya_context* ctx, const lya_forests* F, const lya_grid3* G3, const lya_options* o,
+                   void* stream, double* num, double* wsum, int64_t* ntrip, double* xi) {
+  return xi3_impl(ctx, F, G3, o, stream, nullptr, 1, num, wsum, ntrip, xi);
+}
+
+lya_status lya_xi3_subsamples(lya_context* ctx, const lya_forests* F, const lya_grid3* G3,
+                              const lya_options* o, void* stream, const int32_t* subsample, int32_t n_sub,
+                              double* num, double* wsum, int64_t* ntrip, double* xi) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!subsample) return fail(ctx, LYA_E_INVALID, "NULL subsample");
+  return xi3_impl(ctx, F, G3, o, stream, subsample, n_sub, num, wsum, ntrip, xi);
 }
 
 lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,

@@ -105,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.lya_xi_subsamples.restype = I32
     lib.lya_xi3.argtypes = [P, FP, ctypes.POINTER(lya_grid3), OP, P, P, P, P, P]
     lib.lya_xi3.restype = I32
+    lib.lya_xi3_subsamples.argtypes = [P, FP, ctypes.POINTER(lya_grid3), OP, P, P, I32, P, P, P, P]
+    lib.lya_xi3_subsamples.restype = I32
     lib.lya_xi_means.argtypes = [P, FP, GP, OP, P, P, P, P, P, P, P, P]
     lib.lya_xi_means.restype = I32
     lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
@@ -282,6 +284,27 @@ class Library:
         self._check(self.lib.lya_xi3(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
                                      self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
                                      _ptr(out["ntrip"]), _ptr(out.get("xi"))))
+        return out
+
+    def xi3_subsamples(self, forests: DeviceForests, grid3, subsample, n_sub, stream=None, out=None, **opts):
+        """Triplet sums of the 3PCF split by the subsample of each entry's main
+        vertex forest; returns dict of [R, n_sub, n_bins] tensors.  `subsample`
+        is an int32 device tensor [n_forests] with ids in [0, n_sub)."""
+        import torch
+        g = HostGrid3(grid3)
+        R = int(forests.n_realisations)
+        dev = forests.dist.device
+        sub = subsample.to(device=dev, dtype=torch.int32).contiguous()
+        if sub.numel() != forests.n_forests:
+            raise ValueError("subsample must have one entry per forest")
+        shape = (R, int(n_sub), g.n_bins)
+        if out is None:
+            out = {k: torch.empty(shape, dtype=torch.int64 if k == "ntrip" else torch.float64, device=dev)
+                   for k in ("num", "wsum", "ntrip", "xi")}
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi3_subsamples(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                                self._stream(stream), _ptr(sub), int(n_sub), _ptr(out["num"]),
+                                                _ptr(out["wsum"]), _ptr(out["ntrip"]), _ptr(out.get("xi"))))
         return out
 
     def xi_means(self, forests: DeviceForests, grid, stream=None, out=None, **opts):

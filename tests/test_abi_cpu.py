@@ -53,6 +53,7 @@ def test_defaults_and_null_arguments():
     assert lib.lya_xi_covariance(None, None, None, 1, 1, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_means(None, None, None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi3(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_xi3_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
     assert o.counters == 0 and o.deterministic == 0
     assert lib.lya_create(None, 0) == L.LYA_E_INVALID
     assert lib.lya_last_error(None) == b"NULL context"

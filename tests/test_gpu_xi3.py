@@ -296,3 +296,40 @@ def test_xi3_projected_deltas_vs_oracle(lib):
     e_w = O.err_rel(out["wsum"], ref.wsum)
     print(f"[xi3 projected] entries={int(ref.ntrip.sum())} e_N={e_n:.2e} e_W={e_w:.2e}", flush=True)
     assert e_n <= TOL and e_w <= TOL
+
+
+def run3_sub(lib, F, G3, sub, n_sub, expect_variant=None, **kw):
+    from paper_2507_00129_amd import DeviceForests
+    out = lib.xi3_subsamples(DeviceForests.from_host(F, "cuda:0"), G3,
+                             torch.as_tensor(sub, dtype=torch.int32, device="cuda:0"), n_sub, **kw)
+    torch.cuda.synchronize()
+    if expect_variant is not None:
+        assert lib.last_stats()["variant"] == expect_variant
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_xi3_subsamples_vs_oracle(lib, variant):
+    """Sums split by the subsample of each entry's main vertex forest (the
+    dispersion of the paper's 3PCF figure), two realisations of 15 forests,
+    4 subsamples: every slab against the oracle's split sums, and the slabs
+    add up to lya_xi3's counts."""
+    parts = [truncate(make_patch(15, 0.6, 80 + r, z_range=(2.1, 2.3)), 30) for r in range(2)]
+    F = concat_realisations(parts)
+    G3 = grid3(r_max=30.0, n_r=6, n_t=5, n_c=8)
+    sub = np.random.default_rng(4).integers(0, 4, F.n_forests).astype(np.int32)
+    out = run3_sub(lib, F, G3, sub, 4, variant=variant, expect_variant=variant)
+    assert out["ntrip"].shape == (2, 4, G3.n_bins)
+    ref = O.xi3_sums(F, G3, sub=sub, n_sub=4)
+    flat = {k: v.reshape(8, G3.n_bins) for k, v in out.items()}
+    check3(flat, ref, f"subsamples v{variant}")
+    whole = run3(lib, F, G3, variant=variant)
+    np.testing.assert_array_equal(out["ntrip"].sum(axis=1), whole["ntrip"])
+
+
+def test_xi3_subsamples_invalid_id(lib):
+    from paper_2507_00129_amd import LyaError, LYA_E_INVALID
+    F = tiny(0, n_forests=4, k=4, width_deg=0.3)
+    with pytest.raises(LyaError) as ei:
+        run3_sub(lib, F, grid3(), np.array([0, 1, 2, 3], np.int32), 3)
+    assert ei.value.status == LYA_E_INVALID
