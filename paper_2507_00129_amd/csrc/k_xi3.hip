@@ -180,12 +180,19 @@ struct CosAxis {
   int n;
 };
 
-// Bin of x on the cos alpha axis, the last bin closed (-1 outside).
+// Bin of x on the cos alpha axis, the last bin closed (-1 outside).  The host
+// accepts only edges within 1e-9 bins of lo + k d, and t = (x - lo) / d is
+// computed to ~1e-13 bins, so a fractional part of t farther than 1e-8 from
+// 0 and 1 puts x strictly inside bin floor(t); only closer values are settled
+// by comparison with the edges.
 __device__ __forceinline__ int cos_axis_bin(const CosAxis& c, double x) {
   if (x < c.lo) return -1;
   if (x >= c.hi) return x == c.hi ? c.n - 1 : -1;
-  int k = (int)__dmul_rn(__dsub_rn(x, c.lo), c.inv);
+  const double t = __dmul_rn(__dsub_rn(x, c.lo), c.inv);
+  int k = (int)t;
   k = k < 0 ? 0 : (k > c.n - 1 ? c.n - 1 : k);
+  const double fr = __dsub_rn(t, (double)k);
+  if (fr > 1e-8 && fr < 1.0 - 1e-8) return k;
   while (k > 0 && x < c.e[k]) --k;
   while (k < c.n - 1 && x >= c.e[k + 1]) ++k;
   return k;
