@@ -59,6 +59,7 @@ struct Xi3SmemC {
   int32_t cfill[kCellC];
   double ce[kCosC + 1];             // cos alpha edges
   int32_t m;
+  int32_t stop;                     // another workgroup overflowed: leave the item
   int64_t item;
 };
 
@@ -344,9 +345,13 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
       const int64_t pi = fi.pix0 + i;
       const double wdi = a.pts[pi].wd, wi = a.pts[pi].w;
       __syncthreads();  // the previous vertex's partners have been read
-      if (tid == 0) sm.m = 0;
+      if (tid == 0) {
+        sm.m = 0;
+        sm.stop = __hip_atomic_load(&a.glob->flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kBadCapC;
+      }
       for (int c = tid; c < ncell; c += kBlock3) sm.cfill[c] = 0;
       __syncthreads();
+      if (sm.stop) break;  // the host re-runs the call with the wide kernel
       gather_partners(a, item, fi, a.pts[pi].x, a.pts[pi].y, a.pts[pi].z, kCapC, &sm.m, LdsStore<kCapC>{sm.p});
       __syncthreads();
       const int m = sm.m;
