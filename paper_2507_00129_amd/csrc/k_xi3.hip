@@ -428,6 +428,9 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
               sk = ((kq & 0xffff) - r_lo) * nc * nt + (kq >> 16);
             }
             const int jb = pp * nj / P, je = (pp + 1) * nj / P;
+            int rs = -1;
+            unsigned rc = 0u;
+            double rn = 0.0, rw = 0.0;
             for (int jj = jb; jj < je; ++jj) {
               const int j = sm.perm[j0 + jj];
               if (kon && sm.p.fid[j] != kfid) {
@@ -439,11 +442,27 @@ __global__ __launch_bounds__(kBlock3) void xi3c_kernel(Xi3Args a) {
                   const int s = sk + kc * nt;
                   const double pn = __dmul_rn(__dmul_rn(wdi, sm.p.wd[j]), kwd);
                   const double pw = __dmul_rn(__dmul_rn(wi, sm.p.w[j]), kw);
-                  atomicAdd(&sm.hc[s], 1u);
-                  atomicAdd(&sm.hn[s], pn);
-                  atomicAdd(&sm.hw[s], pw);
+                  if (s != rs) {
+                    if (rs >= 0) {
+                      atomicAdd(&sm.hc[rs], rc);
+                      atomicAdd(&sm.hn[rs], rn);
+                      atomicAdd(&sm.hw[rs], rw);
+                    }
+                    rs = s;
+                    rc = 0u;
+                    rn = 0.0;
+                    rw = 0.0;
+                  }
+                  ++rc;
+                  rn = __dadd_rn(rn, pn);
+                  rw = __dadd_rn(rw, pw);
                 }
               }
+            }
+            if (rs >= 0) {
+              atomicAdd(&sm.hc[rs], rc);
+              atomicAdd(&sm.hn[rs], rn);
+              atomicAdd(&sm.hw[rs], rw);
             }
           }
           __syncthreads();
@@ -601,6 +620,9 @@ __global__ __launch_bounds__(kBlock3) void xi3w_kernel(Xi3Args a) {
                 sk = ((kq & 0xffff) - r_lo) * nc * nt + (kq >> 16);
               }
               const int jb = pp * njc / P, je = (pp + 1) * njc / P;
+              int rs = -1;
+              unsigned rc = 0u;
+              double rn = 0.0, rw = 0.0;
               for (int jj = jb; jj < je; ++jj) {
                 if (kon && sm.jfid[jj] != kfid) {
                   double ca = __dadd_rn(__dadd_rn(__dmul_rn(sm.jx[jj], kx), __dmul_rn(sm.jy[jj], ky)),
@@ -611,11 +633,27 @@ __global__ __launch_bounds__(kBlock3) void xi3w_kernel(Xi3Args a) {
                     const int s = sk + kc * nt;
                     const double pn = __dmul_rn(__dmul_rn(wdi, sm.jwd[jj]), kwd);
                     const double pw = __dmul_rn(__dmul_rn(wi, sm.jw[jj]), kw);
-                    atomicAdd(&sm.hc[s], 1u);
-                    atomicAdd(&sm.hn[s], pn);
-                    atomicAdd(&sm.hw[s], pw);
+                    if (s != rs) {
+                      if (rs >= 0) {
+                        atomicAdd(&sm.hc[rs], rc);
+                        atomicAdd(&sm.hn[rs], rn);
+                        atomicAdd(&sm.hw[rs], rw);
+                      }
+                      rs = s;
+                      rc = 0u;
+                      rn = 0.0;
+                      rw = 0.0;
+                    }
+                    ++rc;
+                    rn = __dadd_rn(rn, pn);
+                    rw = __dadd_rn(rw, pw);
                   }
                 }
+              }
+              if (rs >= 0) {
+                atomicAdd(&sm.hc[rs], rc);
+                atomicAdd(&sm.hn[rs], rn);
+                atomicAdd(&sm.hw[rs], rw);
               }
             }
           }
