@@ -13,11 +13,16 @@
 // forests (a symmetric neighbour list with the box cut r_par, r_perp < r_max,
 // which every side shorter than r_max passes).  The workgroup takes f's pixels
 // one at a time: its waves scan the neighbours' pixels (one forest per wave,
-// lanes over pixels) and append every partner j with r_j in the r grid to an
-// LDS list (unit vector, side bins, w d, w, forest); then all threads run
-// over the ordered partner pairs (j, k) of different forests, bin cos alpha
-// and add the triplet to the global FP64 sums with atomics (the 5-d histogram
-// is far larger than LDS).  Everything is FP64; the geometry is written with
+// lanes over pixels) and append every partner j with r_j in the r grid to a
+// list (unit vector, side bins, w d, w, forest); then the ordered partner
+// pairs (j, k) of different forests are binned in cos alpha.  The 5-d
+// histogram is far larger than LDS.  Three kernels: the combining kernel
+// (list in LDS) orders the partners by the (r, theta) cell of their side and
+// sums each cell's entries in an LDS slice of the histogram before adding the
+// slice to the global FP64 sums; the wide kernel does the same with the list
+// in a per-workgroup global scratch, for pixels with thousands of partners;
+// the direct kernel adds every entry to the global sums (grids whose slice
+// does not fit LDS).  Everything is FP64; the geometry is written with
 // explicit operation order so it rounds like its definition.
 #include "lya_common.h"
 
@@ -91,7 +96,7 @@ struct GPartners {
   }
 };
 
-// Workgroup b's two lists (as gathered, and ordered by cell) in the scratch.
+// This workgroup's two lists (as gathered, and ordered by cell) in the scratch.
 __device__ __forceinline__ GPartners scratch_list(const Xi3Args& a, int which) {
   const int64_t cap = a.w_cap;
   double* d = a.w_dbl + ((int64_t)blockIdx.x * 2 + which) * 5 * cap;
