@@ -102,3 +102,30 @@ def test_deterministic_rejected_by_other_calls(lib):
         with pytest.raises(LyaError) as ei:
             c()
         assert ei.value.status == LYA_E_UNSUPPORTED
+
+
+def test_full_batched_workload_deterministic_bitwise(lib):
+    """The full batched covariance workload (64 realisations of 2k-20k
+    forests, ~6.7e7 pixels, FP32 form) in one deterministic launch against 64
+    separate deterministic launches: every realisation's N, W, counts and xi
+    carry the same bits."""
+    import time
+    from paper_2507_00129_amd import DeviceForests
+    from test_gpu_batched import realisation
+    F, G, _ = make_config(3, seed=0)
+    assert F.n_realisations == 64
+    dF = DeviceForests.from_host(F)
+    t = time.perf_counter()
+    out = lib.xi(dF, G, precision="fp32", deterministic=True, timing=True)
+    torch.cuda.synchronize()
+    st = lib.last_stats()
+    bat = {k: v.cpu().numpy() for k, v in out.items()}
+    del dF, out
+    print(f"[det batched full] pixels={F.n_pix} pairs={int(bat['npairs'].sum()):.4e} "
+          f"kernel={st['ms_main']:.1f} ms call={(time.perf_counter() - t) * 1e3:.1f} ms", flush=True)
+    for r in range(F.n_realisations):
+        S = realisation(F, r)
+        sep = {k: v.cpu().numpy() for k, v in lib.xi(DeviceForests.from_host(S), G, precision="fp32",
+                                                      deterministic=True).items()}
+        for k in ("num", "wsum", "npairs", "xi"):
+            assert np.array_equal(sep[k][0].view(np.uint64), bat[k][r].view(np.uint64)), (r, k)
