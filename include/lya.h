@@ -126,14 +126,17 @@ typedef struct {
   int32_t deterministic;      /* lya_xi: bitwise-reproducible sums, independent of
                                  the order the GPU adds pairs in, and identical
                                  for a realisation run alone or batched with
-                                 others.  Each pair's products w d w d and w w
-                                 (in the precision's arithmetic) are scaled by
-                                 2^s_r and rounded to an integer q, |q| <= 2^55,
-                                 with s_r per realisation from the largest |w d|
-                                 and w of its pixels; the integers are summed
-                                 exactly (two 64-bit words) and N, W converted
-                                 to FP64 at the end.  The rounding adds at most
-                                 2^-56 max|w d|^2 (max w^2) per pair.  Needs
+                                 others.  Runs of at most 32 same-bin products
+                                 w d w d (and w w) of one pixel against
+                                 consecutive pixels of the other forest are
+                                 summed in a fixed order in the precision's
+                                 arithmetic, scaled by 2^s_r and rounded to an
+                                 integer q, |q| <= 2^55, with s_r per
+                                 realisation from the largest |w d| and w of
+                                 its pixels; the integers are summed exactly
+                                 (two 64-bit words) and N, W converted to FP64
+                                 at the end.  The rounding adds at most
+                                 2^-51 max|w d|^2 (max w^2) per run.  Needs
                                  fewer than 2^36 pairs per bin and realisation
                                  (LYA_E_UNSUPPORTED otherwise); one fixed kernel
                                  variant.  The other calls return

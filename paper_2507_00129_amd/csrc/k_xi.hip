@@ -25,12 +25,14 @@
 // products of the same bin are first summed in FP32 registers (runs end at
 // every 32nd pixel of f, so a run holds at most 32 products).
 //
-// Deterministic form (DET).  Each in-grid pair's products, in the form's
-// arithmetic, are scaled by 2^s (s per realisation, from its largest |w d| and
-// w, so that |product| 2^s <= 2^55), rounded to integers and summed exactly as
-// two 64-bit words (low 28 bits and the rest), in LDS and then in global
-// memory; integer addition does not depend on the order, so the sums are
-// bitwise reproducible and identical for a realisation alone or batched.
+// Deterministic form (DET).  The run sums of the run-length form (at most 32
+// products of one lane, summed in a fixed order in the form's arithmetic) are
+// scaled by 2^s (s per realisation, from its largest |w d| and w, so that
+// |run sum| 2^s <= 2^55), rounded to integers and summed exactly as two 64-bit
+// words (low 28 bits and the rest), in LDS and then in global memory; integer
+// addition does not depend on the order, so the sums are bitwise reproducible
+// and identical for a realisation alone or batched (a run depends only on the
+// forest pair and the pixel, not on how the work is split).
 //
 // Bin means.  The MEANS form also sums w_i w_j x_par, w_i w_j x_perp (the bin
 // coordinates x = (r - e0) / dr the binning already computes) and
@@ -98,8 +100,10 @@ template <> struct Batch<Rec64> {
 // Fixed-point terms of the deterministic form: q = rint(x), |q| <= 2^55, split
 // as q = hi 2^28 + lo with 0 <= lo < 2^28; the two words are summed in separate
 // 64-bit integers (two's complement for hi), exact for fewer than 2^36 terms.
+// A term is a run sum of at most kRunMax = 2^5 products below m^2, so the
+// scale is 2^(50 - 2 e) for m < 2^e.
 constexpr int kDetShift = 28;
-constexpr int kDetBits = 55;
+constexpr int kDetBits = 50;
 
 __device__ __forceinline__ void det_add(unsigned long long* h, double x) {
   const long long q = __double2ll_rn(x);
@@ -178,7 +182,7 @@ __device__ void flush_det(const XiArgs& a, unsigned long long* hq, unsigned* hn,
 template <typename T, int BLOCK, bool RLE, bool ZLO, bool MEANS, bool DET = false>
 __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
   static_assert(RLE || !MEANS, "bin means are accumulated by the run-length form");
-  static_assert(!(DET && (RLE || MEANS)), "the deterministic form adds every pair");
+  static_assert(!(DET && MEANS), "the deterministic form has no bin means");
   using Rec = typename RecOf<T>::type;
   extern __shared__ double smem[];
   __shared__ NbTable tb;
@@ -335,6 +339,12 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
           int curA = -1, ist = c0;
           T accN = 0, accW = 0, accP = 0, accT = 0, accZ = 0;
           auto add_run = [&](int A, int count) {
+            if constexpr (DET) {
+              det_add(&hq[4 * A], __dmul_rn((double)accN, scN));
+              det_add(&hq[4 * A + 2], __dmul_rn((double)accW, scW));
+              atomicAdd(&hn[A], (unsigned)count);
+              return;
+            }
             atomicAdd(&hNW[2 * A], (double)accN);
             atomicAdd(&hNW[2 * A + 1], (double)accW);
             atomicAdd(&hn[A], (unsigned)count);
@@ -559,22 +569,23 @@ int xi_blocks_per_cu(int variant, int precision, int n_bins) {
   return precision == LYA_FP64 ? occ_t<double>(variant, n_bins) : occ_t<float>(variant, n_bins);
 }
 
-// The deterministic form: 512 threads, one pair per lane and step.
-constexpr int kDetBlock = 512;
+// The deterministic form: the run-length form with 1024 threads (its 36 B
+// of LDS per bin leave one workgroup per CU at 2500 bins).
+constexpr int kDetBlock = 1024;
 
 hipError_t launch_xi_det(int precision, const XiArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
   const bool zlo = a.g.zero_lo_par && a.g.zero_lo_perp;
   if (precision == LYA_FP64)
-    return zlo ? launch_one<double, kDetBlock, false, true, false, true>(a, blocks, st)
-               : launch_one<double, kDetBlock, false, false, false, true>(a, blocks, st);
-  return zlo ? launch_one<float, kDetBlock, false, true, false, true>(a, blocks, st)
-             : launch_one<float, kDetBlock, false, false, false, true>(a, blocks, st);
+    return zlo ? launch_one<double, kDetBlock, true, true, false, true>(a, blocks, st)
+               : launch_one<double, kDetBlock, true, false, false, true>(a, blocks, st);
+  return zlo ? launch_one<float, kDetBlock, true, true, false, true>(a, blocks, st)
+             : launch_one<float, kDetBlock, true, false, false, true>(a, blocks, st);
 }
 
 int xi_det_blocks_per_cu(int precision, int n_bins) {
-  return precision == LYA_FP64 ? occupancy<double, kDetBlock, false, false, true>(n_bins)
-                               : occupancy<float, kDetBlock, false, false, true>(n_bins);
+  return precision == LYA_FP64 ? occupancy<double, kDetBlock, true, false, true>(n_bins)
+                               : occupancy<float, kDetBlock, true, false, true>(n_bins);
 }
 
 hipError_t launch_det_max(const lya_forests* F, const ForestInfo* finfo, const double* delta,
