@@ -17,7 +17,10 @@
  *     and the weighted bin-mean r_par, r_perp and z of each bin;
  *   - the triplet sums of the anisotropic three-point function
  *     xi3_A = sum_A w_i d_i w_j d_j w_k d_k / sum_A w_i w_j w_k over pixels of
- *     three distinct forests (Sec. 2.3, eq. estimator_three).
+ *     three distinct forests (Sec. 2.3, eq. estimator_three), also split by
+ *     subsample;
+ *   - optionally (lya_options.deterministic), xi sums that are bitwise
+ *     reproducible and identical for a realisation alone or batched.
  *
  * Geometry.  Forest f has a sky direction n_f (from ra, dec).  With
  * s = |n_f - n_g| / 2 = sin(theta/2) and c = sqrt(1 - s^2), a pixel pair at
