@@ -260,6 +260,8 @@ def main():
                          ms_step=1e3 * wall / args.steps,
                          ms_xi_kernel=mean([s["ms_main"] for s in sx]),
                          ms_d_kernel=mean([s["ms_main"] for s in sd]),
+                         ms_xi_kernel_median=float(np.median([s["ms_main"] for s in sx])),
+                         ms_d_kernel_median=float(np.median([s["ms_main"] for s in sd])),
                          ms_xi_total=mean([s["ms_precompute"] + s["ms_worklist"] + s["ms_main"] + s["ms_finalize"] for s in sx]),
                          ms_d_total=mean([s["ms_precompute"] + s["ms_worklist"] + s["ms_main"] + s["ms_finalize"] for s in sd]),
                          cand=int(sx[-1]["candidate_pairs"]), d_fmas=int(sdc["outer_fmas"]),
@@ -349,6 +351,12 @@ def main():
     line["roofline_xi"] = xi_roofline(r32)
     line["xi_pairs_per_s_kernel"] = r32["xi_pairs"] / (r32["ms_xi_kernel"] / 1e3)
     line["d_pairs_per_s_kernel"] = r32["d_pairs"] / max(r32["ms_d_kernel"] / 1e3, 1e-12)
+    # whole calls (precompute, work list, kernel, finalise; device time of the
+    # timed steps) and the spread of the kernel times over the timed steps
+    line["xi_pairs_per_s_call"] = r32["xi_pairs"] / (r32["ms_xi_total"] / 1e3)
+    line["d_pairs_per_s_call"] = r32["d_pairs"] / max(r32["ms_d_total"] / 1e3, 1e-12)
+    line["kernel_ms"] = dict(xi_mean=r32["ms_xi_kernel"], xi_median=r32["ms_xi_kernel_median"],
+                             d_mean=r32["ms_d_kernel"], d_median=r32["ms_d_kernel_median"])
     if means is not None:
         line["xi_means_fp32"] = means
     if xi3 is not None:
@@ -359,6 +367,10 @@ def main():
         line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_step"],
                             xi_pairs_per_s_kernel=r64["xi_pairs"] / (r64["ms_xi_kernel"] / 1e3),
                             d_pairs_per_s_kernel=r64["d_pairs"] / max(r64["ms_d_kernel"] / 1e3, 1e-12),
+                            xi_pairs_per_s_call=r64["xi_pairs"] / (r64["ms_xi_total"] / 1e3),
+                            d_pairs_per_s_call=r64["d_pairs"] / max(r64["ms_d_total"] / 1e3, 1e-12),
+                            kernel_ms=dict(xi_mean=r64["ms_xi_kernel"], xi_median=r64["ms_xi_kernel_median"],
+                                           d_mean=r64["ms_d_kernel"], d_median=r64["ms_d_kernel_median"]),
                             d_mfma_tflops=d64 / 1e12, d_mfma_frac_of_f64_peak=d64 / PEAK_MFMA_F64)
         line["fp32_over_fp64"] = r32["value"] / r64["value"]
         if not args.no_check:
