@@ -68,9 +68,13 @@ typedef enum {
 typedef enum {
   /* Pair geometry and products in FP32 (distances re-centred so that
      FP32 keeps ~1e-4 Mpc/h); pairs within rounding of a bin edge are re-binned
-     in FP64, so binning equals the FP64 decision; sums are accumulated with
-     error compensation into FP64 totals.  Per-forest projection sums and the
-     final normalisation are FP64. */
+     in FP64, so binning equals the FP64 decision.  xi: runs of at most 32
+     same-bin FP32 products are summed in FP32 registers and the run sums are
+     accumulated in FP64 (LDS, then global) -- FP64 accumulation, not a
+     compensated FP32 sum.  D: the row histograms and the row contraction are
+     FP32, accumulated in FP32 over a run of forest pairs and then added to
+     FP64 totals.  Per-forest projection sums and the final normalisation
+     are FP64. */
   LYA_FP32_COMP = 0,
   /* Everything in FP64. */
   LYA_FP64 = 1
@@ -139,7 +143,7 @@ typedef struct {
                                  its pixels; the integers are summed exactly
                                  (two 64-bit words) and N, W converted to FP64
                                  at the end.  The rounding adds at most
-                                 2^-51 max|w d|^2 (max w^2) per run.  Needs
+                                 2^-49 max|w d|^2 (max w^2) per run.  Needs
                                  fewer than 2^36 pairs per bin and realisation
                                  (LYA_E_UNSUPPORTED otherwise); one fixed kernel
                                  variant.  The other calls return
@@ -302,7 +306,10 @@ lya_status lya_dmat(lya_context *ctx, const lya_forests *forests, const lya_grid
                     const lya_options *opts, void *stream,
                     double *dmat, double *wsum_d);
 
-/* Gradient of a scalar L(xi) with respect to delta and w.  Inputs
+/* Gradient of a scalar L(xi) with respect to delta and w: the derivative of
+   the estimator of Sec. 2.1 (eq. estimator_two), xi_A = N_A / W_A, through
+   N_A and W_A for fixed bins (positions get no gradient: the binning is
+   piecewise constant).  Inputs
    grad_xi = dL/dxi, xi and wsum as produced by lya_xi with the same options,
    each [n_realisations * n_bins], device.  Outputs [n_pix], device.
    Without project_deltas:

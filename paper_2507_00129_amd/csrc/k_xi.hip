@@ -101,7 +101,7 @@ template <> struct Batch<Rec64> {
 // as q = hi 2^28 + lo with 0 <= lo < 2^28; the two words are summed in separate
 // 64-bit integers (two's complement for hi), exact for fewer than 2^36 terms.
 // A term is a run sum of at most kRunMax = 2^5 products below m^2, so the
-// scale is 2^(50 - 2 e) for m < 2^e.
+// scale is 2^(kDetBits - 2 e) = 2^(50 - 2 e) for m < 2^e.
 constexpr int kDetShift = 28;
 constexpr int kDetBits = 50;
 
@@ -112,7 +112,9 @@ __device__ __forceinline__ void det_add(unsigned long long* h, double x) {
 }
 
 // s for products below m^2, m given by the bits of a non-negative double:
-// s = 55 - 2 e with m < 2^e (clamped to the double's range).
+// s = kDetBits - 2 e with m < 2^e (clamped to the double's range).  A run sum
+// then stays below 2^5 m^2 2^s <= 2^55, and rounding it to an integer adds at
+// most 0.5 2^-s = 2^(2 e - 51) <= 2^-49 m^2 (m >= 2^(e - 1)).
 __device__ __forceinline__ int det_shift(unsigned long long mbits) {
   if (mbits == 0ull) return 0;
   const int E = (int)(mbits >> 52);
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(BLOCK) void xi_kernel(XiArgs a) {
 
     // output slab: the realisation, or realisation * n_sub + subsample of f
     const int okey = a.sub ? fi.real * a.n_sub + a.sub[f] : fi.real;
-    if (okey != cur_key || pending + (double)total * fi.npix > 4.0e9) {
+    if (okey != cur_key || pending + (double)total * fi.npix > a.flush_pairs) {
       if (cur_key >= 0) {
         if constexpr (DET) flush_det<BLOCK>(a, hq, hn, cur_key); else flush_hist<BLOCK, MEANS>(a, hNW, hM, hn, cur_key);
         __syncthreads();

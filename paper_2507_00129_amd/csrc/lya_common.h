@@ -238,7 +238,12 @@ struct XiArgs {
   // (N low, N high, W low, W high words)
   const unsigned long long* det_max;
   unsigned long long* det_acc;
+  // a workgroup flushes its LDS histograms before the candidate pairs added
+  // since its last flush could exceed this (u32 counts hold < 2^32)
+  double flush_pairs;
 };
+// default of XiArgs::flush_pairs
+constexpr double kXiFlushPairs = 4.0e9;
 int xi_num_variants();
 const char* xi_variant_name(int v);
 hipError_t launch_xi(int variant, int precision, const XiArgs& a, int blocks, hipStream_t st);

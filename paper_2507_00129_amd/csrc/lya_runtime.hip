@@ -3,6 +3,7 @@
 // and the autotuner that picks kernel variants by timing them on the input.
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -28,11 +29,16 @@ struct lya_context {
   std::map<std::string, int> tuned;
   hipEvent_t ev[8]{};
   void* pinned = nullptr;  // small pinned host staging area
+  // candidate pairs after which an xi workgroup flushes its LDS histograms;
+  // the environment variable LYA_XI_FLUSH_PAIRS lowers it (a test hook that
+  // exercises the flush on small inputs)
+  double xi_flush_pairs = kXiFlushPairs;
 };
 
 namespace {
 
 constexpr double kPi = 3.141592653589793;
+
 constexpr int kDmatChunk = 1024;  // kept forest pairs per distortion work item
 
 lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -417,6 +423,10 @@ lya_status lya_create(lya_context** out, int device) {
     delete ctx;
     return LYA_E_NOMEM;
   }
+  if (const char* fp = getenv("LYA_XI_FLUSH_PAIRS")) {
+    const double v = atof(fp);
+    if (v >= 1.0 && v < kXiFlushPairs) ctx->xi_flush_pairs = v;
+  }
   *out = ctx;
   return LYA_OK;
 }
@@ -483,7 +493,13 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
     tm.at(1);
     Worklist W;
     const int chunk = xi_chunk(F, 4096);
-    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, false, 0, 0, false, chunk, "xi", W, sub != nullptr));
+    // subsample sums and the deterministic form list each unordered pair under
+    // the forest with the smaller input index: the owner (and with it which
+    // forest's pixels form the run sums) then does not depend on the sky
+    // index, whose strip height follows the smallest distance of the whole
+    // batch
+    LYA_TRY(build_worklist(ctx, F, gd, P, st, false, false, 0, 0, false, chunk, "xi", W,
+                           sub != nullptr || o->deterministic != 0));
     tm.at(2);
     ctx->stats.forest_pairs = W.n_pairs;
     ctx->stats.work_items = W.n_items;
@@ -511,6 +527,7 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
     a.n_sub = sub ? n_sub : 1;
     a.msum = msum;
     a.n_out = nout;
+    a.flush_pairs = ctx->xi_flush_pairs;
 
     if (o->deterministic) {
       // fixed-point integer sums with a scale per realisation; one variant

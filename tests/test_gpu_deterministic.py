@@ -129,3 +129,24 @@ def test_full_batched_workload_deterministic_bitwise(lib):
                                                       deterministic=True).items()}
         for k in ("num", "wsum", "npairs", "xi"):
             assert np.array_equal(sep[k][0].view(np.uint64), bat[k][r].view(np.uint64)), (r, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deterministic_batched_with_different_min_distance(lib, prec):
+    """A high-redshift realisation (its pixels start above 3600 A, so its
+    smallest distance is larger than the other realisations') in a batch: the
+    sky index's strip height follows the smallest distance of the whole call,
+    so it differs between the batched and the separate run, yet the
+    realisation's sums keep their bits (the row forest of a pair is the one
+    with the smaller input index, whatever the strips)."""
+    parts = [make_patch(80, 2.0, 411, z_range=(3.0, 3.5)), make_patch(80, 2.0, 412),
+             make_patch(50, 2.0, 413, z_range=(2.1, 2.3))]
+    assert parts[0].dist.min() > parts[1].dist.min() + 200.0
+    F = concat_realisations(parts)
+    bat = run_xi(lib, F, G60, precision=prec, deterministic=True)
+    for r, P in enumerate(parts):
+        sep = run_xi(lib, P, G60, precision=prec, deterministic=True)
+        assert sep["npairs"].sum() > 0
+        for k in ("num", "wsum", "npairs", "xi"):
+            assert np.array_equal(sep[k][0].view(np.uint64), bat[k][r].view(np.uint64)), (r, k)
+    print(f"[det min-distance {prec}] pairs={int(bat['npairs'].sum())} bitwise equal", flush=True)

@@ -8,7 +8,7 @@ import oracle as O
 from synth import Grid, concat_realisations, make_config, make_patch, subset_forests, uniform_grid
 from synth.survey import nearest_to_centre
 
-from helpers import tiny
+from helpers import tiny, truncate
 from test_gpu_xi import _ragged_forests
 
 torch = pytest.importorskip("torch")
@@ -149,3 +149,63 @@ def test_windows_wider_than_one_tile(lib, prec, n_par):
     for v in (0,):
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"wide-windows-v{v}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config0_against_definition(lib, prec):
+    """Config 0 against eq. distortion with each forest pair's inner double sum
+    formed as eta_f M^B eta_g^T (oracle.dmat_definition): no factorisation in
+    common with the kernels."""
+    F, G, _ = make_config(0, seed=0)
+    ref = O.dmat_definition(F, G, O.dmat_pairs(F, G))
+    out = run_dmat(lib, F, G, precision=prec)
+    check(out, ref, prec, "config0-definition")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_realisations_against_definition(lib, prec):
+    """Three realisations of short forests (a few hundred pixels each, many
+    touched bins per forest pair) against the definition form."""
+    parts = [truncate(make_patch(n, 1.0, 90 + r, z_range=(2.1, 2.4)), 40) for r, n in enumerate((9, 14, 11))]
+    F = concat_realisations(parts)
+    G = uniform_grid(12, 60.0, 10, 40.0)
+    ref = O.dmat_definition(F, G, O.dmat_pairs(F, G))
+    assert (ref.wd > 0).sum() > 100
+    out = run_dmat(lib, F, G, precision=prec)
+    check(out, ref, prec, "realisations-definition")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config1_subpatch_120(lib, prec):
+    """The 120 forests nearest the centre of an eBOSS-like patch on the 50x50
+    grid to 200 Mpc/h (7e3 forest pairs, long runs of pairs per tile)."""
+    F, G, _ = make_config(1, seed=0, scale=0.02)
+    S = subset_forests(F, nearest_to_centre(F, 120))
+    ref = O.dmat(S, G, O.dmat_pairs(S, G))
+    out = run_dmat(lib, S, G, precision=prec)
+    check(out, ref, prec, "config1-sub120")
+
+
+def test_full_config1_fp32_vs_fp64(lib):
+    """The full eBOSS-like patch (30k forests, all 1.9e7 forest pairs): the
+    FP32 form's D against the FP64 form's, row-normwise within 1e-5, w_A
+    within 1e-5, and no in-grid pixel pair outside its window."""
+    import time
+    from paper_2507_00129_amd import DeviceForests
+    F, G, _ = make_config(1, seed=0)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        t = time.perf_counter()
+        o = lib.dmat(dF, G, precision=prec, timing=True, counters=True)
+        torch.cuda.synchronize()
+        st = lib.last_stats()
+        assert st["lost_pairs"] == 0, st
+        out[prec] = {k: v.cpu().numpy() for k, v in o.items()}
+        print(f"[dmat full {prec}] forest pairs={st['forest_pairs']} in-grid pairs={st['ingrid_pairs']:.4e} "
+              f"kernel={st['ms_main']:.0f} ms call={(time.perf_counter() - t) * 1e3:.0f} ms", flush=True)
+        del o
+    e_d = O.err_rows(out["fp32"]["dmat"], out["fp64"]["dmat"])
+    e_w = O.err_rel(out["fp32"]["wsum_d"], out["fp64"]["wsum_d"])
+    print(f"[dmat full] fp32 vs fp64: e_D={e_d:.2e} e_W={e_w:.2e}", flush=True)
+    assert e_d <= 1e-5 and e_w <= 1e-5

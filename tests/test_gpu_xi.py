@@ -265,3 +265,79 @@ def test_full_desi_workload_fp32_vs_fp64(lib):
     e_w = O.err_rel(out["fp32"]["wsum"], out["fp64"]["wsum"])
     print(f"[desi full] fp32 vs fp64: e_N={e_n:.2e} e_W={e_w:.2e}", flush=True)
     assert e_n <= 1e-5 and e_w <= 1e-5
+
+
+def test_flush_path_vs_oracle(lib, monkeypatch):
+    """A workgroup adds its LDS histograms to the global sums and clears them
+    before its u32 pair counts could overflow (after 4e9 candidate pairs).
+    LYA_XI_FLUSH_PAIRS (read by lya_create) lowers that threshold to 5000
+    candidate pairs, so every workgroup flushes before nearly every work item:
+    the sums must still match the oracle in every form and variant."""
+    from paper_2507_00129_amd import Library
+    F, G, _ = make_config(0, seed=5)
+    ref = O.xi_sums(F, G)
+    monkeypatch.setenv("LYA_XI_FLUSH_PAIRS", "5000")
+    L = Library(0)
+    try:
+        for prec in ("fp64", "fp32"):
+            for v in range(4):
+                check(run_xi(L, F, G, precision=prec, variant=v, autotune=False), ref, prec, f"flush v{v}")
+            check(run_xi(L, F, G, precision=prec, deterministic=True), ref, prec, "flush det")
+    finally:
+        L.close()
+
+
+def test_single_bin_count_overflow_flush(lib):
+    """One bin holding every pair of 45k forests (3.6e6 pixels, ~1e13 pairs):
+    each persistent workgroup evaluates more than 2^32 candidate pairs, so its
+    u32 bin count would overflow without the flush taken every 4e9 candidate
+    pairs.  Checked against the O(n) closed forms N = ((sum S_f)^2 - sum S_f^2)/2
+    (S_f = sum_i w_i d_i), W likewise, and the exact pair count."""
+    import time
+    from paper_2507_00129_amd import DeviceForests
+    F, _, _ = make_config(1, seed=6, scale=1.5)
+    G = Grid(np.array([0.0, 1e5]), np.array([0.0, 1e5]))
+    fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
+    S = np.bincount(fid, weights=F.weight * F.delta, minlength=F.n_forests)
+    Wf = np.bincount(fid, weights=F.weight, minlength=F.n_forests)
+    Af = np.bincount(fid, weights=np.abs(F.weight * F.delta), minlength=F.n_forests)
+    n = np.diff(F.offsets).astype(np.int64)
+    N_exp = (S.sum() ** 2 - np.sum(S ** 2)) / 2
+    W_exp = (Wf.sum() ** 2 - np.sum(Wf ** 2)) / 2
+    A_exp = (Af.sum() ** 2 - np.sum(Af ** 2)) / 2
+    n_exp = (int(n.sum()) ** 2 - int(np.sum(n ** 2))) // 2
+    dF = DeviceForests.from_host(F, "cuda:0")
+    tol = {"fp64": 1e-10, "fp32": 1e-5}
+    for prec in ("fp64", "fp32"):
+        t = time.perf_counter()
+        out = lib.xi(dF, G, precision=prec, variant=3, autotune=False, timing=True)
+        torch.cuda.synchronize()
+        st = lib.last_stats()
+        o = {k: v.cpu().numpy() for k, v in out.items()}
+        per_wg = st["candidate_pairs"] / st["grid_blocks"]
+        print(f"[single-bin overflow {prec}] pixels={F.n_pix} pairs={int(o['npairs'][0, 0]):.4e} "
+              f"workgroups={st['grid_blocks']} candidates/workgroup={per_wg:.3e} kernel={st['ms_main']:.0f} ms "
+              f"dN/A={abs(o['num'][0, 0] - N_exp) / A_exp:.2e} dW/W={abs(o['wsum'][0, 0] - W_exp) / W_exp:.2e} "
+              f"call={(time.perf_counter() - t):.1f} s", flush=True)
+        assert st["candidate_pairs"] == n_exp
+        # the premise: on average a workgroup sees more pairs than a u32 holds
+        assert per_wg > 2.0 ** 32
+        assert int(o["npairs"][0, 0]) == n_exp
+        assert abs(o["num"][0, 0] - N_exp) <= tol[prec] * A_exp
+        assert abs(o["wsum"][0, 0] - W_exp) <= tol[prec] * W_exp
+
+
+def test_config2_compact_subpatch(lib):
+    """DESI-like forests (linear 0.8 A pixels, 300-700 per forest) on the 50x50
+    grid to 200 Mpc/h with deltas projected per forest (MEAN_SLOPE), as the
+    DESI-like workload runs: the 48 forests nearest the centre of a patch at
+    its density, against the oracle's sums on deltas it projected itself, in
+    both forms (one oracle run)."""
+    F, G, ex = make_config(2, seed=1, scale=0.01)
+    assert ex["project_deltas"]
+    S = subset_forests(F, nearest_to_centre(F, 48))
+    ref = O.xi_sums(S, G, project=True, eta_mode=O.MEAN_SLOPE)
+    assert ref.npairs.sum() > 5e7
+    for prec in ("fp64", "fp32"):
+        check(run_xi(lib, S, G, precision=prec, project_deltas=True, eta="mean_slope"), ref, prec,
+              "config2-sub")
