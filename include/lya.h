@@ -180,6 +180,9 @@ void lya_options_default(lya_options *opts);
    grow-only device workspace and the autotuner's cache. */
 lya_status lya_create(lya_context **ctx, int device);
 void lya_destroy(lya_context *ctx);
+/* Message of the last failure on ctx; with ctx == NULL, the message of the
+   last lya_create that failed on the calling thread ("NULL context" if
+   none). */
 const char *lya_last_error(const lya_context *ctx);
 lya_status lya_last_stats(const lya_context *ctx, lya_stats *out);
 

@@ -30,6 +30,11 @@ __global__ void keys_kernel(WorklistArgs a) {
   a.ids[f] = (int32_t)f;
 }
 
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 __device__ __forceinline__ int cell_of(uint64_t key, int n_strips) {
   return (int)(key >> 44) * n_strips + (int)((key >> 32) & 0xFFF);
 }
@@ -151,9 +156,12 @@ hipError_t launch_sort_forests(WorklistArgs& a, hipStream_t st) {
                                          (int)a.n_forests, 0, 64, st);
   if (e != hipSuccess) return e;
   const size_t ncell = (size_t)a.n_real * a.n_strips;
-  e = hipMemsetAsync(a.cell_begin, 0xFF, ncell * sizeof(int32_t), st);
-  if (e != hipSuccess) return e;
-  e = hipMemsetAsync(a.cell_end, 0xFF, ncell * sizeof(int32_t), st);
+  // empty cells read -1 (a fill kernel rather than a memset node)
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)ncell, 256)), dim3(256), 0, st, a.cell_begin,
+                     (int64_t)ncell, -1);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk((int64_t)ncell, 256)), dim3(256), 0, st, a.cell_end,
+                     (int64_t)ncell, -1);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cells_kernel, dim3(nblk(a.n_forests, 256)), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -52,6 +52,19 @@ lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) {
   return s;
 }
 
+// Message of the last lya_create that failed on this thread (no context to
+// hold it); lya_last_error(NULL) returns it.
+thread_local char g_create_err[256] = "";
+
+lya_status create_failed(lya_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lya_status create_failed(lya_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_create_err, sizeof g_create_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \
     hipError_t e_ = (expr);                                                                \
@@ -67,8 +80,8 @@ lya_status fail(lya_context* ctx, lya_status s, const char* fmt, ...) {
 
 // Grow-only named workspace buffer (256-byte aligned by hipMalloc).
 lya_status ws(lya_context* ctx, const char* name, size_t bytes, void** out) {
-  Buf& b = ctx->bufs[name];
   if (bytes == 0) bytes = 256;
+  Buf& b = ctx->bufs[name];
   if (b.bytes < bytes) {
     if (b.p) {
       hipDeviceSynchronize();
@@ -402,26 +415,28 @@ lya_status lya_create(lya_context** out, int device) {
   if (!out) return LYA_E_INVALID;
   *out = nullptr;
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n) {
     hipGetLastError();
-    return LYA_E_DEVICE;
+    return create_failed(LYA_E_DEVICE, "hipGetDeviceCount: %s (%d devices, device %d requested)",
+                         hipGetErrorString(e), n, device);
   }
   lya_context* ctx = new lya_context();
   ctx->device = device;
-  if (hipSetDevice(device) != hipSuccess) {
+  if ((e = hipSetDevice(device)) != hipSuccess) {
     delete ctx;
-    return LYA_E_DEVICE;
+    return create_failed(LYA_E_DEVICE, "hipSetDevice(%d): %s", device, hipGetErrorString(e));
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
-  for (auto& e : ctx->ev)
-    if (hipEventCreate(&e) != hipSuccess) {
+  for (auto& ev : ctx->ev)
+    if ((e = hipEventCreate(&ev)) != hipSuccess) {
       delete ctx;
-      return LYA_E_DEVICE;
+      return create_failed(LYA_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
     }
-  if (hipHostMalloc(&ctx->pinned, 4096) != hipSuccess) {
+  if ((e = hipHostMalloc(&ctx->pinned, 4096)) != hipSuccess) {
     delete ctx;
-    return LYA_E_NOMEM;
+    return create_failed(LYA_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
   }
   if (const char* fp = getenv("LYA_XI_FLUSH_PAIRS")) {
     const double v = atof(fp);
@@ -443,7 +458,10 @@ void lya_destroy(lya_context* ctx) {
   delete ctx;
 }
 
-const char* lya_last_error(const lya_context* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+const char* lya_last_error(const lya_context* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_create_err[0] ? g_create_err : "NULL context";
+}
 
 lya_status lya_last_stats(const lya_context* ctx, lya_stats* out) {
   if (!ctx || !out) return LYA_E_INVALID;

@@ -82,6 +82,11 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing (run paper_2507_00129_amd.build)")
+    # torch first: its HIP runtime is then the one the library binds to (same
+    # soname), so streams and device pointers from torch are valid in the
+    # library; loaded the other way round, the process would hold two HIP
+    # runtimes
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.lya_options_default.argtypes = [ctypes.POINTER(lya_options)]
@@ -207,7 +212,7 @@ class Library:
         self.ctx = ctypes.c_void_p()
         s = self.lib.lya_create(ctypes.byref(self.ctx), self.device)
         if s != LYA_OK:
-            raise LyaError(s, f"lya_create(device={device}) failed")
+            raise LyaError(s, f"lya_create(device={device}) failed: {self.lib.lya_last_error(None).decode()}")
 
     def close(self):
         if self.ctx:
