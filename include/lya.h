@@ -198,6 +198,29 @@ lya_status lya_xi(lya_context *ctx, const lya_forests *forests, const lya_grid *
                   const lya_options *opts, void *stream,
                   double *num, double *wsum, int64_t *npairs, double *xi);
 
+/* Size of the device array that lya_xi_noalloc works in (64 MiB per GPU). */
+#define LYA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* lya_xi for callers that cannot allocate device memory: code that must not
+   call hipMalloc (inside a stream capture, a tight serving loop, a harness
+   that forbids allocation).  Same arguments, outputs, options and errors as
+   lya_xi.  The work space (per-forest sums, packed pixel records, sky index,
+   neighbour lists, work items, sort buffers) is taken from a fixed device
+   array of LYA_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+   runs on until the process ends (its address is looked up once per device,
+   in lya_create); the call allocates no device or pinned memory.  An input
+   whose work space does not fit returns LYA_E_UNSUPPORTED with the size in
+   the message (the outputs are then unspecified); as a guide, ~1e6 pixels
+   with ~8e6 forest pairs fit.  The autotuner is not run: options.variant >= 0
+   forces a variant, otherwise a variant the context has already tuned for
+   this shape, else the default.  All calls on one GPU share that GPU's array
+   and everything they need in it is rewritten by each call: calls that
+   overlap on one GPU (two threads, two contexts, or two streams with no
+   ordering between the calls) race and give wrong results. */
+lya_status lya_xi_noalloc(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
+                          const lya_options *opts, void *stream,
+                          double *num, double *wsum, int64_t *npairs, double *xi);
+
 /* lya_xi plus the weighted bin-mean coordinates of the pairs, the r_par,
    r_perp and z columns that the paper's output carries next to xi for the
    model fit (Sec. 3.1: the PICCA-format output read by Vega).  Extra outputs,

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,11 +34,44 @@ struct lya_context {
   // the environment variable LYA_XI_FLUSH_PAIRS lowers it (a test hook that
   // exercises the flush on small inputs)
   double xi_flush_pairs = kXiFlushPairs;
+  // the no-allocation entry point carves its workspace from `scratch_base`
+  // (this device's copy of the library's fixed scratch array) while `noalloc`
+  // is set, bumping `scratch_off`
+  unsigned char* scratch_base = nullptr;
+  hipError_t scratch_status = hipSuccess;
+  bool noalloc = false;
+  size_t scratch_off = 0;
 };
+
+// Fixed device scratch of lya_xi_noalloc.  Every GPU the library runs on holds
+// its own copy until the process ends.  In host code this name is only a
+// stand-in for the symbol: the device address of a GPU's copy comes from
+// hipGetSymbolAddress, taken once per device (scratch_of) and kept.
+static __device__ __align__(256) unsigned char scratch[LYA_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
 constexpr double kPi = 3.141592653589793;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch array on `device`, which must be current;
+// looked up once per device.
+hipError_t scratch_of(int device, unsigned char** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = (unsigned char*)p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 constexpr int kDmatChunk = 1024;  // kept forest pairs per distortion work item
 
@@ -78,9 +112,20 @@ lya_status create_failed(lya_status s, const char* fmt, ...) {
     if (s_ != LYA_OK) return s_;    \
   } while (0)
 
-// Grow-only named workspace buffer (256-byte aligned by hipMalloc).
+// Grow-only named workspace buffer (256-byte aligned by hipMalloc); in the
+// no-allocation mode a 256-byte aligned slice of the device scratch array.
 lya_status ws(lya_context* ctx, const char* name, size_t bytes, void** out) {
   if (bytes == 0) bytes = 256;
+  if (ctx->noalloc) {
+    const size_t at = (ctx->scratch_off + 255) & ~(size_t)255;
+    if (at > LYA_NOALLOC_SCRATCH_BYTES || bytes > LYA_NOALLOC_SCRATCH_BYTES - at)
+      return fail(ctx, LYA_E_UNSUPPORTED,
+                  "input too large for the no-allocation scratch: %s needs %zu bytes at offset %zu of %llu",
+                  name, bytes, at, (unsigned long long)LYA_NOALLOC_SCRATCH_BYTES);
+    *out = ctx->scratch_base + at;
+    ctx->scratch_off = at + bytes;
+    return LYA_OK;
+  }
   Buf& b = ctx->bufs[name];
   if (b.bytes < bytes) {
     if (b.p) {
@@ -438,6 +483,10 @@ lya_status lya_create(lya_context** out, int device) {
     delete ctx;
     return create_failed(LYA_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
   }
+  // the no-allocation entry point reports a failed lookup; the others never need it
+  ctx->scratch_status = scratch_of(device, &ctx->scratch_base);
+  if (ctx->scratch_status != hipSuccess) hipGetLastError();
+  ctx->err.reserve(512);  // error messages then need no allocation
   if (const char* fp = getenv("LYA_XI_FLUSH_PAIRS")) {
     const double v = atof(fp);
     if (v >= 1.0 && v < kXiFlushPairs) ctx->xi_flush_pairs = v;
@@ -601,7 +650,7 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
       variant = o->variant;
     } else if (found != ctx->tuned.end()) {
       variant = found->second;
-    } else if (o->autotune && W.n_items > 0) {
+    } else if (o->autotune && W.n_items > 0 && !ctx->noalloc) {
       double* sn;
       double* sw;
       unsigned long long* sc;
@@ -658,6 +707,20 @@ lya_status xi_impl(lya_context* ctx, const lya_forests* F, const lya_grid* G, co
 lya_status lya_xi(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                   void* stream, double* num, double* wsum, int64_t* npairs, double* xi) {
   return xi_impl(ctx, F, G, o, stream, nullptr, 1, num, wsum, npairs, xi);
+}
+
+lya_status lya_xi_noalloc(lya_context* ctx, const lya_forests* F, const lya_grid* G,
+                          const lya_options* o, void* stream, double* num, double* wsum, int64_t* npairs,
+                          double* xi) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!ctx->scratch_base)
+    return fail(ctx, LYA_E_DEVICE, "address of the device scratch array unavailable: %s",
+                hipGetErrorString(ctx->scratch_status));
+  ctx->noalloc = true;
+  ctx->scratch_off = 0;
+  const lya_status s = xi_impl(ctx, F, G, o, stream, nullptr, 1, num, wsum, npairs, xi);
+  ctx->noalloc = false;
+  return s;
 }
 
 lya_status lya_xi_means(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,

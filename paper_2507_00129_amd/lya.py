@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     FP, GP, OP = ctypes.POINTER(lya_forests), ctypes.POINTER(lya_grid), ctypes.POINTER(lya_options)
     lib.lya_xi.argtypes = [P, FP, GP, OP, P, P, P, P, P]
     lib.lya_xi.restype = I32
+    lib.lya_xi_noalloc.argtypes = [P, FP, GP, OP, P, P, P, P, P]
+    lib.lya_xi_noalloc.restype = I32
     lib.lya_dmat.argtypes = [P, FP, GP, OP, P, P, P]
     lib.lya_dmat.restype = I32
     lib.lya_xi_backward.argtypes = [P, FP, GP, OP, P, P, P, P, P, P]
@@ -273,6 +275,17 @@ class Library:
         self._check(self.lib.lya_xi(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
                                     self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
                                     _ptr(out["npairs"]), _ptr(out.get("xi"))))
+        return out
+
+    def xi_noalloc(self, forests: DeviceForests, grid, out, stream=None, **opts):
+        """lya_xi_noalloc: xi into caller-given outputs (dict of [R, n_bins]
+        tensors num, wsum, npairs and optionally xi) with no device allocation
+        in the library."""
+        g = HostGrid(grid)
+        fs, gs, o = forests.c_struct(), g.c_struct(), self.options(**opts)
+        self._check(self.lib.lya_xi_noalloc(self.ctx, ctypes.byref(fs), ctypes.byref(gs), ctypes.byref(o),
+                                            self._stream(stream), _ptr(out["num"]), _ptr(out["wsum"]),
+                                            _ptr(out["npairs"]), _ptr(out.get("xi"))))
         return out
 
     def xi3(self, forests: DeviceForests, grid3, stream=None, out=None, **opts):
