@@ -671,8 +671,12 @@ __global__ void finalize_dmat_kernel(double* d, const double* wd, int64_t n_rows
 
 }  // namespace
 
-int dmat_num_variants() { return kNumVariants; }
-const char* dmat_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kNames[v] : "?"; }
+// variants: this file's kernel, then the single-wave kernels (k_dmat_wave.hip)
+int dmat_num_variants() { return kNumVariants + dmat_wave_num_variants(); }
+const char* dmat_variant_name(int v) {
+  if (v >= kNumVariants) return dmat_wave_variant_name(v - kNumVariants);
+  return v >= 0 ? kNames[v] : "?";
+}
 
 hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st) {
   if (a.n_pairs == 0) return hipSuccess;
@@ -682,12 +686,12 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
-  (void)variant;
+  if (variant >= kNumVariants) return launch_dmat_wave(variant - kNumVariants, precision, a, blocks, st);
   return precision == LYA_FP64 ? launch_one<double, 512>(a, blocks, st) : launch_one<float, 512>(a, blocks, st);
 }
 
 int dmat_blocks_per_cu(int variant, int precision) {
-  (void)variant;
+  if (variant >= kNumVariants) return dmat_wave_blocks_per_cu(variant - kNumVariants, precision);
   return precision == LYA_FP64 ? occupancy<double, 512>() : occupancy<float, 512>();
 }
 

@@ -1,0 +1,679 @@
+// Distortion matrix, single-wave form (Sec. 2.2, eq. distortion).
+//
+// With eta_ii' = delta_ii' - p_i . q_i', p = (1, a), q = w p (1/W, 1/S) per
+// forest (a = L - Lbar), the numerator of one kept forest pair (f, g) is
+//   num_AB = w_A [A = B]
+//          - sum_{i in f} w_i sum_l c_gl R^l_i[A] R^l_i[B]
+//          - sum_{j in g} w_j sum_l c_fl R^l_j[A] R^l_j[B]
+//          + sum_kl c_fk c_gl H^kl_A H^kl_B
+// with c_X = (1/W_X, 1/S_X) (0 where the term is off), the row histograms
+// R^l_i[A] = sum_{j: A(i,j) = A} w_j p^l_j (the other forest's pixels) and
+// the pair histograms H^kl_A = sum_{(i,j) in A} w_i p^k_i w_j p^l_j.  Because
+// q is p scaled per pixel by w and per forest by c, the second factor of each
+// row term is the same histogram as the first and the fourth term is a sum of
+// squares too: num is symmetric.  Only the blocks on and above the diagonal
+// of a tile are accumulated; the flush writes each off-diagonal block twice.
+//
+// One wavefront is one workgroup: it owns its accumulator tile in registers,
+// a small LDS area, and needs no barrier with other waves.  It takes work
+// items (chunks of the window-sorted pair list) from an atomic counter; the
+// pairs of a chunk that share a window (the k_perp rows their r_perp range
+// spans) add into one tile, flushed to the global FP64 numerator once per
+// run.  Per forest pair, rows are taken two at a time (the K = 4 of a 16x16x4
+// MFMA step is two rows times l = 0, 1): the 64 lanes hold the other forest's
+// pixels (up to PMAX each) and bin both rows against them, adding w and w a
+// to the rows' histograms in LDS; the wave then reads the histograms back in
+// MFMA operand layout, scaled by sqrt(w_row c_l), and issues one step for
+// every tile block (bx <= by) that the union of the two rows' block masks
+// covers.  Two LDS buffers alternate, so the binning of the next two rows is
+// issued while the matrix core works on the current ones.  The pair
+// histograms H are summed in registers from the operands of the f rows; after
+// them, one more step per block adds the H term (K = 4 is kl) and the
+// Kronecker term w_A goes to an FP64 LDS accumulator.
+//
+// Tiles: NB x NB blocks of 16 window bins (the upper triangle, NB (NB+1)/2
+// accumulators).  Windows wider than NB blocks take several passes over the
+// run, each re-binning its rows: a diagonal pass per segment of NB blocks,
+// and rectangle passes of NB x NY blocks between segments.
+#include "lya_bin.h"
+#include "lya_common.h"
+
+namespace lya {
+
+namespace {
+
+typedef double wv_d4 __attribute__((ext_vector_type(4)));
+typedef float wv_f4 __attribute__((ext_vector_type(4)));
+
+// MFMA of each form.  16x16x4: operand A[i][k] and B[k][j] come from lane
+// 16 k + i (resp. 16 k + j).  FP32: register r of lane 16 g + j holds row
+// 4 g + r of column j; FP64: row g + 4 r.
+template <typename T> struct WForm;
+template <> struct WForm<float> {
+  using Acc = wv_f4;
+  using Rec = DRec32;
+  __device__ __forceinline__ static int row(int g, int r) { return 4 * g + r; }
+  __device__ __forceinline__ static Acc step(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct WForm<double> {
+  using Acc = wv_d4;
+  using Rec = DRec64;
+  __device__ __forceinline__ static int row(int g, int r) { return g + 4 * r; }
+  __device__ __forceinline__ static Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// OR over the wave, uniform result: four DPP steps reduce each row of 16
+// lanes, four lane reads combine the rows.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  int x = (int)v;
+  x |= __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // row_ror:4
+  x |= __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  return (uint32_t)(__builtin_amdgcn_readlane(x, 0) | __builtin_amdgcn_readlane(x, 16) |
+                    __builtin_amdgcn_readlane(x, 32) | __builtin_amdgcn_readlane(x, 48));
+}
+
+__device__ __forceinline__ float bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ float xor32(float v) { return __shfl_xor(v, 32, 64); }
+__device__ __forceinline__ double xor32(double v) { return __shfl_xor(v, 32, 64); }
+
+// One pass over a window of nblk blocks.  Diagonal pass: storage blocks
+// [0, nx) hold window blocks x0 .. x0 + nx - 1 and the tile keeps the blocks
+// bx <= by among them.  Rectangle pass: storage blocks [0, nx) hold window
+// blocks x0 ..., storage blocks NX + [0, ny) hold window blocks y0 ..., and
+// the tile keeps all nx x ny blocks (x and y ranges disjoint).
+struct WPass {
+  int x0, nx, y0, ny;
+  bool diag;
+};
+
+// Diagonal passes over segments of NB blocks, then for every pair of
+// segments a < b rectangle passes over pieces of NX blocks of a times pieces
+// of NY blocks of b.
+template <int NB, int NX, int NY>
+__device__ __forceinline__ int count_passes(int nblk) {
+  const int nseg = (nblk + NB - 1) / NB;
+  int n = nseg;
+  for (int b = 1; b < nseg; ++b) {
+    const int lb = min(NB, nblk - b * NB);
+    n += b * ((NB + NX - 1) / NX) * ((lb + NY - 1) / NY);
+  }
+  return n;
+}
+
+template <int NB, int NX, int NY>
+__device__ __forceinline__ WPass pass_of(int p, int nblk) {
+  const int nseg = (nblk + NB - 1) / NB;
+  if (p < nseg) {
+    const int n = min(NB, nblk - p * NB);
+    return WPass{p * NB, n, p * NB, n, true};
+  }
+  p -= nseg;
+  constexpr int px = (NB + NX - 1) / NX;  // pieces of a full segment
+  for (int b = 1; b < nseg; ++b) {
+    const int lb = min(NB, nblk - b * NB), py = (lb + NY - 1) / NY;
+    if (p < b * px * py) {
+      const int a = p / (px * py), rem = p % (px * py), ix = rem / py, iy = rem % py;
+      return WPass{a * NB + ix * NX, min(NX, NB - ix * NX), b * NB + iy * NY, min(NY, lb - iy * NY), false};
+    }
+    p -= b * px * py;
+  }
+  return WPass{0, 0, 0, 0, true};
+}
+
+template <int N> struct WIC { static constexpr int value = N; };
+
+// Column by of slot j in the upper-triangle order j = by (by + 1) / 2 + bx.
+constexpr int tri_row(int j) {
+  int by = 0;
+  while ((by + 1) * (by + 2) / 2 <= j) ++by;
+  return by;
+}
+
+// f(WIC<I>{}) for I = B .. E - 1: indices into register arrays stay
+// compile-time constants whatever the loop unroller decides.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(WIC<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Uniform pair data.
+struct WPair {
+  int64_t pf, pg;
+  int nf, ng;
+  double s, c;
+  double fdmin, fdmax, gdmin, gdmax;
+};
+
+template <typename T, int NB, int PMAX, int WPE, bool ZLO>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void dmat_wave_kernel(DmatArgs a) {
+  using Form = WForm<T>;
+  using Acc = typename Form::Acc;
+  using Rec = typename Form::Rec;
+  constexpr bool kF32 = sizeof(T) == 4;
+  constexpr int MB = NB * (NB + 1) / 2;  // accumulator blocks
+  constexpr int NX = NB / 2, NY = NB - NX;  // rectangle passes: NX x NY blocks
+  constexpr int SB = NB;                 // storage blocks per row and component
+  constexpr int SW = 16 * SB + 16;       // storage stride (padded against bank conflicts)
+  static_assert(NX + NY == SB, "a rectangle pass stores its x and y ranges side by side");
+  constexpr int CH = 64 * PMAX;          // other-forest pixels held in registers at a time
+  constexpr int GB = 4;                  // tile blocks staged per flush group
+  __shared__ T buf[2][4][SW];            // [buffer][2 row + l][storage bin]
+  __shared__ T stg[GB * 256];            // flush stage: GB blocks of 16 x 16
+  __shared__ uint8_t slot_by[MB];        // block column of each accumulator slot
+  __shared__ double wdacc[16 * NB];      // w_A of the run (diagonal passes)
+  __shared__ int32_t otab[16 * SB];      // output bin of each storage bin of the pass (-1 past the window)
+  constexpr int RCH = 128;               // rows of a sweep staged at a time
+  __shared__ T srow[3][RCH];             // d, w, w a of the staged rows
+  __shared__ double srowD[RCH];          // FP64 distance of the staged rows (edge guard)
+
+  const int lane = threadIdx.x;
+  const int lk = lane >> 4, lm = lane & 15;
+  const int rpar = lk >> 1, comp = lk & 1;  // operand slot of this lane: row of the step, l
+
+  BinK<T, ZLO> K;
+  K.init(a.g, a.glob, a.edges_par, a.edges_perp);
+  const int NP = K.NP, NT = K.NT, nb = NP * NT;
+  const Rec* __restrict__ recs;
+  if constexpr (kF32) recs = a.drec32; else recs = a.drec64;
+
+  for (int e = lane; e < 2 * 4 * SW; e += 64) (&buf[0][0][0])[e] = (T)0;
+  for (int e = lane; e < 16 * NB; e += 64) wdacc[e] = 0.0;
+  for (int j = lane; j < MB; j += 64) slot_by[j] = (uint8_t)tri_row(j);
+  unsigned long long n_in = 0, n_lost = 0, nalg = 0;  // statistics only
+
+  Acc acc[MB];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) acc[j] = Acc{0, 0, 0, 0};
+  T h0[SB], h1[SB];  // H partials: lane (row r, l, i) sums w_r p^k_r R^l_r[16 b + i], k = 0, 1
+#pragma unroll
+  for (int b = 0; b < SB; ++b) h0[b] = h1[b] = (T)0;
+
+  // one MFMA step, tile[bx][by] += A[bx] B[by], for every block bx <= by of
+  // the pass whose two storage blocks are set in the uniform mask u; a
+  // rectangle pass keeps only bx < NX <= by (x range times y range).  Each
+  // step sits in its own conditional block: the compiler then updates the
+  // accumulators in place.
+  auto tile_steps = [&](uint32_t u, bool diag, const T* A, const T* B) __attribute__((always_inline)) {
+    static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+      constexpr int by = decltype(BY)::value;
+      if (!((u >> by) & 1u)) return;
+      static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
+        constexpr int bx = decltype(BX)::value;
+        constexpr int j = by * (by + 1) / 2 + bx;
+        constexpr bool in_rect = bx < NX && by >= NX;
+        if (((u >> bx) & 1u) && (in_rect || diag)) acc[j] = Form::step(A[bx], B[by], acc[j]);
+      });
+    });
+  };
+
+  for (;;) {
+    __syncthreads();
+    unsigned itv = 0;
+    if (lane == 0) itv = atomicAdd(a.counter, 1u);
+    const int64_t it = (int64_t)(unsigned)__builtin_amdgcn_readlane((int)itv, 0);
+    if (it >= a.n_items) break;
+    const int64_t k0 = it * a.chunk;
+    const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
+    for (int64_t r0 = k0; r0 < k1;) {
+      const uint64_t key = a.wkeys[r0];
+      int64_t lo = r0 + 1, hi = k1;  // end of the run of equal keys
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.wkeys[mid] == key) lo = mid + 1; else hi = mid;
+      }
+      const int64_t r1 = lo;
+      if (key == ~0ull) {
+        r0 = r1;
+        continue;
+      }
+      const int real = (int)(key >> 40);
+      const int kt0 = (int)((key >> 16) & 0xFFFFFF);
+      const int span = (int)(key & 0xFFFF);
+      const int nwin = span * NP;
+      const int base_L = kt0 * NP;
+      const int nblk = (nwin + 15) >> 4;
+      const int64_t obase = (int64_t)real * nb;
+      const int npass = count_passes<NB, NX, NY>(nblk);
+
+      for (int ps = 0; ps < npass; ++ps) {
+        const WPass P = pass_of<NB, NX, NY>(ps, nblk);
+        __syncthreads();  // the previous pass's flush has read the table
+        for (int e = lane; e < 16 * SB; e += 64) {
+          const int sb = e >> 4;
+          const bool ypart = !P.diag && sb >= NX;
+          const int wb = ypart ? P.y0 + (sb - NX) : P.x0 + sb;
+          const int w = 16 * wb + (e & 15);
+          const bool used = ypart ? sb - NX < P.ny : sb < P.nx;
+          otab[e] = (used && w < nwin) ? out_index(w + base_L, NP, NT) : -1;
+        }
+
+        for (int64_t kk = r0; kk < r1; ++kk) {
+          const int q = a.worder[kk];
+          WPair pr;
+          {
+            const ForestInfo fi = a.finfo[a.sorted[a.pair_p[q]]];
+            const ForestInfo gi = a.finfo[a.sorted[a.nbr[q]]];
+            pair_sc(fi, gi, pr.s, pr.c);
+            pr.pf = fi.pix0;
+            pr.pg = gi.pix0;
+            pr.nf = fi.npix;
+            pr.ng = gi.npix;
+            pr.fdmin = fi.dmin;
+            pr.fdmax = fi.dmax;
+            pr.gdmin = gi.dmin;
+            pr.gdmax = gi.dmax;
+          }
+          // pixels within r_par reach of the other forest's extent: the first and
+          // last such pixel of each forest bound the rows and the lanes' pixels
+          const double reach = a.g.emax_par / pr.c * (1.0 + 1e-12) + 1e-9;
+          int rng[4];
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int n = side ? pr.ng : pr.nf;
+            const int64_t p0 = side ? pr.pg : pr.pf;
+            const double lo_d = (side ? pr.fdmin : pr.gdmin) - reach, hi_d = (side ? pr.fdmax : pr.gdmax) + reach;
+            int first = 0x7fffffff, last = -1;
+            for (int e0 = 0; e0 < n; e0 += 64) {
+              const int e = e0 + lane;
+              bool in = false;
+              if (e < n) {
+                double D;
+                if constexpr (kF32) D = recs[p0 + e].D; else D = recs[p0 + e].d;
+                in = D > lo_d && D < hi_d;
+              }
+              const uint64_t m = __ballot(in);
+              if (m != 0ull) {
+                first = min(first, e0 + __ffsll((long long)m) - 1);
+                last = e0 + 63 - __clzll((long long)m);
+              }
+            }
+            rng[2 * side] = first;
+            rng[2 * side + 1] = last;
+          }
+          const int f_lo = rng[0], f_n = rng[1] + 1 - rng[0];
+          const int g_lo = rng[2], g_n = rng[3] + 1 - rng[2];
+          if (f_n <= 0 || g_n <= 0) continue;  // no pixel pair of these forests is in the grid
+          T cf0, cf1, cg0, cg1;  // c of f and g: (1 / W, 1 / S), 0 where the term is off
+          {
+            const EtaInfo ef = a.einfo[a.sorted[a.pair_p[q]]];
+            const EtaInfo eg = a.einfo[a.sorted[a.nbr[q]]];
+            cf0 = (T)(ef.active ? 1.0 / ef.W : 0.0);
+            cf1 = (T)(ef.slope ? 1.0 / ef.S : 0.0);
+            cg0 = (T)(eg.active ? 1.0 / eg.W : 0.0);
+            cg1 = (T)(eg.slope ? 1.0 / eg.S : 0.0);
+          }
+          const T s = (T)pr.s, c = (T)pr.c;
+          const T bsep = kF32 ? (T)(2.0 * a.glob->dc * pr.s) : (T)0;
+          const bool count_in = a.counters && ps == 0;
+
+          // the two sweeps: rows of f against g's pixels (rs = 0, which also sums
+          // the pair histograms H), then rows of g against f's pixels
+          uint32_t u_h = 0;  // blocks the H partials reach
+#pragma unroll
+          for (int b = 0; b < SB; ++b) h0[b] = h1[b] = (T)0;
+#pragma unroll 1
+          for (int rs = 0; rs < 2; ++rs) {
+            const int nr = rs ? g_n : f_n, no = rs ? f_n : g_n;
+            const int64_t prow0 = rs ? pr.pg + g_lo : pr.pf + f_lo;
+            const int64_t poth0 = rs ? pr.pf + f_lo : pr.pg + g_lo;
+            const T co_l = comp ? (rs ? cf1 : cg1) : (rs ? cf0 : cg0);  // c of the other forest, this lane's l
+            const int nch = (no + CH - 1) / CH;
+            // the other forest's pixels, CH at a time, in registers: lane l holds
+            // pixels c0 + l ppl + k, k < ppl <= PMAX (blocked, so that the 64 pixels
+            // of one k are spread over the forest and mostly fall in different bins)
+            T od[PMAX], ow[PMAX], owa[PMAX];
+            int ppl = 0, cn = 0, cload = -1;
+            auto load_other = [&](int c0) {
+              if (c0 == cload) return;
+              cload = c0;
+              cn = min(CH, no - c0);
+              ppl = (cn + 63) >> 6;
+#pragma unroll
+              for (int k = 0; k < PMAX; ++k) {
+                const int j = lane * ppl + k;
+                od[k] = (T)1e30;  // far away: never in the grid
+                ow[k] = owa[k] = (T)0;
+                if (k < ppl && j < cn) {
+                  const Rec rec = recs[poth0 + c0 + j];
+                  od[k] = rec.d;
+                  ow[k] = rec.w;
+                  owa[k] = rec.w * rec.a;
+                }
+              }
+            };
+            // the rows, RCH at a time, staged in LDS from rbase on (rows past nr as zeros)
+            int rbase = -RCH;
+            auto rows_at = [&](int r) {
+              const int cb = r & ~(RCH - 1);
+              if (cb == rbase) return;
+              rbase = cb;
+              __syncthreads();
+              for (int i = lane; i < RCH; i += 64) {
+                const int rr = cb + i;
+                T d = 0, w = 0, wa = 0;
+                double D = 0.0;
+                if (rr < nr) {
+                  const Rec rec = recs[prow0 + rr];
+                  d = rec.d;
+                  w = rec.w;
+                  wa = rec.w * rec.a;
+                  if constexpr (kF32) D = rec.D; else D = rec.d;
+                }
+                srow[0][i] = d;
+                srow[1][i] = w;
+                srow[2][i] = wa;
+                srowD[i] = D;
+              }
+              __syncthreads();
+            };
+            // bins rows r and r + 1 into buffer bsel (w and w a added at each pair's
+            // storage bin); returns the union of their block masks (uniform).  The
+            // 2 x PMAX evaluations of a chunk are straight-line code with predicates;
+            // the FP64 edge path and the LDS adds are the only branches.
+            auto bin_rows = [&](int r, int bsel) -> uint32_t {
+              uint32_t bits = 0;
+              rows_at(r);
+              const T rdv[2] = {srow[0][r - rbase], srow[0][r + 1 - rbase]};
+              const bool rowok[2] = {true, r + 1 < nr};
+#pragma unroll 1
+              for (int c0 = 0; c0 < no; c0 += CH) {
+                load_other(c0);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                  T* hw = &buf[bsel][2 * h][0];
+#pragma unroll
+                  for (int k = 0; k < PMAX; ++k) {
+                    T rp, rt;
+                    separations(rdv[h], od[k], c, s, bsep, rp, rt);
+                    T xp, xt;
+                    if constexpr (ZLO) {
+                      xp = rp * K.invp;
+                      xt = rt * K.invt;
+                    } else {
+                      xp = (rp - K.e0p) * K.invp;
+                      xt = (rt - K.e0t) * K.invt;
+                    }
+                    const bool inr = rowok[h] & (xp < K.np_hi) & (xt < K.nt_hi) &
+                                     (ZLO || ((xp > K.lo_p) & (xt > K.lo_t)));
+                    const T rxp = rint(xp), rxt = rint(xt);
+                    bool gp = fabs(xp - rxp) < K.taup, gt = fabs(xt - rxt) < K.taut;
+                    if constexpr (ZLO) {
+                      gp &= rxp != (T)0;
+                    } else {
+                      gp &= !(K.zlp & (rxp == (T)0));
+                      gt &= !(K.zlt & (rxt == (T)0));
+                    }
+                    // (clamped before the conversion: out-of-range lanes are discarded below)
+                    int L = (int)__umul24((unsigned)(int)fmin(xt, (T)65536), (unsigned)NP) + (int)fmin(xp, (T)65536);
+                    if (inr & (gp | gt)) {
+                      // within rounding of an edge: the FP64 separations against the edges
+                      double rp64, rt64;
+                      if constexpr (kF32) {
+                        separations64(srowD[r + h - rbase], recs[poth0 + c0 + lane * ppl + k].D, pr.c, pr.s,
+                                      rp64, rt64);
+                      } else {
+                        rp64 = rp;
+                        rt64 = rt;
+                      }
+                      const int kp = bin_exact(rp64, K.ep, NP, (int)floor((double)xp));
+                      const int kt = bin_exact(rt64, K.et, NT, (int)floor((double)xt));
+                      L = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
+                    }
+                    const int w = L - base_L;
+                    const bool ing = inr & (L >= 0);
+                    const bool inw = ing & ((unsigned)w < (unsigned)nwin);
+                    n_lost += (ing & !inw) ? 1ull : 0ull;
+                    if (count_in && rs == 0) n_in += inw ? 1ull : 0ull;
+                    // storage bin of the pass
+                    const int wx = w - 16 * P.x0, wy = w - 16 * P.y0;
+                    const bool okx = (unsigned)wx < (unsigned)(16 * P.nx);
+                    const bool oky = !P.diag & ((unsigned)wy < (unsigned)(16 * P.ny));
+                    const int sidx = okx ? wx : 16 * NX + wy;
+                    const bool ok = inw & (okx | oky);
+                    if (ok) {
+                      atomicAdd(&hw[sidx], ow[k]);
+                      atomicAdd(&hw[SW + sidx], owa[k]);
+                    }
+                    bits |= ok ? (1u << ((sidx >> 4) & 31)) : 0u;
+                  }
+                }
+              }
+              return wave_or(bits);
+            };
+
+            // steps of two rows; the binning of step st + 1 is issued before the
+            // matrix steps of step st, into the other buffer
+            const int nsteps = (nr + 1) >> 1;
+            uint32_t ucur = 0;
+#pragma unroll 1
+            for (int st = -1; st < nsteps; ++st) {
+              T op[SB];
+              T wr = 0, wra = 0;
+              if (st >= 0) {
+                __syncthreads();  // the rows' LDS adds (and the last clears) are complete
+                const int bsel = st & 1;
+                // this lane's row (rows past nr were staged as zeros)
+                wr = srow[1][2 * st + rpar - rbase];
+                wra = srow[2][2 * st + rpar - rbase];
+                // operands: R^l of the lane's row over each block the step reaches;
+                // the slots read are cleared for the next use of this buffer
+#pragma unroll
+                for (int b = 0; b < SB; ++b) {
+                  op[b] = (T)0;
+                  if ((ucur >> b) & 1u) {
+                    T* pp = &buf[bsel][lk][16 * b + lm];
+                    op[b] = *pp;
+                    *pp = (T)0;
+                  }
+                }
+              }
+              const uint32_t unext = st + 1 < nsteps ? bin_rows(2 * st + 2, (st + 1) & 1) : 0u;
+              if (st >= 0) {
+                if (a.counters) {
+                  // outer-product FMAs of the sparse rows: 2 per (x, y) of nonzero R bins,
+                  // counted per row over the x and y ranges
+                  int cx[2] = {0, 0}, cy[2] = {0, 0};
+#pragma unroll
+                  for (int b = 0; b < SB; ++b) {
+                    if (!((ucur >> b) & 1u)) continue;
+                    const uint64_t m = __ballot(op[b] != (T)0);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                      const int nz = __popc((uint32_t)((m >> (32 * h)) | (m >> (32 * h + 16))) & 0xFFFFu);
+                      if (P.diag || b < NX) cx[h] += nz; else cy[h] += nz;
+                    }
+                  }
+#pragma unroll
+                  for (int h = 0; h < 2; ++h)
+                    nalg += 2ull * (unsigned long long)cx[h] * (unsigned long long)(P.diag ? cx[h] : cy[h]);
+                }
+                if (rs == 0) {
+                  u_h |= ucur;
+#pragma unroll
+                  for (int b = 0; b < SB; ++b)
+                    if ((ucur >> b) & 1u) {
+                      h0[b] = fma(wr, op[b], h0[b]);
+                      h1[b] = fma(wra, op[b], h1[b]);
+                    }
+                }
+                const T sq = sqrt(wr * co_l);
+#pragma unroll
+                for (int b = 0; b < SB; ++b) op[b] *= sq;
+                tile_steps(ucur, P.diag, op, op);
+              }
+              ucur = unext;
+            }
+
+          }
+          // ---- the pair term H (x) H, from the f rows' histograms
+          // ---- H: add the two row halves; lane (kl, i) then holds H^kl[16 b + i]
+#pragma unroll
+          for (int b = 0; b < SB; ++b) {
+            if (!((u_h >> b) & 1u)) continue;
+            const T mine = lane < 32 ? h0[b] : h1[b];
+            const T give = lane < 32 ? h1[b] : h0[b];
+            h0[b] = mine + xor32(give);
+          }
+          // H term: A = -c_fk c_gl H^kl (k = lane's row slot, l = its component), B = H^kl
+          const T s4 = -(rpar ? cf1 : cf0) * (comp ? cg1 : cg0);
+#pragma unroll
+          for (int b = 0; b < SB; ++b) h1[b] = h0[b] * s4;
+          // every block of the pass (blocks H does not reach add zeros): the masked
+          // form of these steps came out of the compiler without the H term
+          static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+            constexpr int by = decltype(BY)::value;
+            static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
+              constexpr int bx = decltype(BX)::value;
+              constexpr int j = by * (by + 1) / 2 + bx;
+              constexpr bool in_rect = bx < NX && by >= NX;
+              if (in_rect || P.diag) acc[j] = Form::step(h1[bx], h0[by], acc[j]);
+            });
+          });
+          if (a.counters) {
+            int hx = 0, qy = 0;
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+              if (!((u_h >> b) & 1u)) continue;
+              const uint64_t m0 = __ballot(lk == 0 && h0[b] != (T)0);
+              const uint64_t m3 = __ballot(lk == 3 && h0[b] != (T)0);
+              const int n0 = __popcll(m0), nq = __popc((uint32_t)(m0 | (m3 >> 48)) & 0xFFFFu);
+              if (P.diag || b < NX) hx += n0;
+              if (P.diag || b >= NX) qy += nq;
+            }
+            nalg += 4ull * (unsigned long long)hx * (unsigned long long)qy;
+          }
+          // w_A and the Kronecker term, from H^00 (lanes 0..15)
+          if (P.diag && lk == 0) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              if ((u_h >> b) & 1u) wdacc[16 * b + lm] += (double)h0[b];
+          }
+        }
+
+        // ---- add the tile (num gets -tile) and w_A to the global sums.  The
+        // blocks go through an LDS stage GB at a time, so the atomics are one
+        // loop; off-diagonal blocks (bx < by, every block of a rectangle pass)
+        // also go to (y, x).
+        static_for<0, (MB + GB - 1) / GB>([&](auto G) __attribute__((always_inline)) {
+          constexpr int g = decltype(G)::value;
+          __syncthreads();  // the previous group's stage has been read
+          static_for<0, GB>([&](auto I) __attribute__((always_inline)) {
+            constexpr int jj = g * GB + decltype(I)::value;
+            if constexpr (jj < MB) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) stg[(decltype(I)::value * 16 + Form::row(lk, r)) * 16 + lm] = acc[jj][r];
+              acc[jj] = Acc{0, 0, 0, 0};
+            }
+          });
+          __syncthreads();
+          for (int e = lane; e < GB * 256; e += 64) {
+            const int jj = g * GB + (e >> 8);
+            if (jj >= MB) break;
+            const double v = -(double)stg[e];
+            const int by = slot_by[jj], bx = jj - by * (by + 1) / 2;
+            const int ox = otab[16 * bx + ((e >> 4) & 15)], oy = otab[16 * by + (e & 15)];
+            if (v != 0.0 && ox >= 0 && oy >= 0) {
+              atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
+              if (bx != by) atomicAdd(&a.dnum[(obase + oy) * nb + ox], v);
+            }
+          }
+        });
+        if (P.diag) {
+          for (int x = lane; x < 16 * P.nx; x += 64) {
+            const double v = wdacc[x];
+            const int ox = otab[x];
+            if (v != 0.0 && ox >= 0) {
+              atomicAdd(&a.wd[obase + ox], v);
+              atomicAdd(&a.dnum[(obase + ox) * nb + ox], v);
+            }
+            wdacc[x] = 0.0;
+          }
+        }
+      }
+      r0 = r1;
+    }
+  }
+  if (a.counters) {
+    unsigned long long ni = n_in, nl = n_lost;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ni += __shfl_xor(ni, o, 64);
+      nl += __shfl_xor(nl, o, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&a.counters[0], ni);
+      atomicAdd(&a.counters[1], nalg);
+      atomicAdd(&a.counters[2], nl);
+    }
+  }
+}
+
+template <typename T, int NB, int PMAX, int WPE>
+hipError_t launch_wave(const DmatArgs& a, int blocks, hipStream_t st) {
+  if (a.g.zero_lo_par && a.g.zero_lo_perp)
+    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, true>), dim3(blocks), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, false>), dim3(blocks), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int NB, int PMAX, int WPE>
+int wave_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_wave_kernel<T, NB, PMAX, WPE, true>, 64, 0) != hipSuccess)
+    return 4;
+  return n > 0 ? n : 1;
+}
+
+// tile shapes (blocks per side) of the two variants per form: the larger tile
+// runs one wave per SIMD with its accumulators in AGPRs (FP32: 160-bin
+// windows, three k_perp rows of 50 bins, in one pass), the smaller two waves
+// per SIMD with VGPR accumulators; both are the largest that compile without
+// register spills
+constexpr int kNB32[2] = {10, 8};
+constexpr int kNB64[2] = {7, 5};
+constexpr int kPMax = 4;    // FP32: 256 pixels of the other forest in registers at a time
+constexpr int kPMax64 = 3;  // FP64: 192
+
+}  // namespace
+
+int dmat_wave_num_variants() { return 2; }
+
+const char* dmat_wave_variant_name(int v) {
+  static const char* const names[2] = {"w64-sym-big", "w64-sym-small"};
+  return (v >= 0 && v < 2) ? names[v] : "?";
+}
+
+hipError_t launch_dmat_wave(int v, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
+  if (a.n_items == 0) return hipSuccess;
+  if (precision == LYA_FP64)
+    return v == 0 ? launch_wave<double, kNB64[0], kPMax64, 1>(a, blocks, st)
+                  : launch_wave<double, kNB64[1], kPMax64, 2>(a, blocks, st);
+  return v == 0 ? launch_wave<float, kNB32[0], kPMax, 1>(a, blocks, st) : launch_wave<float, kNB32[1], kPMax, 2>(a, blocks, st);
+}
+
+int dmat_wave_blocks_per_cu(int v, int precision) {
+  if (precision == LYA_FP64)
+    return v == 0 ? wave_occupancy<double, kNB64[0], kPMax64, 1>() : wave_occupancy<double, kNB64[1], kPMax64, 2>();
+  return v == 0 ? wave_occupancy<float, kNB32[0], kPMax, 1>() : wave_occupancy<float, kNB32[1], kPMax, 2>();
+}
+
+}  // namespace lya

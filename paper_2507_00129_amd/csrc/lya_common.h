@@ -288,6 +288,11 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in, int32_t* v_out,
                             int64_t n, void* tmp, size_t bytes, hipStream_t st);
 size_t sort_keys_bytes(int64_t n);
+// the single-wave symmetric-tile D kernel (two tile shapes per form)
+int dmat_wave_num_variants();
+const char* dmat_wave_variant_name(int v);
+hipError_t launch_dmat_wave(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
+int dmat_wave_blocks_per_cu(int variant, int precision);
 int dmat_num_variants();
 const char* dmat_variant_name(int v);
 hipError_t launch_dmat(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);

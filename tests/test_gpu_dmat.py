@@ -16,6 +16,9 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 G60 = uniform_grid(15, 60.0)
+# kernel variants: 0 the 8-wave kernel with a full tile; 1 and 2 the
+# single-wave kernel with the upper-triangle tile (large and small tile)
+VARIANTS = [0, 1, 2]
 ETA = {"identity": O.IDENTITY, "mean": O.MEAN, "mean_slope": O.MEAN_SLOPE}
 
 
@@ -47,17 +50,18 @@ def check(out, ref, prec, what):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("eta", ["mean", "mean_slope"])
-def test_tiny_against_four_nested_sums(lib, prec, eta):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_tiny_against_four_nested_sums(lib, prec, eta, variant):
     F = tiny(0, n_forests=3, k=6)
     G = uniform_grid(4, 24.0, 3, 30.0)
     pairs = O.dmat_pairs(F, G)
     ref = O.dmat_brute(F, G, pairs, ETA[eta])
-    out = run_dmat(lib, F, G, precision=prec, eta=eta)
-    check(out, ref, prec, f"tiny-{eta}")
+    out = run_dmat(lib, F, G, precision=prec, eta=eta, variant=variant, autotune=False)
+    check(out, ref, prec, f"tiny-{eta}-v{variant}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0])
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_config0(lib, prec, variant):
     F, G, _ = make_config(0, seed=0)
     ref = O.dmat(F, G, O.dmat_pairs(F, G))
@@ -66,9 +70,10 @@ def test_config0(lib, prec, variant):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_identity_eta_gives_identity(lib, prec):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_identity_eta_gives_identity(lib, prec, variant):
     F, G, _ = make_config(0, seed=1, scale=0.5)
-    out = run_dmat(lib, F, G, precision=prec, eta="identity")
+    out = run_dmat(lib, F, G, precision=prec, eta="identity", variant=variant, autotune=False)
     D, wd = out["dmat"][0], out["wsum_d"][0]
     rows = wd > 0
     assert rows.sum() > 50
@@ -80,7 +85,8 @@ def test_identity_eta_gives_identity(lib, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("eta", ["mean", "mean_slope"])
-def test_covering_grid_row_sums(lib, prec, eta):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_covering_grid_row_sums(lib, prec, eta, variant):
     """A uniform grid holding every pair of these compact forests (r < 400
     Mpc/h): the eta rows sum to zero, so every row of D does too."""
     F = tiny(4, n_forests=6, k=40)
@@ -88,7 +94,7 @@ def test_covering_grid_row_sums(lib, prec, eta):
     ref = O.xi_sums(F, G)
     n = np.diff(F.offsets)
     assert ref.npairs.sum() == (n.sum() ** 2 - np.sum(n ** 2)) // 2
-    out = run_dmat(lib, F, G, precision=prec, eta=eta)
+    out = run_dmat(lib, F, G, precision=prec, eta=eta, variant=variant, autotune=False)
     D = out["dmat"][0]
     assert np.abs(D).max() > 0.1
     assert np.abs(D.sum(1)).max() <= (1e-10 if prec == "fp64" else 1e-5)
@@ -109,19 +115,20 @@ def test_keep_fraction_subset(lib, prec):
 def test_ragged(lib, prec):
     F = _ragged_forests(7)
     ref = O.dmat(F, G60, O.dmat_pairs(F, G60))
-    for v in (0,):
+    for v in VARIANTS:
         out = run_dmat(lib, F, G60, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"ragged-v{v}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_realisations(lib, prec):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_realisations(lib, prec, variant):
     parts = [make_patch(n, 2.0, 60 + r) for r, n in enumerate((20, 33, 27))]
     F = concat_realisations(parts)
     ref = O.dmat(F, G60, O.dmat_pairs(F, G60))
-    out = run_dmat(lib, F, G60, precision=prec)
+    out = run_dmat(lib, F, G60, precision=prec, variant=variant, autotune=False)
     assert out["dmat"].shape == (3, G60.n_bins, G60.n_bins)
-    check(out, ref, prec, "realisations")
+    check(out, ref, prec, f"realisations-v{variant}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -131,7 +138,7 @@ def test_config1_compact_subpatch(lib, prec):
     F, G, _ = make_config(1, seed=0, scale=0.02)
     S = subset_forests(F, nearest_to_centre(F, 60))
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
-    for v in (0,):
+    for v in VARIANTS:
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"config1-sub-v{v}")
 
@@ -140,30 +147,34 @@ def test_config1_compact_subpatch(lib, prec):
 @pytest.mark.parametrize("n_par", [100, 120])
 def test_windows_wider_than_one_tile(lib, prec, n_par):
     """n_par r_par bins of 2 Mpc/h make every r_perp window n_par, 2 n_par or
-    3 n_par bins wide; windows wider than a tile (160 bins in the FP64 form,
-    224 in the FP32 form) are covered by several tiles and passes per run."""
+    3 n_par bins wide; windows wider than a tile (variant 0: 160 bins in the
+    FP64 form, 224 in the FP32 form; variants 1 and 2: 112 and 80 (FP64), 160
+    and 128 (FP32)) are covered by several tiles and passes per run, diagonal
+    and rectangle passes in variants 1 and 2."""
     F, _, _ = make_config(1, seed=3, scale=0.02)
     S = subset_forests(F, nearest_to_centre(F, 40))
     G = uniform_grid(n_par, 2.0 * n_par, 12, 60.0)
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
-    for v in (0,):
+    for v in VARIANTS:
         out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
         check(out, ref, prec, f"wide-windows-v{v}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_config0_against_definition(lib, prec):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_config0_against_definition(lib, prec, variant):
     """Config 0 against eq. distortion with each forest pair's inner double sum
     formed as eta_f M^B eta_g^T (oracle.dmat_definition): no factorisation in
     common with the kernels."""
     F, G, _ = make_config(0, seed=0)
     ref = O.dmat_definition(F, G, O.dmat_pairs(F, G))
-    out = run_dmat(lib, F, G, precision=prec)
-    check(out, ref, prec, "config0-definition")
+    out = run_dmat(lib, F, G, precision=prec, variant=variant, autotune=False)
+    check(out, ref, prec, f"config0-definition-v{variant}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_realisations_against_definition(lib, prec):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_realisations_against_definition(lib, prec, variant):
     """Three realisations of short forests (a few hundred pixels each, many
     touched bins per forest pair) against the definition form."""
     parts = [truncate(make_patch(n, 1.0, 90 + r, z_range=(2.1, 2.4)), 40) for r, n in enumerate((9, 14, 11))]
@@ -171,19 +182,20 @@ def test_realisations_against_definition(lib, prec):
     G = uniform_grid(12, 60.0, 10, 40.0)
     ref = O.dmat_definition(F, G, O.dmat_pairs(F, G))
     assert (ref.wd > 0).sum() > 100
-    out = run_dmat(lib, F, G, precision=prec)
-    check(out, ref, prec, "realisations-definition")
+    out = run_dmat(lib, F, G, precision=prec, variant=variant, autotune=False)
+    check(out, ref, prec, f"realisations-definition-v{variant}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_config1_subpatch_120(lib, prec):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_config1_subpatch_120(lib, prec, variant):
     """The 120 forests nearest the centre of an eBOSS-like patch on the 50x50
     grid to 200 Mpc/h (7e3 forest pairs, long runs of pairs per tile)."""
     F, G, _ = make_config(1, seed=0, scale=0.02)
     S = subset_forests(F, nearest_to_centre(F, 120))
     ref = O.dmat(S, G, O.dmat_pairs(S, G))
-    out = run_dmat(lib, S, G, precision=prec)
-    check(out, ref, prec, "config1-sub120")
+    out = run_dmat(lib, S, G, precision=prec, variant=variant, autotune=False)
+    check(out, ref, prec, f"config1-sub120-v{variant}")
 
 
 def test_full_config1_fp32_vs_fp64(lib):
