@@ -356,6 +356,21 @@ lya_status lya_xi_backward(lya_context *ctx, const lya_forests *forests, const l
                            const double *grad_xi, const double *xi, const double *wsum,
                            double *grad_delta, double *grad_weight);
 
+/* Measured peak rates of the context's GPU, the denominators of the pair
+   kernels' roofline fractions: out[8] (HOST) gets lane-operations per second
+   over the whole chip from microbenchmark kernels (many waves per SIMD, long
+   runs of independent operations, timed with events on `stream`):
+     out[0] FP32 VALU fused multiply-add (non-packed)
+     out[1] FP64 VALU fused multiply-add
+     out[2] LDS atomic add, FP32 (64 lanes on 64 consecutive words)
+     out[3] LDS atomic add, FP64 (64 consecutive doubles)
+     out[4] LDS atomic add, u32 (64 consecutive words)
+     out[5] LDS atomic add, FP32, four lanes on each address
+     out[6] LDS store, 32 bits (64 consecutive words)
+     out[7] 0
+   Takes a few hundred milliseconds and synchronises the stream. */
+lya_status lya_measure_peaks(lya_context *ctx, void *stream, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "liblya.so")
 SOURCES = ["lya_runtime.hip", "k_precompute.hip", "k_worklist.hip", "k_xi.hip", "k_cov.hip",
-           "k_dmat.hip", "k_dmat_wave.hip", "k_backward.hip", "k_xi3.hip"]
+           "k_dmat.hip", "k_dmat_wave.hip", "k_backward.hip", "k_xi3.hip", "k_peaks.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("LYA_OFFLOAD_ARCH", "gfx950")

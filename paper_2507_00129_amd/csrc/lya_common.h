@@ -288,6 +288,13 @@ hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hip
 hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in, int32_t* v_out,
                             int64_t n, void* tmp, size_t bytes, hipStream_t st);
 size_t sort_keys_bytes(int64_t n);
+// microbenchmarks of the LDS atomic / store and VALU FMA rates (k_peaks.hip)
+hipError_t launch_lds_rate(int kind, int blocks, int iters, unsigned long long* sink, hipStream_t st);
+hipError_t launch_valu_rate(int fp64, int blocks, int iters, void* out, hipStream_t st);
+int peak_block();
+int peak_unroll_lds();
+int peak_unroll_valu();
+
 // the single-wave symmetric-tile D kernel (two tile shapes per form)
 int dmat_wave_num_variants();
 const char* dmat_wave_variant_name(int v);

@@ -723,6 +723,40 @@ lya_status lya_xi_noalloc(lya_context* ctx, const lya_forests* F, const lya_grid
   return s;
 }
 
+lya_status lya_measure_peaks(lya_context* ctx, void* stream, double* out) {
+  if (!ctx) return LYA_E_INVALID;
+  if (!out) return fail(ctx, LYA_E_INVALID, "NULL output");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ctx->err.clear();
+  unsigned long long* sink;
+  float* vout;
+  LYA_TRY(wst(ctx, "peak_sink", 1, &sink));
+  LYA_TRY(wst(ctx, "peak_out", (size_t)2 * peak_block(), &vout));
+  const int blocks = 8 * ctx->n_cu;  // 32 waves per CU
+  const double lanes = (double)blocks * peak_block();
+  // (kind, iterations, operations per lane and iteration): FP32 FMA, FP64 FMA,
+  // then the LDS kinds of k_peaks.hip
+  struct Run { int valu, kind, iters; };
+  const Run runs[7] = {{1, 0, 40000}, {1, 1, 20000}, {0, 0, 20000}, {0, 1, 20000},
+                       {0, 2, 20000}, {0, 3, 5000},  {0, 4, 20000}};
+  for (int r = 0; r < 8; ++r) out[r] = 0.0;
+  for (int r = 0; r < 7; ++r) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up
+      HIP_TRY(hipEventRecord(ctx->ev[6], st));
+      if (runs[r].valu) HIP_TRY(launch_valu_rate(runs[r].kind, blocks, runs[r].iters, vout, st));
+      else HIP_TRY(launch_lds_rate(runs[r].kind, blocks, runs[r].iters, sink, st));
+      HIP_TRY(hipEventRecord(ctx->ev[7], st));
+      HIP_TRY(hipEventSynchronize(ctx->ev[7]));
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[6], ctx->ev[7]));
+    }
+    const double per_lane = (double)runs[r].iters * (runs[r].valu ? peak_unroll_valu() : peak_unroll_lds());
+    out[r] = ms > 0.f ? lanes * per_lane / (ms * 1e-3) : 0.0;
+  }
+  return LYA_OK;
+}
+
 lya_status lya_xi_means(lya_context* ctx, const lya_forests* F, const lya_grid* G, const lya_options* o,
                         void* stream, double* num, double* wsum, int64_t* npairs, double* xi,
                         double* rpar, double* rperp, double* z) {

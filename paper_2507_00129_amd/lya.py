@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.lya_xi_means.restype = I32
     lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
     lib.lya_xi_covariance.restype = I32
+    lib.lya_measure_peaks.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.lya_measure_peaks.restype = I32
     _lib = lib
     return lib
 
@@ -377,6 +379,15 @@ class Library:
         self._check(self.lib.lya_xi_covariance(self.ctx, _ptr(num), _ptr(wsum), n_sub, nb, self._stream(stream),
                                                _ptr(xi), _ptr(cov)))
         return xi, cov
+
+    PEAK_KEYS = ("valu_fma_f32", "valu_fma_f64", "lds_add_f32", "lds_add_f64", "lds_add_u32",
+                 "lds_add_f32_4per_address", "lds_store_b32")
+
+    def measure_peaks(self, stream=None) -> dict:
+        """Measured whole-chip lane-operations per second (lya_measure_peaks)."""
+        buf = (ctypes.c_double * 8)()
+        self._check(self.lib.lya_measure_peaks(self.ctx, self._stream(stream), buf))
+        return {k: float(buf[i]) for i, k in enumerate(self.PEAK_KEYS)}
 
     def dmat(self, forests: DeviceForests, grid, stream=None, out=None, **opts):
         """Distortion matrix; returns dict(dmat [R, nb, nb], wsum_d [R, nb])."""

@@ -48,6 +48,7 @@ def test_defaults_and_null_arguments():
     assert o.dmat_keep_fraction == 1.0 and o.variant == -1
     assert lib.lya_xi(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_noalloc(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
+    assert lib.lya_measure_peaks(None, None, None) == L.LYA_E_INVALID
     assert lib.lya_dmat(None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_backward(None, None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
