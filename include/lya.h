@@ -356,8 +356,13 @@ lya_status lya_xi_backward(lya_context *ctx, const lya_forests *forests, const l
                            const double *grad_xi, const double *xi, const double *wsum,
                            double *grad_delta, double *grad_weight);
 
+/* Short name of a main-kernel variant (the index lya_stats.variant reports):
+   kernel 0 = the xi pair kernel, 1 = the distortion-matrix kernel.  Returns a
+   static string, or NULL for an index out of range. */
+const char *lya_variant_name(int32_t kernel, int32_t variant);
+
 /* Measured peak rates of the context's GPU, the denominators of the pair
-   kernels' roofline fractions: out[8] (HOST) gets lane-operations per second
+   kernels' roofline fractions: out[LYA_N_PEAKS] (HOST) gets lane-operations per second
    over the whole chip from microbenchmark kernels (many waves per SIMD, long
    runs of independent operations, timed with events on `stream`):
      out[0] FP32 VALU fused multiply-add (non-packed)
@@ -367,8 +372,10 @@ lya_status lya_xi_backward(lya_context *ctx, const lya_forests *forests, const l
      out[4] LDS atomic add, u32 (64 consecutive words)
      out[5] LDS atomic add, FP32, four lanes on each address
      out[6] LDS store, 32 bits (64 consecutive words)
-     out[7] 0
+     out[7] FP32 VALU add
+     out[8] u32 VALU add
    Takes a few hundred milliseconds and synchronises the stream. */
+#define LYA_N_PEAKS 9
 lya_status lya_measure_peaks(lya_context *ctx, void *stream, double *out);
 
 #ifdef __cplusplus

@@ -1,6 +1,7 @@
 // Microbenchmarks of the rates the pair kernels are bound by: LDS atomic adds
 // (FP32, FP64, u32; conflict-free and with four lanes per address), plain LDS
-// stores, and non-packed FP32 / FP64 VALU fused multiply-adds.  Each kernel
+// stores, non-packed FP32 / FP64 VALU fused multiply-adds, and plain FP32 and
+// u32 VALU additions.  Each kernel
 // issues long runs of independent operations from many waves per SIMD; the
 // host divides the lane-operations by the event-timed kernel duration.
 #include "lya_common.h"
@@ -57,6 +58,36 @@ __global__ __launch_bounds__(kPeakBlock) void valu_rate_kernel(T* out, int iters
   if (s == (T)-12345) out[threadIdx.x] = s;  // never true: keeps the chains alive
 }
 
+// The same eight chains of one plain instruction, written in assembly so that
+// the compiler can neither fold a chain of additions nor pick another opcode:
+// OP 0 = v_add_f32, OP 1 = v_add_u32.
+template <int OP>
+__global__ __launch_bounds__(kPeakBlock) void valu_add_rate_kernel(float* out, int iters, float x) {
+  float f[8];
+  unsigned u[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f[k] = x + (float)(threadIdx.x + k);
+    u[k] = threadIdx.x + k;
+  }
+  const float cf = 1.0e-7f;
+  const unsigned cu = 3u;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if constexpr (OP == 0) asm volatile("v_add_f32 %0, %0, %1" : "+v"(f[k]) : "v"(cf));
+        else asm volatile("v_add_u32 %0, %0, %1" : "+v"(u[k]) : "v"(cu));
+      }
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += f[k] + (float)u[k];
+  if (s == -12345.f) out[threadIdx.x] = s;  // never true
+}
+
 }  // namespace
 
 hipError_t launch_lds_rate(int kind, int blocks, int iters, unsigned long long* sink, hipStream_t st) {
@@ -73,11 +104,14 @@ hipError_t launch_lds_rate(int kind, int blocks, int iters, unsigned long long* 
   return hipGetLastError();
 }
 
-hipError_t launch_valu_rate(int fp64, int blocks, int iters, void* out, hipStream_t st) {
-  if (fp64)
-    hipLaunchKernelGGL(valu_rate_kernel<double>, dim3(blocks), dim3(kPeakBlock), 0, st, (double*)out, iters, 1.0);
-  else
-    hipLaunchKernelGGL(valu_rate_kernel<float>, dim3(blocks), dim3(kPeakBlock), 0, st, (float*)out, iters, 1.0f);
+hipError_t launch_valu_rate(int kind, int blocks, int iters, void* out, hipStream_t st) {
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(valu_rate_kernel<float>, dim3(blocks), dim3(kPeakBlock), 0, st, (float*)out, iters, 1.0f); break;
+    case 1: hipLaunchKernelGGL(valu_rate_kernel<double>, dim3(blocks), dim3(kPeakBlock), 0, st, (double*)out, iters, 1.0); break;
+    case 2: hipLaunchKernelGGL(valu_add_rate_kernel<0>, dim3(blocks), dim3(kPeakBlock), 0, st, (float*)out, iters, 1.0f); break;
+    case 3: hipLaunchKernelGGL(valu_add_rate_kernel<1>, dim3(blocks), dim3(kPeakBlock), 0, st, (float*)out, iters, 1.0f); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

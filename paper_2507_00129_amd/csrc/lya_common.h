@@ -290,7 +290,7 @@ hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in
 size_t sort_keys_bytes(int64_t n);
 // microbenchmarks of the LDS atomic / store and VALU FMA rates (k_peaks.hip)
 hipError_t launch_lds_rate(int kind, int blocks, int iters, unsigned long long* sink, hipStream_t st);
-hipError_t launch_valu_rate(int fp64, int blocks, int iters, void* out, hipStream_t st);
+hipError_t launch_valu_rate(int kind, int blocks, int iters, void* out, hipStream_t st);  // 0 FP32 FMA, 1 FP64 FMA, 2 FP32 add, 3 u32 add
 int peak_block();
 int peak_unroll_lds();
 int peak_unroll_valu();

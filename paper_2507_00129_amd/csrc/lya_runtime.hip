@@ -723,6 +723,12 @@ lya_status lya_xi_noalloc(lya_context* ctx, const lya_forests* F, const lya_grid
   return s;
 }
 
+const char* lya_variant_name(int32_t kernel, int32_t variant) {
+  if (kernel == 0) return (variant >= 0 && variant < xi_num_variants()) ? xi_variant_name(variant) : nullptr;
+  if (kernel == 1) return (variant >= 0 && variant < dmat_num_variants()) ? dmat_variant_name(variant) : nullptr;
+  return nullptr;
+}
+
 lya_status lya_measure_peaks(lya_context* ctx, void* stream, double* out) {
   if (!ctx) return LYA_E_INVALID;
   if (!out) return fail(ctx, LYA_E_INVALID, "NULL output");
@@ -735,13 +741,12 @@ lya_status lya_measure_peaks(lya_context* ctx, void* stream, double* out) {
   LYA_TRY(wst(ctx, "peak_out", (size_t)2 * peak_block(), &vout));
   const int blocks = 8 * ctx->n_cu;  // 32 waves per CU
   const double lanes = (double)blocks * peak_block();
-  // (kind, iterations, operations per lane and iteration): FP32 FMA, FP64 FMA,
-  // then the LDS kinds of k_peaks.hip
+  // (VALU or LDS, kind, iterations): FP32 FMA, FP64 FMA, the LDS kinds of
+  // k_peaks.hip, then FP32 and u32 additions
   struct Run { int valu, kind, iters; };
-  const Run runs[7] = {{1, 0, 40000}, {1, 1, 20000}, {0, 0, 20000}, {0, 1, 20000},
-                       {0, 2, 20000}, {0, 3, 5000},  {0, 4, 20000}};
-  for (int r = 0; r < 8; ++r) out[r] = 0.0;
-  for (int r = 0; r < 7; ++r) {
+  const Run runs[LYA_N_PEAKS] = {{1, 0, 40000}, {1, 1, 20000}, {0, 0, 20000}, {0, 1, 20000}, {0, 2, 20000},
+                                 {0, 3, 5000},  {0, 4, 20000}, {1, 2, 40000}, {1, 3, 40000}};
+  for (int r = 0; r < LYA_N_PEAKS; ++r) {
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up
       HIP_TRY(hipEventRecord(ctx->ev[6], st));

@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.lya_xi_means.restype = I32
     lib.lya_xi_covariance.argtypes = [P, P, P, I64, I64, P, P, P]
     lib.lya_xi_covariance.restype = I32
+    lib.lya_variant_name.argtypes = [I32, I32]
+    lib.lya_variant_name.restype = ctypes.c_char_p
     lib.lya_measure_peaks.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
     lib.lya_measure_peaks.restype = I32
     _lib = lib
@@ -381,11 +383,18 @@ class Library:
         return xi, cov
 
     PEAK_KEYS = ("valu_fma_f32", "valu_fma_f64", "lds_add_f32", "lds_add_f64", "lds_add_u32",
-                 "lds_add_f32_4per_address", "lds_store_b32")
+                 "lds_add_f32_4per_address", "lds_store_b32", "valu_add_f32", "valu_add_u32")
+
+    def variant_name(self, kernel: str, variant: int) -> str:
+        """Name of a main-kernel variant; kernel is "xi" or "dmat"."""
+        n = self.lib.lya_variant_name({"xi": 0, "dmat": 1}[kernel], int(variant))
+        if n is None:
+            raise ValueError(f"no {kernel} variant {variant}")
+        return n.decode()
 
     def measure_peaks(self, stream=None) -> dict:
         """Measured whole-chip lane-operations per second (lya_measure_peaks)."""
-        buf = (ctypes.c_double * 8)()
+        buf = (ctypes.c_double * len(self.PEAK_KEYS))()
         self._check(self.lib.lya_measure_peaks(self.ctx, self._stream(stream), buf))
         return {k: float(buf[i]) for i, k in enumerate(self.PEAK_KEYS)}
 

@@ -57,5 +57,8 @@ def test_defaults_and_null_arguments():
     assert lib.lya_xi3(None, None, None, None, None, None, None, None, None) == L.LYA_E_INVALID
     assert lib.lya_xi3_subsamples(None, None, None, None, None, None, 1, None, None, None, None) == L.LYA_E_INVALID
     assert o.counters == 0 and o.deterministic == 0
+    assert lib.lya_variant_name(0, 0) and lib.lya_variant_name(1, 0)
+    assert lib.lya_variant_name(0, -1) is None and lib.lya_variant_name(1, 99) is None
+    assert lib.lya_variant_name(2, 0) is None
     assert lib.lya_create(None, 0) == L.LYA_E_INVALID
     assert lib.lya_last_error(None) == b"NULL context"
