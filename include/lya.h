@@ -103,9 +103,11 @@ typedef struct {
   int32_t n_realisations;     /* >= 1; outputs are stacked per realisation */
 } lya_forests;
 
-/* Bin edges (HOST pointers), strictly increasing, finite, edges[0] >= 0.
-   This build requires uniformly spaced edges on each axis (to 1e-9 of a
-   bin); other grids return LYA_E_UNSUPPORTED.  n_par * n_perp <= 4096. */
+/* Bin edges (HOST pointers), strictly increasing, finite, edges[0] >= 0;
+   bins are half-open, [e_k, e_k+1) (Sec. 2.1).  Edges uniformly spaced on both
+   axes (to 1e-9 of a bin) are binned from floor((r - e_0) / dr) with an FP64
+   edge guard; any other edges are binned by searching the FP64 edge arrays
+   for every pair in range (same results, slower).  n_par * n_perp <= 4096. */
 typedef struct {
   int32_t n_par;
   int32_t n_perp;
@@ -154,7 +156,7 @@ typedef struct {
 typedef struct {
   int64_t forest_pairs;       /* unordered forest pairs in the work list */
   int64_t work_items;         /* persistent-kernel work items */
-  int64_t candidate_pairs;    /* pixel pairs evaluated (sum n_f n_g over the list) */
+  int64_t candidate_pairs;    /* pixel pairs of the listed forest pairs (sum n_f n_g) */
   int32_t variant;            /* kernel variant index used for the main kernel */
   int32_t grid_blocks;        /* persistent workgroups launched */
   /* device milliseconds per stage, filled when options.timing != 0 */

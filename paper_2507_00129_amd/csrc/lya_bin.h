@@ -1,5 +1,8 @@
 // Pair binning shared by the xi, distortion and backward kernels.
 //
+// On a grid with non-uniform edges the coordinates below use the mean bin width
+// and every pair in range takes the FP64 edge-array path (GridDev::exact_all).
+//
 // A pair's bin coordinates are x = (r - e0) / dr on each axis.  In FP32 the
 // separations carry a bounded rounding error (tau bins, computed per call from
 // the data, see globals_kernel); a pair whose coordinate lies within tau of an
@@ -41,6 +44,12 @@ struct BinK {
     } else {
       taup = 1e-8;
       taut = 1e-8;
+    }
+    if (g.exact_all) {
+      // non-uniform edges: a guard half width of a whole (mean) bin sends every
+      // pair in range to the FP64 search of the edge arrays
+      taup = (T)1;
+      taut = (T)1;
     }
     np_hi = (T)NP + taup;
     nt_hi = (T)NT + taut;

@@ -69,6 +69,10 @@ struct GridDev {
   double inv_par, inv_perp;     // 1 / bin width
   double emax_par, emax_perp;   // last edges
   int32_t zero_lo_par, zero_lo_perp;  // first edge is exactly 0
+  // 0: uniformly spaced edges on both axes (bin = floor of the coordinate,
+  // edge guard only near integers); 1: other edges -- the coordinates use the
+  // mean bin width and every pair is binned by searching the FP64 edge arrays
+  int32_t exact_all;
 };
 
 // Validation error bits (Globals::flag).
@@ -102,14 +106,31 @@ __device__ __forceinline__ bool pair_may_bin(const ForestInfo& a, const ForestIn
   return rperp_min < eperp_max && rpar_min < epar_max;
 }
 
-// Exact bin of r against FP64 edges[0..n]; k0 is a guess within a few bins.
-// Returns -1 outside [edges[0], edges[n]).
+// Exact bin of r against FP64 edges[0..n]: the k with edges[k] <= r <
+// edges[k + 1], or -1 outside [edges[0], edges[n]).  k0 is a guess: on a
+// uniform grid it is right or one bin off; otherwise the remaining range is
+// bisected.
 __device__ __forceinline__ int bin_exact(double r, const double* __restrict__ edges, int n, int k0) {
   if (!(r >= edges[0]) || !(r < edges[n])) return -1;
-  int k = k0 < 0 ? 0 : (k0 > n - 1 ? n - 1 : k0);
-  while (r < edges[k]) --k;
-  while (r >= edges[k + 1]) ++k;
-  return k;
+  const int k = k0 < 0 ? 0 : (k0 > n - 1 ? n - 1 : k0);
+  int lo, hi;  // invariant: edges[lo] <= r < edges[hi]
+  if (r < edges[k]) {  // k >= 1 here, since r >= edges[0]
+    if (r >= edges[k - 1]) return k - 1;
+    lo = 0;
+    hi = k - 1;
+  } else if (r >= edges[k + 1]) {  // k + 1 < n here, since r < edges[n]
+    if (r < edges[k + 2]) return k + 1;
+    lo = k + 2;
+    hi = n;
+  } else {
+    return k;
+  }
+  while (hi - lo > 1) {
+    const int m = (lo + hi) >> 1;
+    if (r < edges[m]) hi = m;
+    else lo = m;
+  }
+  return lo;
 }
 
 // SplitMix64 output function (Steele, Lea & Flood 2014): mix(x + golden gamma).

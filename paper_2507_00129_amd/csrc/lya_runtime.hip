@@ -155,7 +155,7 @@ lya_status wst(lya_context* ctx, const char* name, size_t count, T** out) {
 }
 
 lya_status check_axis(lya_context* ctx, const double* e, int n, const char* axis, double& e0,
-                      double& inv, double& emax) {
+                      double& inv, double& emax, bool& uniform) {
   if (!e) return fail(ctx, LYA_E_INVALID, "edges_%s is NULL", axis);
   if (n < 1) return fail(ctx, LYA_E_INVALID, "n_%s = %d must be >= 1", axis, n);
   for (int k = 0; k <= n; ++k)
@@ -164,10 +164,12 @@ lya_status check_axis(lya_context* ctx, const double* e, int n, const char* axis
   for (int k = 0; k < n; ++k)
     if (!(e[k + 1] > e[k]))
       return fail(ctx, LYA_E_INVALID, "edges_%s not strictly increasing at %d", axis, k);
+  // uniform to 1e-9 of a bin: binned from floor(x) with the edge guard;
+  // otherwise every pair searches the edge array (GridDev::exact_all)
   const double d = (e[n] - e[0]) / n;
+  uniform = true;
   for (int k = 0; k <= n; ++k)
-    if (fabs(e[k] - (e[0] + k * d)) > 1e-9 * d)
-      return fail(ctx, LYA_E_UNSUPPORTED, "edges_%s are not uniformly spaced (edge %d); this build bins uniform grids only", axis, k);
+    if (fabs(e[k] - (e[0] + k * d)) > 1e-9 * d) uniform = false;
   e0 = e[0];
   inv = 1.0 / d;
   emax = e[n];
@@ -197,8 +199,9 @@ lya_status check_common(lya_context* ctx, const lya_forests* F, const lya_grid* 
     return fail(ctx, LYA_E_UNSUPPORTED, "n_par * n_perp = %lld exceeds %d bins",
                 (long long)G->n_par * G->n_perp, kMaxBins);
   double e0p, ip, ep, e0t, it, et;
-  LYA_TRY(check_axis(ctx, G->edges_par, G->n_par, "par", e0p, ip, ep));
-  LYA_TRY(check_axis(ctx, G->edges_perp, G->n_perp, "perp", e0t, it, et));
+  bool up, ut;
+  LYA_TRY(check_axis(ctx, G->edges_par, G->n_par, "par", e0p, ip, ep, up));
+  LYA_TRY(check_axis(ctx, G->edges_perp, G->n_perp, "perp", e0t, it, et, ut));
   gd.n_par = G->n_par;
   gd.n_perp = G->n_perp;
   gd.e0_par = e0p;
@@ -209,6 +212,7 @@ lya_status check_common(lya_context* ctx, const lya_forests* F, const lya_grid* 
   gd.emax_perp = et;
   gd.zero_lo_par = e0p == 0.0;
   gd.zero_lo_perp = e0t == 0.0;
+  gd.exact_all = (up && ut) ? 0 : 1;
   return LYA_OK;
 }
 
@@ -809,7 +813,9 @@ lya_status xi3_impl(lya_context* ctx, const lya_forests* F, const lya_grid3* G3,
   if (!ctx) return LYA_E_INVALID;
   if (!G3) return fail(ctx, LYA_E_INVALID, "NULL grid");
   double r_e0, r_inv, r_max;
-  LYA_TRY(check_axis(ctx, G3->r_edges, G3->n_r, "r", r_e0, r_inv, r_max));
+  bool r_uniform;
+  LYA_TRY(check_axis(ctx, G3->r_edges, G3->n_r, "r", r_e0, r_inv, r_max, r_uniform));
+  if (!r_uniform) return fail(ctx, LYA_E_UNSUPPORTED, "r_edges are not uniformly spaced (the 3PCF bins uniform sides only)");
   const int nt = G3->n_theta, nc = G3->n_cos;
   const double* te = G3->theta_edges;
   const double* ce = G3->cos_edges;

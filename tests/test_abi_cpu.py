@@ -36,6 +36,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.lya_options) == 4 * 8 + 8 + 8 + 8
     assert L.lya_options.deterministic.offset == 48
     assert L.lya_options.dmat_keep_fraction.offset == 32
+    assert ctypes.sizeof(L.lya_stats) == 3 * 8 + 2 * 4 + 4 * 4 + 3 * 8
 
 
 def test_defaults_and_null_arguments():

@@ -224,7 +224,9 @@ def test_invalid_inputs(lib):
     bad.realisation[1] = 2
     bad.n_realisations = 2
     expect(LYA_E_INVALID, bad)
-    expect(LYA_E_UNSUPPORTED, F, Grid(np.array([0.0, 1.0, 3.0]), np.array([0.0, 4.0])))
+    # non-uniform edges are valid input (binned by searching the edge arrays)
+    Gn = Grid(np.array([0.0, 1.0, 3.0]), np.array([0.0, 4.0]))
+    check(run_xi(lib, F, Gn, precision="fp64"), O.xi_sums(F, Gn), "fp64", "non-uniform")
     expect(LYA_E_INVALID, F, Grid(np.array([0.0, 2.0, 1.0]), np.array([0.0, 4.0])))
     expect(LYA_E_INVALID, F, Grid(np.array([-1.0, 2.0]), np.array([0.0, 4.0])))
     expect(LYA_E_UNSUPPORTED, F, uniform_grid(100, 200.0))
