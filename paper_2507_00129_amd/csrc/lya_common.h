@@ -196,6 +196,7 @@ struct WorklistArgs {
   const double* dec;
   int n_strips;
   double strip_h;
+  double theta;           // largest angle at which a pixel pair can be in the grid (<= strip_h)
   double eperp_max, epar_max;
   int symmetric;          // neighbours on both sides (backward)
   int own_by_index;       // each unordered pair listed under the forest with the smaller input index

@@ -351,6 +351,7 @@ lya_status build_worklist(lya_context* ctx, const lya_forests* F, const GridDev&
   a.dec = F->dec;
   a.n_strips = n_strips;
   a.strip_h = kPi / n_strips;
+  a.theta = theta;
   a.eperp_max = gd.emax_perp;
   a.epar_max = gd.emax_par;
   a.symmetric = symmetric || own_by_index;
