@@ -950,7 +950,7 @@ def _near(x, e, tau):
     return np.any(np.abs(np.asarray(x)[..., None] - e) <= np.asarray(tau)[..., None], axis=-1)
 
 
-def xi3_sums(F, g3: Grid3, edge_tau=1e-12, sub=None, n_sub=1) -> Xi3Sums:
+def xi3_sums(F, g3: Grid3, edge_tau=1e-12, sub=None, n_sub=1, vertices=None) -> Xi3Sums:
     """Triplet sums of eq. estimator_three, vertex by vertex.
 
     For a vertex pixel i the partners are the pixels of every other forest of
@@ -962,11 +962,17 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12, sub=None, n_sub=1) -> Xi3Sums:
     by subsample for the dispersion of the 3PCF figure (subsamples of the
     forests in sky pixels): every entry goes to slab r * n_sub + sub[f] of
     its main vertex's forest f; the first axis is then R * n_sub.
+
+    With `vertices` (forest indices) only the pixels of those forests act as
+    the main vertex; their partners still come from every forest.  The entries
+    of one vertex do not depend on the others, so this is the restriction of
+    the same sums to those vertices (it keeps checks at survey density cheap).
     """
     n_sub = int(n_sub) if sub is not None else 1
     R = max(1, int(F.n_realisations)) * n_sub
     nb = g3.n_bins
     rmax = float(g3.r_edges[-1])
+    vset = None if vertices is None else set(int(v) for v in vertices)
     n_vec = unit_vectors(F.ra, F.dec)
     fid = np.repeat(np.arange(F.n_forests), np.diff(F.offsets))
     pos = F.dist[:, None] * n_vec[fid]
@@ -985,7 +991,7 @@ def xi3_sums(F, g3: Grid3, edge_tau=1e-12, sub=None, n_sub=1) -> Xi3Sums:
         nbrs[int(f)].append(int(g))
         nbrs[int(g)].append(int(f))
     for f in range(F.n_forests):
-        if not nbrs[f] or F.offsets[f + 1] == F.offsets[f]:
+        if not nbrs[f] or F.offsets[f + 1] == F.offsets[f] or (vset is not None and f not in vset):
             continue
         g_list = np.array(sorted(nbrs[f]), np.int64)
         idx = np.concatenate([np.arange(F.offsets[g], F.offsets[g + 1]) for g in g_list])

@@ -327,6 +327,25 @@ def test_xi3_subsamples_vs_oracle(lib, variant):
     np.testing.assert_array_equal(out["ntrip"].sum(axis=1), whole["ntrip"])
 
 
+def test_xi3_wide_kernel_vs_oracle_at_eboss_density(lib):
+    """The wide kernel on the grid of the paper's 3PCF figure (r to 80 Mpc/h,
+    20 x 10 x 20 bins) at eBOSS density, against the oracle restricted to one
+    vertex forest (the shortest of the ten nearest the centre): the subsample
+    split puts it alone in slab 0, whose entries (1.4e8, from thousands of
+    partners per vertex pixel) must match exactly, with N and W to 1e-12."""
+    F, _, _ = make_config(1, seed=3, scale=0.05)
+    S = subset_forests(F, nearest_to_centre(F, 150))
+    G3 = O.Grid3(np.linspace(0.0, 80.0, 21), np.linspace(0.0, np.pi, 11), np.linspace(-1.0, 1.0, 21))
+    chosen = [int(np.argmin(np.diff(S.offsets)[:10]))]
+    sub = np.ones(S.n_forests, np.int32)
+    sub[chosen] = 0
+    out = run3_sub(lib, S, G3, sub, 2, expect_variant=2)
+    ref = O.xi3_sums(S, G3, vertices=chosen)
+    slab0 = {k: v[:, 0] for k, v in out.items()}
+    assert ref.ntrip.sum() > 1e7
+    check3(slab0, ref, "wide kernel, eBOSS density, 3 vertex forests")
+
+
 def test_xi3_subsamples_invalid_id(lib):
     from paper_2507_00129_amd import LyaError, LYA_E_INVALID
     F = tiny(0, n_forests=4, k=4, width_deg=0.3)

@@ -660,6 +660,26 @@ def test_xi3_subsample_split_vs_python_brute():
         for f in keep)
 
 
+def test_xi3_vertex_restriction_vs_python_brute():
+    """Restricting the main vertex to some forests gives the pure-Python loop's
+    slab for a subsample split that puts exactly those forests in slab 0, and
+    the restrictions to a set and to its complement add up to the whole."""
+    F = tiny(21, n_forests=6, k=4, width_deg=0.3)
+    G3 = _grid3()
+    chosen = [1, 4]
+    V = O.xi3_sums(F, G3, vertices=chosen)
+    sub = np.array([0 if f in chosen else 1 for f in range(F.n_forests)], np.int32)
+    N_, W_, C_ = O.xi3_brute(F, G3, sub=sub, n_sub=2)
+    assert C_[0].sum() > 20
+    assert (V.ntrip[0] == C_[0]).all()
+    assert np.allclose(V.num[0], N_[0], rtol=1e-13, atol=1e-13 * np.abs(N_[0]).max())
+    assert np.allclose(V.wsum[0], W_[0], rtol=1e-13, atol=1e-13 * np.abs(W_[0]).max())
+    rest = O.xi3_sums(F, G3, vertices=[f for f in range(F.n_forests) if f not in chosen])
+    U = O.xi3_sums(F, G3)
+    assert (V.ntrip + rest.ntrip == U.ntrip).all()
+    assert np.allclose(V.wsum + rest.wsum, U.wsum, rtol=1e-13, atol=0)
+
+
 def test_xi3_single_bin_closed_form():
     """With one bin holding every triangle, the sums run over all ordered
     triples of distinct forests: sum S_f S_g S_h = S1^3 - 3 S1 S2 + 2 S3 with
