@@ -56,6 +56,9 @@ template <> struct WForm<float> {
   __device__ __forceinline__ static Acc step(float a, float b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // operand scale: the hardware square root (1 ulp), well inside the form's
+  // FP32 rounding of the operands
+  __device__ __forceinline__ static float root(float x) { return __builtin_amdgcn_sqrtf(x); }
 };
 template <> struct WForm<double> {
   using Acc = wv_d4;
@@ -64,6 +67,7 @@ template <> struct WForm<double> {
   __device__ __forceinline__ static Acc step(double a, double b, Acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ __forceinline__ static double root(double x) { return sqrt(x); }
 };
 
 // OR over the wave, uniform result: four DPP steps reduce each row of 16
@@ -213,15 +217,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   // rectangle pass keeps only bx < NX <= by (x range times y range).  Each
   // step sits in its own conditional block: the compiler then updates the
   // accumulators in place.
+  // the pass type folded into two block masks up front, so that each block
+  // pair costs one scalar bit test: a rectangle pass keeps the pairs with
+  // bx < NX <= by, a diagonal pass every bx <= by
   auto tile_steps = [&](uint32_t u, bool diag, const T* A, const T* B) __attribute__((always_inline)) {
+    constexpr uint32_t kXMask = (1u << NX) - 1u;
+    const uint32_t ux = diag ? u : (u & kXMask), uy = diag ? u : (u & ~kXMask);
     static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
       constexpr int by = decltype(BY)::value;
-      if (!((u >> by) & 1u)) return;
+      if (!((uy >> by) & 1u)) return;
       static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
         constexpr int bx = decltype(BX)::value;
         constexpr int j = by * (by + 1) / 2 + bx;
-        constexpr bool in_rect = bx < NX && by >= NX;
-        if (((u >> bx) & 1u) && (in_rect || diag)) acc[j] = Form::step(A[bx], B[by], acc[j]);
+        if ((ux >> bx) & 1u) acc[j] = Form::step(A[bx], B[by], acc[j]);
       });
     });
   };
@@ -519,7 +527,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                       h1[b] = fma(wra, op[b], h1[b]);
                     }
                 }
-                const T sq = sqrt(wr * co_l);
+                const T sq = Form::root(wr * co_l);
 #pragma unroll
                 for (int b = 0; b < SB; ++b) op[b] *= sq;
                 tile_steps(ucur, P.diag, op, op);
