@@ -35,6 +35,8 @@
 // accumulators).  Windows wider than NB blocks take several passes over the
 // run, each re-binning its rows: a diagonal pass per segment of NB blocks,
 // and rectangle passes of NB x NY blocks between segments.
+#include <type_traits>
+
 #include "lya_bin.h"
 #include "lya_common.h"
 
@@ -396,78 +398,115 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
             };
             // bins rows r and r + 1 into buffer bsel (w and w a added at each pair's
             // storage bin); returns the union of their block masks (uniform).  The
-            // 2 x PMAX evaluations of a chunk are straight-line code with predicates;
-            // the FP64 edge path and the LDS adds are the only branches.
-            auto bin_rows = [&](int r, int bsel) -> uint32_t {
-              uint32_t bits = 0;
-              rows_at(r);
-              const T rdv[2] = {srow[0][r - rbase], srow[0][r + 1 - rbase]};
-              const bool rowok[2] = {true, r + 1 < nr};
-#pragma unroll 1
-              for (int c0 = 0; c0 < no; c0 += CH) {
-                load_other(c0);
+            // 2 x NK evaluations of a chunk run in three phases -- the FP32 bins,
+            // then the FP64 edge path where some lane needs it (a uniform branch),
+            // then the storage bins and the LDS adds -- so that the independent
+            // evaluations interleave instead of waiting on one another.
+            auto bin_chunk = [&](auto NKC, int c0, int r, int bsel, const T* rdv, bool row1ok)
+                __attribute__((always_inline)) -> uint32_t {
+              constexpr int NKE = decltype(NKC)::value;
+              int L[2][NKE];
+              bool inr[2][NKE], need[2][NKE];
+              bool anyneed = false;
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int k = 0; k < NKE; ++k) {
+                  T rp, rt;
+                  separations(rdv[h], od[k], c, s, bsep, rp, rt);
+                  T xp, xt;
+                  if constexpr (ZLO) {
+                    xp = rp * K.invp;
+                    xt = rt * K.invt;
+                  } else {
+                    xp = (rp - K.e0p) * K.invp;
+                    xt = (rt - K.e0t) * K.invt;
+                  }
+                  const bool in = (h == 0 || row1ok) & (xp < K.np_hi) & (xt < K.nt_hi) &
+                                  (ZLO || ((xp > K.lo_p) & (xt > K.lo_t)));
+                  const T rxp = rint(xp), rxt = rint(xt);
+                  bool gp = fabs(xp - rxp) < K.taup, gt = fabs(xt - rxt) < K.taut;
+                  if constexpr (ZLO) {
+                    gp &= rxp != (T)0;
+                  } else {
+                    gp &= !(K.zlp & (rxp == (T)0));
+                    gt &= !(K.zlt & (rxt == (T)0));
+                  }
+                  // (clamped before the conversion: out-of-range lanes are discarded below)
+                  L[h][k] = (int)__umul24((unsigned)(int)fmin(xt, (T)65536), (unsigned)NP) + (int)fmin(xp, (T)65536);
+                  inr[h][k] = in;
+                  need[h][k] = in & (gp | gt);
+                  anyneed |= need[h][k];
+                }
+              }
+              if (__ballot(anyneed)) {
+                // within rounding of an edge: the FP64 separations against the edges
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                  double* hw = &buf[bsel][2 * h][0];
 #pragma unroll
-                  for (int k = 0; k < PMAX; ++k) {
-                    if (k >= ppl) break;  // uniform
-                    T rp, rt;
-                    separations(rdv[h], od[k], c, s, bsep, rp, rt);
-                    T xp, xt;
-                    if constexpr (ZLO) {
-                      xp = rp * K.invp;
-                      xt = rt * K.invt;
-                    } else {
-                      xp = (rp - K.e0p) * K.invp;
-                      xt = (rt - K.e0t) * K.invt;
-                    }
-                    const bool inr = rowok[h] & (xp < K.np_hi) & (xt < K.nt_hi) &
-                                     (ZLO || ((xp > K.lo_p) & (xt > K.lo_t)));
-                    const T rxp = rint(xp), rxt = rint(xt);
-                    bool gp = fabs(xp - rxp) < K.taup, gt = fabs(xt - rxt) < K.taut;
-                    if constexpr (ZLO) {
-                      gp &= rxp != (T)0;
-                    } else {
-                      gp &= !(K.zlp & (rxp == (T)0));
-                      gt &= !(K.zlt & (rxt == (T)0));
-                    }
-                    // (clamped before the conversion: out-of-range lanes are discarded below)
-                    int L = (int)__umul24((unsigned)(int)fmin(xt, (T)65536), (unsigned)NP) + (int)fmin(xp, (T)65536);
-                    if (inr & (gp | gt)) {
-                      // within rounding of an edge: the FP64 separations against the edges
+                  for (int k = 0; k < NKE; ++k) {
+                    if (need[h][k]) {
                       double rp64, rt64;
                       if constexpr (kF32) {
                         separations64(srowD[r + h - rbase], recs[poth0 + c0 + lane * ppl + k].D, pr.c, pr.s,
                                       rp64, rt64);
                       } else {
-                        rp64 = rp;
-                        rt64 = rt;
+                        separations(rdv[h], od[k], c, s, bsep, rp64, rt64);
                       }
-                      const int kp = bin_exact(rp64, K.ep, NP, (int)floor((double)xp));
-                      const int kt = bin_exact(rt64, K.et, NT, (int)floor((double)xt));
-                      L = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
+                      const int kp = bin_exact(rp64, K.ep, NP, (int)floor((rp64 - a.g.e0_par) * a.g.inv_par));
+                      const int kt = bin_exact(rt64, K.et, NT, (int)floor((rt64 - a.g.e0_perp) * a.g.inv_perp));
+                      L[h][k] = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
                     }
-                    const int w = L - base_L;
-                    const bool ing = inr & (L >= 0);
-                    const bool inw = ing & ((unsigned)w < (unsigned)nwin);
-                    if (a.counters) {  // statistics only (uniform)
-                      n_lost += (ing & !inw) ? 1ull : 0ull;
-                      if (count_in && rs == 0) n_in += inw ? 1ull : 0ull;
-                    }
-                    // storage bin of the pass
-                    const int wx = w - 16 * P.x0, wy = w - 16 * P.y0;
-                    const bool okx = (unsigned)wx < (unsigned)(16 * P.nx);
-                    const bool oky = !P.diag & ((unsigned)wy < (unsigned)(16 * P.ny));
-                    const int sidx = okx ? wx : 16 * NX + wy;
-                    const bool ok = inw & (okx | oky);
-                    if (ok) {
-                      atomicAdd(&hw[sidx], (double)ow[k]);
-                      atomicAdd(&hw[SW + sidx], (double)owa[k]);
-                    }
-                    bits |= ok ? (1u << ((sidx >> 4) & 31)) : 0u;
                   }
                 }
+              }
+              uint32_t bits = 0;
+              int sidx[2][NKE];
+              bool ok[2][NKE];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int k = 0; k < NKE; ++k) {
+                  const int w = L[h][k] - base_L;
+                  const bool ing = inr[h][k] & (L[h][k] >= 0);
+                  const bool inw = ing & ((unsigned)w < (unsigned)nwin);
+                  if (a.counters) {  // statistics only (uniform)
+                    n_lost += (ing & !inw) ? 1ull : 0ull;
+                    if (count_in && rs == 0) n_in += inw ? 1ull : 0ull;
+                  }
+                  // storage bin of the pass
+                  const int wx = w - 16 * P.x0, wy = w - 16 * P.y0;
+                  const bool okx = (unsigned)wx < (unsigned)(16 * P.nx);
+                  const bool oky = !P.diag & ((unsigned)wy < (unsigned)(16 * P.ny));
+                  sidx[h][k] = okx ? wx : 16 * NX + wy;
+                  ok[h][k] = inw & (okx | oky);
+                  bits |= ok[h][k] ? (1u << ((sidx[h][k] >> 4) & 31)) : 0u;
+                }
+              }
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                double* hw = &buf[bsel][2 * h][0];
+#pragma unroll
+                for (int k = 0; k < NKE; ++k) {
+                  if (ok[h][k]) {
+                    atomicAdd(&hw[sidx[h][k]], (double)ow[k]);
+                    atomicAdd(&hw[SW + sidx[h][k]], (double)owa[k]);
+                  }
+                }
+              }
+              return bits;
+            };
+            auto bin_rows = [&](int r, int bsel) -> uint32_t {
+              uint32_t bits = 0;
+              rows_at(r);
+              const T rdv[2] = {srow[0][r - rbase], srow[0][r + 1 - rbase]};
+              const bool row1ok = r + 1 < nr;
+#pragma unroll 1
+              for (int c0 = 0; c0 < no; c0 += CH) {
+                load_other(c0);
+                // slots k >= ppl hold far-away pixels (never in the grid)
+                if (ppl <= 2) bits |= bin_chunk(std::integral_constant<int, 2 < PMAX ? 2 : PMAX>{}, c0, r, bsel, rdv, row1ok);
+                else bits |= bin_chunk(std::integral_constant<int, PMAX>{}, c0, r, bsel, rdv, row1ok);
               }
               return wave_or(bits);
             };

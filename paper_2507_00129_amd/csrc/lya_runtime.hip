@@ -1055,10 +1055,17 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
       HIP_TRY(launch_sort_keys(k_in, k_out, v_in, v_out, W.n_pairs, tmp, bytes, st));
       a.wkeys = k_out;
       a.worder = v_out;
-      // at least ~8 items per workgroup slot, at most kDmatChunk pairs per item
+      // at least ~64 items per workgroup of the widest variant, so that the
+      // last items leave little idle time at the end of the launch (a forest
+      // pair takes ~0.1 ms of one wave); at most kDmatChunk pairs per item
       // (each item adds its tile to the global numerator once per run)
-      const int64_t per = W.n_pairs / (8 * (int64_t)ctx->n_cu);
-      a.chunk = (int32_t)(per < 64 ? 64 : (per > kDmatChunk ? kDmatChunk : per));
+      int max_wg = 0;
+      for (int v = 0; v < dmat_num_variants(); ++v) {
+        const int b = dmat_blocks_per_cu(v, o->precision);
+        if (b > max_wg) max_wg = b;
+      }
+      const int64_t per = W.n_pairs / (64 * (int64_t)max_wg * ctx->n_cu);
+      a.chunk = (int32_t)(per < 16 ? 16 : (per > kDmatChunk ? kDmatChunk : per));
       a.n_items = (W.n_pairs + a.chunk - 1) / a.chunk;
     }
     a.drec32 = P.drec32;
