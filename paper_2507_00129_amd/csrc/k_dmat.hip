@@ -215,7 +215,7 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
     __syncthreads();
     const int64_t it = sm.item;
     if (it >= a.n_items) break;
-    const int64_t k0 = it * a.chunk;
+    const int64_t k0 = it * a.item_stride * a.chunk;
     const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
     for (int64_t r0 = k0; r0 < k1;) {
       const uint64_t key = a.wkeys[r0];

@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
     if (lane == 0) itv = atomicAdd(a.counter, 1u);
     const int64_t it = (int64_t)(unsigned)__builtin_amdgcn_readlane((int)itv, 0);
     if (it >= a.n_items) break;
-    const int64_t k0 = it * a.chunk;
+    const int64_t k0 = it * a.item_stride * a.chunk;
     const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
     for (int64_t r0 = k0; r0 < k1;) {
       const uint64_t key = a.wkeys[r0];
@@ -525,16 +525,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                 // this lane's row (rows past nr were staged as zeros)
                 wr = srow[1][2 * st + rpar - rbase];
                 wra = srow[2][2 * st + rpar - rbase];
-                // operands: R^l of the lane's row over each block the step reaches;
-                // the slots read are cleared for the next use of this buffer
+                // operands: R^l of the lane's row over every block slot (slots the
+                // step does not reach hold zeros), read without branches so the
+                // reads overlap; the slots are cleared for the next use of this buffer
+                double ov[SB];
+#pragma unroll
+                for (int b = 0; b < SB; ++b) ov[b] = buf[bsel][lk][16 * b + lm];
 #pragma unroll
                 for (int b = 0; b < SB; ++b) {
-                  op[b] = (T)0;
-                  if ((ucur >> b) & 1u) {
-                    double* pp = &buf[bsel][lk][16 * b + lm];
-                    op[b] = (T)*pp;
-                    *pp = 0.0;
-                  }
+                  op[b] = (T)ov[b];
+                  buf[bsel][lk][16 * b + lm] = 0.0;
                 }
               }
               const uint32_t unext = st + 1 < nsteps ? bin_rows(2 * st + 2, (st + 1) & 1) : 0u;

@@ -293,6 +293,7 @@ struct DmatArgs {
   const int32_t* worder;   // pair index of each sorted key
   int64_t n_items;         // chunks of `chunk` consecutive sorted pairs
   int32_t chunk;
+  int32_t item_stride;     // item i is chunk i * item_stride (1; more for the autotuner's sample)
   unsigned int* counter;
   const DRec32* drec32;
   const DRec64* drec64;

@@ -1031,6 +1031,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     unsigned int* counter;
     LYA_TRY(wst(ctx, "dm_counter", 1, &counter));
     DmatArgs a{};
+    a.item_stride = 1;
     a.finfo = P.finfo;
     a.einfo = P.einfo;
     a.sorted = W.sorted;
@@ -1096,8 +1097,12 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
         DmatArgs t = a;
         t.dnum = sd;
         t.wd = sw;
-        // a spread-out sample: every 8th chunk would need a gather; take a prefix of items
-        t.n_items = a.n_items < 2 * ctx->n_cu ? a.n_items : (a.n_items / 8 > 2 * ctx->n_cu ? a.n_items / 8 : 2 * ctx->n_cu);
+        // a sample spread over the sorted pair list (window widths and pair
+        // sizes change along it): every 8th chunk when there are enough
+        if (a.n_items >= 8 * 64 * (int64_t)ctx->n_cu) {
+          t.item_stride = 8;
+          t.n_items = a.n_items / 8;
+        }
         float best = 1e30f;
         for (int v = 0; v < dmat_num_variants(); ++v) {
           const int blocks = dmat_blocks_per_cu(v, o->precision) * ctx->n_cu;
