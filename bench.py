@@ -35,6 +35,8 @@ if ROOT not in sys.path:
 # arithmetic is adds, multiplies and compares.  (The 157.3 TFLOP/s FP32 vector
 # figure is the FMA rate with packed FMAs; packed FP32 is not used here.)
 PEAK_VALU_LANE_OPS = 256 * 4 * 32 * 2.4e9
+# FP64 VALU: one 64-lane FP64 add, multiply or FMA per SIMD every four clocks
+PEAK_VALU_F64_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_MFMA_F64 = 78.6e12                   # dense FP64 matrix peak (flop/s)
 PEAK_MFMA_F32 = 157.3e12                  # dense FP32 matrix peak (flop/s)
 PEAK_HBM = 8.0e12
@@ -340,6 +342,20 @@ def xi_lds_roofline(r, peaks):
                 peak_u32=peaks["lds_add_u32"] / 1e12, ms=r["ms_xi_kernel"])
 
 
+def xi3_roofline(entries, ms, peaks):
+    """Per entry (triplet i; j, k) the 3PCF kernels compute cos alpha = u_j . u_k
+    (3 multiplies, 2 adds), the products w_i d_i w_j d_j w_k d_k and w_i w_j w_k
+    (4 multiplies) and add them to the running sums (2 adds): 11 FP64 lane-ops;
+    unmerged, an entry would also be 2 FP64 and 1 u32 LDS atomic adds."""
+    t = ms / 1e3
+    ops = 11.0 * entries
+    out = dict(bound="alu", achieved=ops / t / 1e12, peak=PEAK_VALU_F64_LANE_OPS / 1e12, unit="TFLOP/s",
+               frac=ops / t / PEAK_VALU_F64_LANE_OPS, work=f"11 FP64 lane-ops x {entries} entries")
+    if peaks:
+        out["lds_atomic_frac"] = entries * (2.0 / peaks["lds_add_f64"] + 1.0 / peaks["lds_add_u32"]) / t
+    return out
+
+
 def d_roofline(r):
     flops = 2.0 * r["d_fmas"]
     achieved = flops / (r["ms_d_kernel"] / 1e3) / 1e12
@@ -498,7 +514,8 @@ def main():
                             f"({S.n_pix} pixels); r to 40 Mpc/h (10 bins), theta 10 bins, cos alpha 20 bins",
                    kernel="xi3c_kernel (entries summed in LDS per side-1 cell)" if variant == 0
                    else "xi3_kernel (global atomics per entry)",
-                   entries=entries, ms_kernel=ms[-1], entries_per_s=entries / t3, dtype="f64")
+                   entries=entries, ms_kernel=ms[-1], entries_per_s=entries / t3, dtype="f64",
+                   roofline=xi3_roofline(entries, ms[-1], peaks))
         log(f"[bench] xi3: {entries:.3e} entries in {ms[-1]:.1f} ms ({entries / t3:.3e} entries/s)")
         del dS, o3
         # the grid of the paper's 3PCF figure: r to 80 Mpc/h in 20 bins, theta
@@ -516,7 +533,8 @@ def main():
                      f"theta 10 bins, cos alpha 20 bins",
             kernel={0: "xi3c_kernel", 1: "xi3_kernel", 2: "xi3w_kernel (partner lists in global scratch)"}[
                 st3["variant"]],
-            entries=e80, ms_kernel=st3["ms_main"], entries_per_s=e80 / (st3["ms_main"] / 1e3))
+            entries=e80, ms_kernel=st3["ms_main"], entries_per_s=e80 / (st3["ms_main"] / 1e3),
+            roofline=xi3_roofline(e80, st3["ms_main"], peaks))
         log(f"[bench] xi3 paper grid: {e80:.3e} entries in {st3['ms_main']:.1f} ms")
         del dS, o3
 

@@ -117,6 +117,46 @@ def test_finite_differences_on_gpu(lib):
         assert abs(fd - gw[i]) <= 1e-4 * abs(gw[i]) + 1e-6 * np.abs(gw).max(), (i, fd, gw[i])
 
 
+def test_finite_differences_fp32_on_gpu(lib):
+    """The FP32 form's forward and backward, central differences with eps =
+    1e-3.  Binning is identical in the two evaluations and the products of
+    unperturbed pixel pairs are bitwise equal, so the difference carries only
+    the FP32 rounding of the perturbed pixel's products and of the run sums
+    that hold them: ~6e-8 |w delta_i| sum_j |w delta_j| per bin against a
+    change of 2 eps w_i sum_j w delta_j, i.e. ~3e-5 |delta_i| times the
+    cancellation ratio sum |w delta| / |sum w delta| of the pixel's partners.
+    Tolerance 2e-4 relative plus 2e-6 of the largest gradient (the same for
+    w, where the O(eps^2) truncation is far smaller)."""
+    from paper_2507_00129_amd import DeviceForests
+    F, G, ex = make_config(4, seed=1, scale=0.02)
+    dF = DeviceForests.from_host(F, "cuda:0")
+    tgt = torch.as_tensor(ex["target"], device="cuda:0")[None, :]
+
+    def loss(d, w):
+        x = lib.xi(dF.with_values(delta=d, weight=w), G, precision="fp32")["xi"]
+        return float(((x - tgt) ** 2).sum())
+
+    out = lib.xi(dF, G, precision="fp32")
+    gd, gw = lib.xi_backward(dF, G, 2.0 * (out["xi"] - tgt), out["xi"], out["wsum"], precision="fp32")
+    gd, gw = gd.cpu().numpy(), gw.cpu().numpy()
+    rng = np.random.default_rng(6)
+    eps = 1e-3
+    worst = 0.0
+    for which, g in (("delta", gd), ("weight", gw)):
+        for i in rng.choice(F.n_pix, 16, replace=False):
+            d, w = dF.delta.clone(), dF.weight.clone()
+            v = d if which == "delta" else w
+            v[i] += eps
+            lp = loss(d, w)
+            v[i] -= 2 * eps
+            lm = loss(d, w)
+            fd = (lp - lm) / (2 * eps)
+            err = abs(fd - g[i]) / (2e-4 * abs(g[i]) + 2e-6 * np.abs(g).max())
+            worst = max(worst, err)
+            assert err <= 1.0, (which, i, fd, g[i])
+    print(f"[fd fp32] worst error / tolerance = {worst:.3f}", flush=True)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_euler_identities_full_size(lib, prec):
     """Full differentiable workload (10k forests, 50x50 bins): xi is homogeneous
@@ -127,7 +167,8 @@ def test_euler_identities_full_size(lib, prec):
     lhs = float(np.dot(F.delta, gd))
     rhs = 4.0 * float(np.sum(xi[0] * (xi[0] - ex["target"])))
     scale = float(np.dot(np.abs(F.delta), np.abs(gd)))
-    print(f"[euler {prec}] {lhs:.6e} vs {rhs:.6e}; w.gw = {np.dot(F.weight, gw):.3e}", flush=True)
+    print(f"[euler {prec}] {lhs:.12e} vs {rhs:.12e} (|diff| / scale = {abs(lhs - rhs) / scale:.2e}); "
+          f"w.gw = {np.dot(F.weight, gw):.3e} (relative {abs(np.dot(F.weight, gw)) / float(np.dot(np.abs(F.weight), np.abs(gw))):.2e})", flush=True)
     assert abs(lhs - rhs) <= TOL[prec] * scale * 10
     assert abs(np.dot(F.weight, gw)) <= TOL[prec] * float(np.dot(np.abs(F.weight), np.abs(gw))) * 10
 
