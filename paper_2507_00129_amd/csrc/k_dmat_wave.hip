@@ -105,14 +105,23 @@ __device__ __forceinline__ double xor32(double v) { return __shfl_xor(v, 32, 64)
 struct WPass {
   int x0, nx, y0, ny;
   bool diag;
+  int ymin;  // diagonal pass: only pairs whose larger storage block is >= ymin
 };
 
 // Diagonal passes over segments of NB blocks, then for every pair of
 // segments a < b rectangle passes over pieces of NX blocks of a times pieces
-// of NY blocks of b.
+// of NY blocks of b.  Two segments (NB < nblk <= 2 NB, r = nblk - NB) take
+// the diagonal pass over blocks [0, NB), a second diagonal pass over the last
+// NB blocks [r, nblk) that keeps only the pairs reaching past block NB, and
+// the rectangle [0, r) x [NB, nblk): 2 + ceil(r / NX) ceil(r / NY) passes,
+// three instead of four for windows of 11 to 15 blocks.
 template <int NB, int NX, int NY>
 __device__ __forceinline__ int count_passes(int nblk) {
   const int nseg = (nblk + NB - 1) / NB;
+  if (nseg == 2) {
+    const int r = nblk - NB;
+    return 2 + ((r + NX - 1) / NX) * ((r + NY - 1) / NY);
+  }
   int n = nseg;
   for (int b = 1; b < nseg; ++b) {
     const int lb = min(NB, nblk - b * NB);
@@ -124,9 +133,16 @@ __device__ __forceinline__ int count_passes(int nblk) {
 template <int NB, int NX, int NY>
 __device__ __forceinline__ WPass pass_of(int p, int nblk) {
   const int nseg = (nblk + NB - 1) / NB;
+  if (nseg == 2) {
+    const int r = nblk - NB;
+    if (p == 0) return WPass{0, NB, 0, NB, true, 0};
+    if (p == 1) return WPass{r, NB, r, NB, true, NB - r};
+    const int py = (r + NY - 1) / NY, ix = (p - 2) / py, iy = (p - 2) % py;
+    return WPass{ix * NX, min(NX, r - ix * NX), NB + iy * NY, min(NY, r - iy * NY), false, 0};
+  }
   if (p < nseg) {
     const int n = min(NB, nblk - p * NB);
-    return WPass{p * NB, n, p * NB, n, true};
+    return WPass{p * NB, n, p * NB, n, true, 0};
   }
   p -= nseg;
   constexpr int px = (NB + NX - 1) / NX;  // pieces of a full segment
@@ -134,11 +150,11 @@ __device__ __forceinline__ WPass pass_of(int p, int nblk) {
     const int lb = min(NB, nblk - b * NB), py = (lb + NY - 1) / NY;
     if (p < b * px * py) {
       const int a = p / (px * py), rem = p % (px * py), ix = rem / py, iy = rem % py;
-      return WPass{a * NB + ix * NX, min(NX, NB - ix * NX), b * NB + iy * NY, min(NY, lb - iy * NY), false};
+      return WPass{a * NB + ix * NX, min(NX, NB - ix * NX), b * NB + iy * NY, min(NY, lb - iy * NY), false, 0};
     }
     p -= b * px * py;
   }
-  return WPass{0, 0, 0, 0, true};
+  return WPass{0, 0, 0, 0, true, 0};
 }
 
 template <int N> struct WIC { static constexpr int value = N; };
@@ -222,9 +238,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   // the pass type folded into two block masks up front, so that each block
   // pair costs one scalar bit test: a rectangle pass keeps the pairs with
   // bx < NX <= by, a diagonal pass every bx <= by
-  auto tile_steps = [&](uint32_t u, bool diag, const T* A, const T* B) __attribute__((always_inline)) {
+  auto tile_steps = [&](uint32_t u, bool diag, int ymin, const T* A, const T* B) __attribute__((always_inline)) {
     constexpr uint32_t kXMask = (1u << NX) - 1u;
-    const uint32_t ux = diag ? u : (u & kXMask), uy = diag ? u : (u & ~kXMask);
+    const uint32_t ux = diag ? u : (u & kXMask), uy = diag ? (u & ~((1u << ymin) - 1u)) : (u & ~kXMask);
     static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
       constexpr int by = decltype(BY)::value;
       if (!((uy >> by) & 1u)) return;
@@ -542,7 +558,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                 if (a.counters) {
                   // outer-product FMAs of the sparse rows: 2 per (x, y) of nonzero R bins,
                   // counted per row over the x and y ranges
-                  int cx[2] = {0, 0}, cy[2] = {0, 0};
+                  // (a diagonal pass with ymin > 0 counts the pairs reaching block ymin:
+                  // all of its pairs less those below it)
+                  int cx[2] = {0, 0}, cy[2] = {0, 0}, cl[2] = {0, 0};
 #pragma unroll
                   for (int b = 0; b < SB; ++b) {
                     if (!((ucur >> b) & 1u)) continue;
@@ -551,11 +569,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                     for (int h = 0; h < 2; ++h) {
                       const int nz = __popc((uint32_t)((m >> (32 * h)) | (m >> (32 * h + 16))) & 0xFFFFu);
                       if (P.diag || b < NX) cx[h] += nz; else cy[h] += nz;
+                      if (P.diag && b < P.ymin) cl[h] += nz;
                     }
                   }
 #pragma unroll
                   for (int h = 0; h < 2; ++h)
-                    nalg += 2ull * (unsigned long long)cx[h] * (unsigned long long)(P.diag ? cx[h] : cy[h]);
+                    nalg += P.diag ? 2ull * (unsigned long long)(cx[h] * cx[h] - cl[h] * cl[h])
+                                   : 2ull * (unsigned long long)cx[h] * (unsigned long long)cy[h];
                 }
                 if (rs == 0) {
                   u_h |= ucur;
@@ -569,7 +589,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                 const T sq = Form::root(wr * co_l);
 #pragma unroll
                 for (int b = 0; b < SB; ++b) op[b] *= sq;
-                tile_steps(ucur, P.diag, op, op);
+                tile_steps(ucur, P.diag, P.ymin, op, op);
               }
               ucur = unext;
             }
@@ -588,19 +608,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
           const T s4 = -(rpar ? cf1 : cf0) * (comp ? cg1 : cg0);
 #pragma unroll
           for (int b = 0; b < SB; ++b) h1[b] = h0[b] * s4;
-          // every block of the pass (blocks H does not reach add zeros): the masked
-          // form of these steps came out of the compiler without the H term
+          // every block of the pass (blocks H does not reach add zeros; pairs below
+          // ymin get a zero operand): the masked form of these steps came out of
+          // the compiler without the H term
+          T hq[SB];
+#pragma unroll
+          for (int b = 0; b < SB; ++b) hq[b] = b >= P.ymin ? h0[b] : (T)0;
           static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
             constexpr int by = decltype(BY)::value;
             static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
               constexpr int bx = decltype(BX)::value;
               constexpr int j = by * (by + 1) / 2 + bx;
               constexpr bool in_rect = bx < NX && by >= NX;
-              if (in_rect || P.diag) acc[j] = Form::step(h1[bx], h0[by], acc[j]);
+              if (in_rect || P.diag) acc[j] = Form::step(h1[bx], hq[by], acc[j]);
             });
           });
           if (a.counters) {
-            int hx = 0, qy = 0;
+            int hx = 0, qy = 0, hl = 0, ql = 0;
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
               if (!((u_h >> b) & 1u)) continue;
@@ -609,14 +633,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
               const int n0 = __popcll(m0), nq = __popc((uint32_t)(m0 | (m3 >> 48)) & 0xFFFFu);
               if (P.diag || b < NX) hx += n0;
               if (P.diag || b >= NX) qy += nq;
+              if (P.diag && b < P.ymin) {
+                hl += n0;
+                ql += nq;
+              }
             }
-            nalg += 4ull * (unsigned long long)hx * (unsigned long long)qy;
+            nalg += 4ull * (unsigned long long)(hx * qy - hl * ql);
           }
           // w_A and the Kronecker term, from H^00 (lanes 0..15)
           if (P.diag && lk == 0) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-              if ((u_h >> b) & 1u) wdacc[16 * b + lm] += (double)h0[b];
+              if (((u_h >> b) & 1u) && b >= P.ymin) wdacc[16 * b + lm] += (double)h0[b];
           }
         }
 
