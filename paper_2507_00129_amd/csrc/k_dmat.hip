@@ -229,9 +229,9 @@ __global__ __launch_bounds__(BLOCK) void dmat_kernel(DmatArgs a) {
         r0 = r1;
         continue;
       }
-      const int real = (int)(key >> 40);
-      const int kt0 = (int)((key >> 16) & 0xFFFFFF);
-      const int span = (int)(key & 0xFFFF);
+      const int real = dmat_key_real(key);
+      const int kt0 = dmat_key_kt0(key);
+      const int span = dmat_key_span(key);
       const int nwin = span * NP;
       const int base_L = kt0 * NP;  // window index w = L - kt0 NP
       const int npass = (nwin + TW - 1) / TW;
@@ -636,10 +636,20 @@ __global__ void dmat_keys_kernel(DmatArgs a, uint64_t* keys, int32_t* idx) {
     const int lo = rmin < et[0] ? 0 : bin_exact(rmin, et, NT, (int)((rmin - a.g.e0_perp) * a.g.inv_perp));
     const int hi = rmax >= et[NT] ? NT - 1 : bin_exact(rmax, et, NT, (int)((rmax - a.g.e0_perp) * a.g.inv_perp));
     if (lo >= 0 && hi >= lo)
-      key = ((uint64_t)fi.real << 40) | ((uint64_t)lo << 16) | (uint64_t)(hi - lo + 1);
+      key = dmat_window_key(hi - lo + 1, fi.real, lo);
   }
   keys[q] = key;
   idx[q] = (int32_t)q;
+}
+
+__global__ void dmat_span_split_kernel(const uint64_t* keys, int64_t n, int max_span, int64_t* out) {
+  const uint64_t bound = dmat_window_key(max_span, 0, 0);
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (keys[m] < bound) lo = m + 1; else hi = m;
+  }
+  *out = lo;
 }
 
 constexpr int kNumVariants = 1;
@@ -676,6 +686,11 @@ int dmat_num_variants() { return kNumVariants + dmat_wave_num_variants(); }
 const char* dmat_variant_name(int v) {
   if (v >= kNumVariants) return dmat_wave_variant_name(v - kNumVariants);
   return v >= 0 ? kNames[v] : "?";
+}
+
+hipError_t launch_dmat_span_split(const uint64_t* keys, int64_t n, int max_span, int64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(dmat_span_split_kernel, dim3(1), dim3(1), 0, st, keys, n, max_span, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st) {

@@ -272,9 +272,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
         r0 = r1;
         continue;
       }
-      const int real = (int)(key >> 40);
-      const int kt0 = (int)((key >> 16) & 0xFFFFFF);
-      const int span = (int)(key & 0xFFFF);
+      const int real = dmat_key_real(key);
+      const int kt0 = dmat_key_kt0(key);
+      const int span = dmat_key_span(key);
       const int nwin = span * NP;
       const int base_L = kt0 * NP;
       const int nblk = (nwin + 15) >> 4;
@@ -736,6 +736,8 @@ constexpr int kPMax64 = 3;  // FP64: 192
 }  // namespace
 
 int dmat_wave_num_variants() { return 2; }
+
+int dmat_wave_tile_blocks(int v, int precision) { return precision == LYA_FP64 ? kNB64[v] : kNB32[v]; }
 
 const char* dmat_wave_variant_name(int v) {
   static const char* const names[2] = {"w64-sym-big", "w64-sym-small"};

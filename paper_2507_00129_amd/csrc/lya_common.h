@@ -308,6 +308,19 @@ struct DmatArgs {
 // window key of every kept pair: (realisation << 40) | (first k_perp << 16) | span;
 // pairs with no possible in-grid pixel pair get ~0
 hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st);
+// Window key of a kept forest pair: (span of k_perp rows, descending;
+// realisation; first k_perp row), so that the sorted list groups pairs by
+// window width, widest (costliest) first, which keeps the end of a launch
+// short; ~0 (last) for a pair with no r_perp inside the grid.
+__host__ __device__ constexpr uint64_t dmat_window_key(int span, int real, int kt0) {
+  return ((uint64_t)(0xFFFF - span) << 48) | ((uint64_t)real << 24) | (uint64_t)kt0;
+}
+__device__ __forceinline__ int dmat_key_span(uint64_t k) { return 0xFFFF - (int)(k >> 48); }
+__device__ __forceinline__ int dmat_key_real(uint64_t k) { return (int)((k >> 24) & 0xFFFFFF); }
+__device__ __forceinline__ int dmat_key_kt0(uint64_t k) { return (int)(k & 0xFFFFFF); }
+// first position of the sorted keys whose window span is at most max_span
+// (one thread; writes the count of wider pairs to *out)
+hipError_t launch_dmat_span_split(const uint64_t* keys, int64_t n, int max_span, int64_t* out, hipStream_t st);
 hipError_t launch_sort_keys(uint64_t* keys_in, uint64_t* keys_out, int32_t* v_in, int32_t* v_out,
                             int64_t n, void* tmp, size_t bytes, hipStream_t st);
 size_t sort_keys_bytes(int64_t n);
@@ -320,6 +333,7 @@ int peak_unroll_valu();
 
 // the single-wave symmetric-tile D kernel (two tile shapes per form)
 int dmat_wave_num_variants();
+int dmat_wave_tile_blocks(int v, int precision);  // tile blocks per side of a single-wave variant
 const char* dmat_wave_variant_name(int v);
 hipError_t launch_dmat_wave(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
 int dmat_wave_blocks_per_cu(int variant, int precision);

@@ -730,7 +730,10 @@ lya_status lya_xi_noalloc(lya_context* ctx, const lya_forests* F, const lya_grid
 
 const char* lya_variant_name(int32_t kernel, int32_t variant) {
   if (kernel == 0) return (variant >= 0 && variant < xi_num_variants()) ? xi_variant_name(variant) : nullptr;
-  if (kernel == 1) return (variant >= 0 && variant < dmat_num_variants()) ? dmat_variant_name(variant) : nullptr;
+  if (kernel == 1) {
+    if (variant == dmat_num_variants()) return "hybrid: w64-sym-small for one-tile windows, w64-sym-big for wider ones";
+    return (variant >= 0 && variant < dmat_num_variants()) ? dmat_variant_name(variant) : nullptr;
+  }
   return nullptr;
 }
 
@@ -1029,7 +1032,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     ctx->stats.work_items = W.n_pairs;
     ctx->stats.candidate_pairs = W.candidates;
     unsigned int* counter;
-    LYA_TRY(wst(ctx, "dm_counter", 1, &counter));
+    LYA_TRY(wst(ctx, "dm_counter", 2, &counter));
     DmatArgs a{};
     a.item_stride = 1;
     a.finfo = P.finfo;
@@ -1077,10 +1080,46 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     a.g = gd;
     a.dnum = dmat;
     a.wd = wsum_d;
+    // variants: the kernels of dmat_num_variants(), then the hybrid launch:
+    // the pairs whose window fits the small single-wave tile in one pass (the
+    // sorted list puts them last) go to that kernel, two waves per SIMD, and
+    // the wider windows to the large-tile kernel
+    const int kHybrid = dmat_num_variants();
+    int64_t n_wide = -1;
+    auto launch_variant = [&](int v, const DmatArgs& args) -> lya_status {
+      if (v < kHybrid) {
+        HIP_TRY(launch_zero(counter, 4, st));
+        HIP_TRY(launch_dmat(v, o->precision, args, dmat_blocks_per_cu(v, o->precision) * ctx->n_cu, st));
+        return LYA_OK;
+      }
+      constexpr int kSmall = 2, kBig = 1;  // dmat variants of the small and the large single-wave tile
+      if (n_wide < 0) {
+        const int max_span = 16 * dmat_wave_tile_blocks(kSmall - 1, o->precision) / gd.n_par;
+        int64_t* dn;
+        LYA_TRY(wst(ctx, "dm_wide", 1, &dn));
+        HIP_TRY(launch_dmat_span_split(a.wkeys, a.n_pairs, max_span, dn, st));
+        HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 64, dn, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        n_wide = *(int64_t*)((char*)ctx->pinned + 64);
+      }
+      // (args may cover a prefix of the list: the autotuner's warm-up launch)
+      DmatArgs wide = args, narrow = args;
+      wide.n_pairs = n_wide < args.n_pairs ? n_wide : args.n_pairs;
+      wide.n_items = (wide.n_pairs + args.chunk - 1) / args.chunk / args.item_stride;
+      narrow.wkeys = args.wkeys + n_wide;
+      narrow.worder = args.worder + n_wide;
+      narrow.n_pairs = args.n_pairs > n_wide ? args.n_pairs - n_wide : 0;
+      narrow.n_items = (narrow.n_pairs + args.chunk - 1) / args.chunk / args.item_stride;
+      narrow.counter = counter + 1;
+      HIP_TRY(launch_zero(counter, 8, st));
+      HIP_TRY(launch_dmat(kBig, o->precision, wide, dmat_blocks_per_cu(kBig, o->precision) * ctx->n_cu, st));
+      HIP_TRY(launch_dmat(kSmall, o->precision, narrow, dmat_blocks_per_cu(kSmall, o->precision) * ctx->n_cu, st));
+      return LYA_OK;
+    };
     int variant = 0;
     if (o->variant >= 0) {
-      if (o->variant >= dmat_num_variants())
-        return fail(ctx, LYA_E_INVALID, "variant %d out of range (dmat has %d)", o->variant, dmat_num_variants());
+      if (o->variant > kHybrid)
+        return fail(ctx, LYA_E_INVALID, "variant %d out of range (dmat has %d)", o->variant, kHybrid + 1);
       variant = o->variant;
     } else {
       char key[96];
@@ -1098,23 +1137,25 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
         t.dnum = sd;
         t.wd = sw;
         // a sample spread over the sorted pair list (window widths and pair
-        // sizes change along it): every 8th chunk when there are enough
-        if (a.n_items >= 8 * 64 * (int64_t)ctx->n_cu) {
-          t.item_stride = 8;
-          t.n_items = a.n_items / 8;
+        // sizes change along it): every 4th chunk when there are enough, so
+        // that each workgroup of each launch still takes ~16 items; one timed
+        // launch per variant after a short one that loads its code
+        if (a.n_items >= 4 * 64 * (int64_t)ctx->n_cu) {
+          t.item_stride = 4;
+          t.n_items = a.n_items / 4;
         }
         float best = 1e30f;
-        for (int v = 0; v < dmat_num_variants(); ++v) {
-          const int blocks = dmat_blocks_per_cu(v, o->precision) * ctx->n_cu;
+        for (int v = 0; v <= kHybrid; ++v) {
           float ms_v = 0.f;
-          for (int rep = 0; rep < 2; ++rep) {
-            HIP_TRY(launch_zero(counter, 4, st));
-            HIP_TRY(hipEventRecord(ctx->ev[6], st));
-            HIP_TRY(launch_dmat(v, o->precision, t, blocks, st));
-            HIP_TRY(hipEventRecord(ctx->ev[7], st));
-            HIP_TRY(hipEventSynchronize(ctx->ev[7]));
-            HIP_TRY(hipEventElapsedTime(&ms_v, ctx->ev[6], ctx->ev[7]));
-          }
+          DmatArgs w = t;
+          w.n_items = t.n_items < 16 ? t.n_items : 16;
+          w.n_pairs = w.n_items * (int64_t)t.item_stride * t.chunk < t.n_pairs ? w.n_items * (int64_t)t.item_stride * t.chunk : t.n_pairs;
+          LYA_TRY(launch_variant(v, w));
+          HIP_TRY(hipEventRecord(ctx->ev[6], st));
+          LYA_TRY(launch_variant(v, t));
+          HIP_TRY(hipEventRecord(ctx->ev[7], st));
+          HIP_TRY(hipEventSynchronize(ctx->ev[7]));
+          HIP_TRY(hipEventElapsedTime(&ms_v, ctx->ev[6], ctx->ev[7]));
           if (ms_v < best) {
             best = ms_v;
             variant = v;
@@ -1123,7 +1164,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
         ctx->tuned[key] = variant;
       }
     }
-    const int blocks = dmat_blocks_per_cu(variant, o->precision) * ctx->n_cu;
+    const int blocks = dmat_blocks_per_cu(variant < kHybrid ? variant : 1, o->precision) * ctx->n_cu;
     ctx->stats.variant = variant;
     ctx->stats.grid_blocks = blocks;
     unsigned long long* wc = nullptr;
@@ -1132,9 +1173,8 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
       HIP_TRY(launch_zero(wc, 3 * sizeof(unsigned long long), st));
     }
     a.counters = wc;
-    HIP_TRY(launch_zero(counter, 4, st));
     tm.at(3);
-    HIP_TRY(launch_dmat(variant, o->precision, a, blocks, st));
+    LYA_TRY(launch_variant(variant, a));
     tm.at(4);
     if (wc) {
       HIP_TRY(hipMemcpyAsync((char*)ctx->pinned + 64, wc, 24, hipMemcpyDeviceToHost, st));

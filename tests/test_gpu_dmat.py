@@ -17,8 +17,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 G60 = uniform_grid(15, 60.0)
 # kernel variants: 0 the 8-wave kernel with a full tile; 1 and 2 the
-# single-wave kernel with the upper-triangle tile (large and small tile)
-VARIANTS = [0, 1, 2]
+# single-wave kernel with the upper-triangle tile (large and small tile); 3 the
+# hybrid launch (small tile for one-tile windows, large tile for the rest)
+VARIANTS = [0, 1, 2, 3]
 ETA = {"identity": O.IDENTITY, "mean": O.MEAN, "mean_slope": O.MEAN_SLOPE}
 
 

@@ -123,7 +123,7 @@ def test_gradient_vs_oracle(lib, prec):
 
 @pytest.mark.parametrize("grid", ["graded", "covering"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_dmat_vs_oracle(lib, grid, prec, variant):
     """Row-normwise error, except for the FP32 form on the covering grid: there
     two bins take nearly every pair and the projection cancels almost all of
