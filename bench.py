@@ -312,17 +312,22 @@ def issued_valu_frac(kernel, source, ms):
     return rec["insts_valu_per_launch"] * 64 / (ms / 1e3) / PEAK_VALU_LANE_OPS
 
 
+XI_KERNELS = {0: "xi_kernel<float, 256, false, true, false, false>", 1: "xi_kernel<float, 512, false, true, false, false>",
+              2: "xi_kernel<float, 256, true, true, false, false>", 3: "xi_kernel<float, 512, true, true, false, false>"}
+
+
 def xi_roofline(r, peaks):
     ops = 6.0 * r["cand"] + 7.0 * r["xi_pairs"]
     t = r["ms_xi_kernel"] / 1e3
     achieved = ops / t / 1e12
-    return dict(kernel=f"xi_kernel<float> ({r['xi_variant_name']})", bound="alu", achieved=achieved,
+    kname = XI_KERNELS.get(r["xi_variant"], "xi_kernel")
+    return dict(kernel=f"{kname} ({r['xi_variant_name']})", bound="alu", achieved=achieved,
                 peak=PEAK_VALU_LANE_OPS / 1e12, unit="TFLOP/s", frac=achieved / (PEAK_VALU_LANE_OPS / 1e12),
-                traffic=measured_traffic("xi_kernel", "k_xi.hip"),
+                traffic=measured_traffic(kname, "k_xi.hip"),
                 work=f"6 ops x {r['cand']} candidate pairs + 7 ops x {r['xi_pairs']} in-grid pairs "
                      f"(lane-operations; peak = a 64-lane add per SIMD every two clocks)",
                 frac_of_measured_add_rate=ops / t / peaks["valu_add_f32"] if peaks else None,
-                issued_valu_frac=issued_valu_frac("xi_kernel", "k_xi.hip", r["ms_xi_kernel"]),
+                issued_valu_frac=issued_valu_frac(kname, "k_xi.hip", r["ms_xi_kernel"]),
                 ms=r["ms_xi_kernel"])
 
 
@@ -356,15 +361,24 @@ def xi3_roofline(entries, ms, peaks):
     return out
 
 
+# FP32 distortion kernels by variant index: the 8-wave kernel, the two
+# single-wave tiles, and the hybrid launch of both single-wave kernels
+D_KERNELS = {0: ["dmat_kernel<float, 512, true>"], 1: ["dmat_wave_kernel<float, 10, 4, 1, true>"],
+             2: ["dmat_wave_kernel<float, 8, 4, 2, true>"],
+             3: ["dmat_wave_kernel<float, 10, 4, 1, true>", "dmat_wave_kernel<float, 8, 4, 2, true>"]}
+
+
 def d_roofline(r):
     flops = 2.0 * r["d_fmas"]
     achieved = flops / (r["ms_d_kernel"] / 1e3) / 1e12
-    kname = "dmat_kernel" if r["d_variant"] == 0 else "dmat_wave_kernel"
+    names = D_KERNELS.get(r["d_variant"], [])
     src = "k_dmat.hip" if r["d_variant"] == 0 else "k_dmat_wave.hip"
+    parts = [measured_traffic(n, src) for n in names]
+    traffic = sum(parts) if parts and all(p is not None for p in parts) else None
     # the FP32 form's contraction runs as FP32 MFMA steps: its own dtype's peak
-    return dict(kernel=f"{kname}<float> ({r['d_variant_name']})", bound="mfma", achieved=achieved,
+    return dict(kernel=" + ".join(names) + f" ({r['d_variant_name']})", bound="mfma", achieved=achieved,
                 peak=PEAK_MFMA_F32 / 1e12, unit="TFLOP/s", frac=achieved / (PEAK_MFMA_F32 / 1e12),
-                traffic=measured_traffic(kname, src),
+                traffic=traffic,
                 work=f"2 x {r['d_fmas']} FMAs of the sparse row outer products and the rank-4 pair term "
                      f"(FP32 MFMA steps into FP32 accumulators, added to the FP64 numerator once per run)",
                 ms=r["ms_d_kernel"])
