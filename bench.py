@@ -341,7 +341,7 @@ def xi_lds_roofline(r, peaks):
     t = r["ms_xi_kernel"] / 1e3
     p = float(r["xi_pairs"])
     busy = 2.0 * p / peaks["lds_add_f64"] + p / peaks["lds_add_u32"]
-    return dict(kernel=f"xi_kernel<float> ({r['xi_variant_name']})", bound="lds_atomic",
+    return dict(kernel=f"{XI_KERNELS.get(r['xi_variant'], 'xi_kernel')} ({r['xi_variant_name']})", bound="lds_atomic",
                 achieved=2.0 * p / t / 1e12, peak=peaks["lds_add_f64"] / 1e12, unit="T FP64 adds/s",
                 frac=busy / t, work=f"2 FP64 + 1 u32 LDS adds x {r['xi_pairs']} in-grid pairs",
                 peak_u32=peaks["lds_add_u32"] / 1e12, ms=r["ms_xi_kernel"])
