@@ -9,8 +9,10 @@
 // Work item = one forest f with all of its neighbours (a symmetric neighbour
 // list), so every contribution to f's pixels is summed inside one workgroup
 // and written with plain stores.  Lanes own pixels i of f; the neighbour's
-// pixels j are wave-uniform (scalar loads); the bin of each pair comes from
-// the shared binner and gamma, gamma*xi are gathered from an LDS table.  Waves
+// pixels j are wave-uniform (scalar loads, several records at a time); the
+// bin of each pair comes from the shared binner, and over a run of
+// consecutive pixels j in one bin the lane sums w_j delta_j and w_j before it
+// gathers gamma, gamma*xi from an LDS table once for the run.  Waves
 // split the neighbours; each lane sums a neighbour's contributions in the
 // working precision, adds them to FP64 registers, and the waves combine their
 // FP64 sums through LDS.
@@ -37,6 +39,29 @@ __device__ __forceinline__ Rec64 load_u(const Rec64* p) {
   const bw_d4 v = *(const __attribute__((address_space(4))) bw_d4*)p;
   return Rec64{v.x, v.y, v.z, v.w};
 }
+// Four (FP32) or two (FP64) consecutive records with one scalar load.
+template <typename R> struct BwBatch;
+typedef float bw_f16 __attribute__((ext_vector_type(16)));
+typedef double bw_d8 __attribute__((ext_vector_type(8)));
+template <> struct BwBatch<Rec32> {
+  static constexpr int N = 4;
+  Rec32 r[4];
+  __device__ __forceinline__ void load(const Rec32* p) {
+    const bw_f16 v = *(const __attribute__((address_space(4))) bw_f16*)p;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) r[u] = Rec32{v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]};
+  }
+};
+template <> struct BwBatch<Rec64> {
+  static constexpr int N = 2;
+  Rec64 r[2];
+  __device__ __forceinline__ void load(const Rec64* p) {
+    const bw_d8 v = *(const __attribute__((address_space(4))) bw_d8*)p;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) r[u] = Rec64{v[4 * u], v[4 * u + 1], v[4 * u + 2], v[4 * u + 3]};
+  }
+};
+
 __device__ __forceinline__ double load_ud(const double* p) {
   return *(const __attribute__((address_space(4))) double*)p;
 }
@@ -112,9 +137,11 @@ __global__ __launch_bounds__(BLOCK) void xi_bwd_kernel(BwdArgs a) {
           const T s = (T)s64, c = (T)c64;
           const T bsep = sizeof(T) == 4 ? (T)(dc2 * s64) : (T)0;
           const Rec* __restrict__ rg = recs + gi.pix0;
-          T p1 = 0, p2 = 0;
-          for (int j = 0; j < gi.npix; ++j) {
-            const Rec rj = load_u(rg + j);
+          // runs of consecutive pixels j in one bin: their w delta and w are
+          // summed first and gamma, gamma xi gathered once per run
+          T p1 = 0, p2 = 0, awd = 0, aw = 0;
+          int cur = -1;
+          auto pair = [&](const Rec& rj, int j) __attribute__((always_inline)) {
             T rp, rt;
             separations(ri.d, rj.d, c, s, bsep, rp, rt);
             const int L = K.bin(rp, rt, [&](double& rp64, double& rt64) {
@@ -125,10 +152,30 @@ __global__ __launch_bounds__(BLOCK) void xi_bwd_kernel(BwdArgs a) {
                 rt64 = rt;
               }
             });
-            if (L >= 0) {
-              p1 += tab[2 * L] * rj.wd;
-              p2 += tab[2 * L + 1] * rj.w;
+            if (L != cur) {
+              if (cur >= 0) {
+                p1 += tab[2 * cur] * awd;
+                p2 += tab[2 * cur + 1] * aw;
+              }
+              cur = L;
+              awd = 0;
+              aw = 0;
             }
+            awd += rj.wd;
+            aw += rj.w;
+          };
+          constexpr int NBAT = BwBatch<Rec>::N;
+          int j = 0;
+          for (; j + NBAT <= gi.npix; j += NBAT) {
+            BwBatch<Rec> b;
+            b.load(rg + j);
+#pragma unroll
+            for (int u = 0; u < NBAT; ++u) pair(b.r[u], j + u);
+          }
+          for (; j < gi.npix; ++j) pair(load_u(rg + j), j);
+          if (cur >= 0) {
+            p1 += tab[2 * cur] * awd;
+            p2 += tab[2 * cur + 1] * aw;
           }
           s1 += (double)p1;
           s2 += (double)p2;
