@@ -106,6 +106,41 @@ def test_ragged_and_degenerate(lib, prec):
         check(out, ref, prec, f"ragged v{v}")
 
 
+def _reordered(F, seed):
+    """F with the pixels of each forest put in decreasing distance (every third
+    forest), shuffled (the next) or left increasing with runs of repeated
+    distances (the rest)."""
+    rng = np.random.default_rng(seed)
+    F = F.copy()
+    perm = np.arange(F.n_pix)
+    for f in range(F.n_forests):
+        sl = F.forest_slice(f)
+        k = np.arange(sl.start, sl.stop)
+        if f % 3 == 0:
+            perm[sl] = k[::-1]
+        elif f % 3 == 1:
+            perm[sl] = rng.permutation(k)
+        elif k.size > 4:
+            F.dist[k[1:-1:3]] = F.dist[k[0:-2:3]]
+    for name in ("dist", "delta", "weight", "loglam"):
+        setattr(F, name, getattr(F, name)[perm].copy())
+    return F
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pixel_order_within_forests(lib, prec):
+    """Nothing in the kernels assumes a forest's pixels sorted by distance:
+    pixels in decreasing, shuffled or repeated-distance order give the oracle's
+    sums, in the run-length and deterministic forms too."""
+    F0, G, _ = make_config(0, seed=11)
+    F = _reordered(F0, 11)
+    ref = O.xi_sums(F, G)
+    for v in (0, 3):
+        for det in (False, True):
+            out = run_xi(lib, F, G, precision=prec, variant=v, autotune=False, deterministic=det)
+            check(out, ref, prec, f"reordered v{v} det={det}")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_empty_and_single(lib, prec):
     F, G, _ = make_config(0, seed=1)
