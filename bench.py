@@ -363,9 +363,9 @@ def xi3_roofline(entries, ms, peaks):
 
 # FP32 distortion kernels by variant index: the 8-wave kernel, the two
 # single-wave tiles, and the hybrid launch of both single-wave kernels
-D_KERNELS = {0: ["dmat_kernel<float, 512, true>"], 1: ["dmat_wave_kernel<float, 10, 4, 1, true>"],
-             2: ["dmat_wave_kernel<float, 8, 4, 2, true>"],
-             3: ["dmat_wave_kernel<float, 10, 4, 1, true>", "dmat_wave_kernel<float, 8, 4, 2, true>"]}
+D_KERNELS = {0: ["dmat_kernel<float, 512, true>"], 1: ["dmat_wave_kernel<float, 10, 4, 2, true, 2>"],
+             2: ["dmat_wave_kernel<float, 8, 4, 2, true, 1>"],
+             3: ["dmat_wave_kernel<float, 10, 4, 2, true, 2>", "dmat_wave_kernel<float, 8, 4, 2, true, 1>"]}
 
 
 def d_roofline(r):

@@ -166,6 +166,21 @@ constexpr int tri_row(int j) {
   return by;
 }
 
+// Two waves per workgroup: block (bx, by) of the upper triangle belongs to
+// wave bx & 1, in slot wrow_base(by) + (bx >> 1) of that wave (row by holds
+// by / 2 + 1 slots; wave 1 leaves the last one of an even row unused).  Both
+// waves then share the row structure, and a slot's column is 2 t + wave.
+constexpr int wrow_base(int by) {
+  int n = 0;
+  for (int y = 0; y < by; ++y) n += y / 2 + 1;
+  return n;
+}
+constexpr int wslot_row(int s) {
+  int by = 0;
+  while (wrow_base(by + 1) <= s) ++by;
+  return by;
+}
+
 // f(WIC<I>{}) for I = B .. E - 1: indices into register arrays stay
 // compile-time constants whatever the loop unroller decides.
 template <int B, int E, typename F>
@@ -184,13 +199,17 @@ struct WPair {
   double fdmin, fdmax, gdmin, gdmax;
 };
 
-template <typename T, int NB, int PMAX, int WPE, bool ZLO>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void dmat_wave_kernel(DmatArgs a) {
+template <typename T, int NB, int PMAX, int WPE, bool ZLO, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void dmat_wave_kernel(DmatArgs a) {
+  static_assert(NW == 1 || NW == 2, "one or two waves per workgroup");
   using Form = WForm<T>;
   using Acc = typename Form::Acc;
   using Rec = typename Form::Rec;
   constexpr bool kF32 = sizeof(T) == 4;
   constexpr int MB = NB * (NB + 1) / 2;  // accumulator blocks
+  constexpr int MBW = NW == 1 ? MB : wrow_base(NB);  // accumulator slots of one wave
+  constexpr int NBUF = NW == 1 ? 2 : 3;    // row-histogram buffers
+  constexpr int NH = 2 / NW;               // rows of a step binned by one wave
   constexpr int NX = NB / 2, NY = NB - NX;  // rectangle passes: NX x NY blocks
   constexpr int SB = NB;                 // storage blocks per row and component
   constexpr int SW = 16 * SB + 16;       // storage stride (padded against bank conflicts)
@@ -199,16 +218,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   constexpr int GB = 4;                  // tile blocks staged per flush group
   // row histograms in FP64 in both forms: on gfx950 an LDS FP64 atomic add
   // runs ~24x faster than an FP32 one (measured by lya_measure_peaks)
-  __shared__ double buf[2][4][SW];       // [buffer][2 row + l][storage bin]
-  __shared__ T stg[GB * 256];            // flush stage: GB blocks of 16 x 16
-  __shared__ uint8_t slot_by[MB];        // block column of each accumulator slot
+  __shared__ double buf[NBUF][4][SW];    // [buffer][2 row + l][storage bin]
+  __shared__ T stg[NW][GB * 256];        // flush stage of each wave: GB blocks of 16 x 16
+  __shared__ uint32_t smask[3][NW];      // two waves: block mask of each wave's row, per buffer
+  __shared__ int64_t s_item;             // two waves: the work item
+  __shared__ uint8_t slot_by[MBW];       // block column of each accumulator slot
+  __shared__ uint8_t slot_t[MBW];        // two waves: the slot's row position t (block row 2 t + wave)
   __shared__ double wdacc[16 * NB];      // w_A of the run (diagonal passes)
   __shared__ int32_t otab[16 * SB];      // output bin of each storage bin of the pass (-1 past the window)
   constexpr int RCH = 128;               // rows of a sweep staged at a time
   __shared__ T srow[3][RCH];             // d, w, w a of the staged rows
   __shared__ double srowD[RCH];          // FP64 distance of the staged rows (edge guard)
 
-  const int lane = threadIdx.x;
+  const int lane = NW == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lk = lane >> 4, lm = lane & 15;
   const int rpar = lk >> 1, comp = lk & 1;  // operand slot of this lane: row of the step, l
 
@@ -218,14 +241,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   const Rec* __restrict__ recs;
   if constexpr (kF32) recs = a.drec32; else recs = a.drec64;
 
-  for (int e = lane; e < 2 * 4 * SW; e += 64) (&buf[0][0][0])[e] = 0.0;
-  for (int e = lane; e < 16 * NB; e += 64) wdacc[e] = 0.0;
-  for (int j = lane; j < MB; j += 64) slot_by[j] = (uint8_t)tri_row(j);
+  for (int e = threadIdx.x; e < NBUF * 4 * SW; e += 64 * NW) (&buf[0][0][0])[e] = 0.0;
+  for (int e = threadIdx.x; e < 16 * NB; e += 64 * NW) wdacc[e] = 0.0;
+  for (int j = threadIdx.x; j < MBW; j += 64 * NW) {
+    if constexpr (NW == 1) {
+      slot_by[j] = (uint8_t)tri_row(j);
+    } else {
+      slot_by[j] = (uint8_t)wslot_row(j);
+      slot_t[j] = (uint8_t)(j - wrow_base(wslot_row(j)));
+    }
+  }
   unsigned long long n_in = 0, n_lost = 0, nalg = 0;  // statistics only
 
-  Acc acc[MB];
+  Acc acc[MBW];
 #pragma unroll
-  for (int j = 0; j < MB; ++j) acc[j] = Acc{0, 0, 0, 0};
+  for (int j = 0; j < MBW; ++j) acc[j] = Acc{0, 0, 0, 0};
   T h0[SB], h1[SB];  // H partials: lane (row r, l, i) sums w_r p^k_r R^l_r[16 b + i], k = 0, 1
 #pragma unroll
   for (int b = 0; b < SB; ++b) h0[b] = h1[b] = (T)0;
@@ -238,25 +268,50 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   // the pass type folded into two block masks up front, so that each block
   // pair costs one scalar bit test: a rectangle pass keeps the pairs with
   // bx < NX <= by, a diagonal pass every bx <= by
+  // With two waves, each issues the steps of its own blocks, (2 t + wv, by).
   auto tile_steps = [&](uint32_t u, bool diag, int ymin, const T* A, const T* B) __attribute__((always_inline)) {
     constexpr uint32_t kXMask = (1u << NX) - 1u;
     const uint32_t ux = diag ? u : (u & kXMask), uy = diag ? (u & ~((1u << ymin) - 1u)) : (u & ~kXMask);
-    static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
-      constexpr int by = decltype(BY)::value;
-      if (!((uy >> by) & 1u)) return;
-      static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
-        constexpr int bx = decltype(BX)::value;
-        constexpr int j = by * (by + 1) / 2 + bx;
-        if ((ux >> bx) & 1u) acc[j] = Form::step(A[bx], B[by], acc[j]);
+    if constexpr (NW == 1) {
+      static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+        constexpr int by = decltype(BY)::value;
+        if (!((uy >> by) & 1u)) return;
+        static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
+          constexpr int bx = decltype(BX)::value;
+          constexpr int j = by * (by + 1) / 2 + bx;
+          if ((ux >> bx) & 1u) acc[j] = Form::step(A[bx], B[by], acc[j]);
+        });
       });
-    });
+    } else {
+      const uint32_t uxw = ux >> wv;  // bit 2 t: block 2 t + wv
+      T Aw[(NB + 1) / 2];
+#pragma unroll
+      for (int t = 0; t < (NB + 1) / 2; ++t) Aw[t] = (2 * t + 1 < NB && wv) ? A[2 * t + 1] : A[2 * t];
+      static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+        constexpr int by = decltype(BY)::value;
+        if (!((uy >> by) & 1u)) return;
+        static_for<0, by / 2 + 1>([&](auto TT) __attribute__((always_inline)) {
+          constexpr int t = decltype(TT)::value;
+          constexpr int sl = wrow_base(by) + t;
+          const bool on = (2 * t == by) ? (wv == 0 && (uxw >> (2 * t)) & 1u) : ((uxw >> (2 * t)) & 1u);
+          if (on) acc[sl] = Form::step(Aw[t], B[by], acc[sl]);
+        });
+      });
+    }
   };
 
   for (;;) {
     __syncthreads();
-    unsigned itv = 0;
-    if (lane == 0) itv = atomicAdd(a.counter, 1u);
-    const int64_t it = (int64_t)(unsigned)__builtin_amdgcn_readlane((int)itv, 0);
+    int64_t it;
+    if constexpr (NW == 1) {
+      unsigned itv = 0;
+      if (lane == 0) itv = atomicAdd(a.counter, 1u);
+      it = (int64_t)(unsigned)__builtin_amdgcn_readlane((int)itv, 0);
+    } else {
+      if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.counter, 1u);
+      __syncthreads();
+      it = s_item;
+    }
     if (it >= a.n_items) break;
     const int64_t k0 = it * a.item_stride * a.chunk;
     const int64_t k1 = min(a.n_pairs, k0 + (int64_t)a.chunk);
@@ -284,7 +339,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
       for (int ps = 0; ps < npass; ++ps) {
         const WPass P = pass_of<NB, NX, NY>(ps, nblk);
         __syncthreads();  // the previous pass's flush has read the table
-        for (int e = lane; e < 16 * SB; e += 64) {
+        for (int e = threadIdx.x; e < 16 * SB; e += 64 * NW) {
           const int sb = e >> 4;
           const bool ypart = !P.diag && sb >= NX;
           const int wb = ypart ? P.y0 + (sb - NX) : P.x0 + sb;
@@ -394,7 +449,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
               if (cb == rbase) return;
               rbase = cb;
               __syncthreads();
-              for (int i = lane; i < RCH; i += 64) {
+              for (int i = threadIdx.x; i < RCH; i += 64 * NW) {
                 const int rr = cb + i;
                 T d = 0, w = 0, wa = 0;
                 double D = 0.0;
@@ -421,15 +476,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
             auto bin_chunk = [&](auto NKC, int c0, int r, int bsel, const T* rdv, bool row1ok)
                 __attribute__((always_inline)) -> uint32_t {
               constexpr int NKE = decltype(NKC)::value;
-              int L[2][NKE];
-              bool inr[2][NKE], need[2][NKE];
+              int L[NH][NKE];
+              bool inr[NH][NKE], need[NH][NKE];
               bool anyneed = false;
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
+              for (int hi = 0; hi < NH; ++hi) {
+                const int h = NW == 1 ? hi : wv;  // row r + h
 #pragma unroll
                 for (int k = 0; k < NKE; ++k) {
                   T rp, rt;
-                  separations(rdv[h], od[k], c, s, bsep, rp, rt);
+                  separations(rdv[hi], od[k], c, s, bsep, rp, rt);
                   T xp, xt;
                   if constexpr (ZLO) {
                     xp = rp * K.invp;
@@ -449,42 +505,44 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                     gt &= !(K.zlt & (rxt == (T)0));
                   }
                   // (clamped before the conversion: out-of-range lanes are discarded below)
-                  L[h][k] = (int)__umul24((unsigned)(int)fmin(xt, (T)65536), (unsigned)NP) + (int)fmin(xp, (T)65536);
-                  inr[h][k] = in;
-                  need[h][k] = in & (gp | gt);
-                  anyneed |= need[h][k];
+                  L[hi][k] = (int)__umul24((unsigned)(int)fmin(xt, (T)65536), (unsigned)NP) + (int)fmin(xp, (T)65536);
+                  inr[hi][k] = in;
+                  need[hi][k] = in & (gp | gt);
+                  anyneed |= need[hi][k];
                 }
               }
               if (__ballot(anyneed)) {
                 // within rounding of an edge: the FP64 separations against the edges
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int hi = 0; hi < NH; ++hi) {
+                const int h = NW == 1 ? hi : wv;  // row r + h
 #pragma unroll
                   for (int k = 0; k < NKE; ++k) {
-                    if (need[h][k]) {
+                    if (need[hi][k]) {
                       double rp64, rt64;
                       if constexpr (kF32) {
                         separations64(srowD[r + h - rbase], recs[poth0 + c0 + lane * ppl + k].D, pr.c, pr.s,
                                       rp64, rt64);
                       } else {
-                        separations(rdv[h], od[k], c, s, bsep, rp64, rt64);
+                        separations(rdv[hi], od[k], c, s, bsep, rp64, rt64);
                       }
                       const int kp = bin_exact(rp64, K.ep, NP, (int)floor((rp64 - a.g.e0_par) * a.g.inv_par));
                       const int kt = bin_exact(rt64, K.et, NT, (int)floor((rt64 - a.g.e0_perp) * a.g.inv_perp));
-                      L[h][k] = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
+                      L[hi][k] = (kp >= 0 && kt >= 0) ? (int)__umul24((unsigned)kt, (unsigned)NP) + kp : -1;
                     }
                   }
                 }
               }
               uint32_t bits = 0;
-              int sidx[2][NKE];
-              bool ok[2][NKE];
+              int sidx[NH][NKE];
+              bool ok[NH][NKE];
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
+              for (int hi = 0; hi < NH; ++hi) {
+                const int h = NW == 1 ? hi : wv;  // row r + h
 #pragma unroll
                 for (int k = 0; k < NKE; ++k) {
-                  const int w = L[h][k] - base_L;
-                  const bool ing = inr[h][k] & (L[h][k] >= 0);
+                  const int w = L[hi][k] - base_L;
+                  const bool ing = inr[hi][k] & (L[hi][k] >= 0);
                   const bool inw = ing & ((unsigned)w < (unsigned)nwin);
                   if (a.counters) {  // statistics only (uniform)
                     n_lost += (ing & !inw) ? 1ull : 0ull;
@@ -494,28 +552,37 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                   const int wx = w - 16 * P.x0, wy = w - 16 * P.y0;
                   const bool okx = (unsigned)wx < (unsigned)(16 * P.nx);
                   const bool oky = !P.diag & ((unsigned)wy < (unsigned)(16 * P.ny));
-                  sidx[h][k] = okx ? wx : 16 * NX + wy;
-                  ok[h][k] = inw & (okx | oky);
-                  bits |= ok[h][k] ? (1u << ((sidx[h][k] >> 4) & 31)) : 0u;
+                  sidx[hi][k] = okx ? wx : 16 * NX + wy;
+                  ok[hi][k] = inw & (okx | oky);
+                  bits |= ok[hi][k] ? (1u << ((sidx[hi][k] >> 4) & 31)) : 0u;
                 }
               }
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
+              for (int hi = 0; hi < NH; ++hi) {
+                const int h = NW == 1 ? hi : wv;  // row r + h
                 double* hw = &buf[bsel][2 * h][0];
 #pragma unroll
                 for (int k = 0; k < NKE; ++k) {
-                  if (ok[h][k]) {
-                    atomicAdd(&hw[sidx[h][k]], (double)ow[k]);
-                    atomicAdd(&hw[SW + sidx[h][k]], (double)owa[k]);
+                  if (ok[hi][k]) {
+                    atomicAdd(&hw[sidx[hi][k]], (double)ow[k]);
+                    atomicAdd(&hw[SW + sidx[hi][k]], (double)owa[k]);
                   }
                 }
               }
               return bits;
             };
+            // with two waves, wave h bins row r + h; the block masks of the two
+            // rows are combined through LDS after the next barrier
             auto bin_rows = [&](int r, int bsel) -> uint32_t {
               uint32_t bits = 0;
               rows_at(r);
-              const T rdv[2] = {srow[0][r - rbase], srow[0][r + 1 - rbase]};
+              T rdv[NH];
+              if constexpr (NW == 1) {
+                rdv[0] = srow[0][r - rbase];
+                rdv[1] = srow[0][r + 1 - rbase];
+              } else {
+                rdv[0] = srow[0][r + wv - rbase];
+              }
               const bool row1ok = r + 1 < nr;
 #pragma unroll 1
               for (int c0 = 0; c0 < no; c0 += CH) {
@@ -528,7 +595,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
             };
 
             // steps of two rows; the binning of step st + 1 is issued before the
-            // matrix steps of step st, into the other buffer
+            // matrix steps of step st, into the next buffer.  One wave reads and
+            // clears its buffer in one step (two buffers); with two waves, a buffer
+            // read in step st is cleared in step st + 1, after the barrier that
+            // follows both waves' reads, so three buffers rotate.
             const int nsteps = (nr + 1) >> 1;
             uint32_t ucur = 0;
 #pragma unroll 1
@@ -537,7 +607,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
               T wr = 0, wra = 0;
               if (st >= 0) {
                 __syncthreads();  // the rows' LDS adds (and the last clears) are complete
-                const int bsel = st & 1;
+                const int bsel = NW == 1 ? (st & 1) : st % 3;
+                if constexpr (NW == 2) ucur = (uint32_t)__builtin_amdgcn_readfirstlane((int)(smask[bsel][0] | smask[bsel][1]));
                 // this lane's row (rows past nr were staged as zeros)
                 wr = srow[1][2 * st + rpar - rbase];
                 wra = srow[2][2 * st + rpar - rbase];
@@ -547,15 +618,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                 double ov[SB];
 #pragma unroll
                 for (int b = 0; b < SB; ++b) ov[b] = buf[bsel][lk][16 * b + lm];
+                if constexpr (NW == 1) {
 #pragma unroll
-                for (int b = 0; b < SB; ++b) {
-                  op[b] = (T)ov[b];
-                  buf[bsel][lk][16 * b + lm] = 0.0;
+                  for (int b = 0; b < SB; ++b) {
+                    op[b] = (T)ov[b];
+                    buf[bsel][lk][16 * b + lm] = 0.0;
+                  }
+                } else {
+                  const int bclr = (st + 2) % 3;  // read by both waves in step st - 1
+#pragma unroll
+                  for (int b = 0; b < SB; ++b) {
+                    op[b] = (T)ov[b];
+                    if ((b & 1) == wv) buf[bclr][lk][16 * b + lm] = 0.0;
+                  }
                 }
               }
-              const uint32_t unext = st + 1 < nsteps ? bin_rows(2 * st + 2, (st + 1) & 1) : 0u;
+              const uint32_t unext =
+                  st + 1 < nsteps ? bin_rows(2 * st + 2, NW == 1 ? ((st + 1) & 1) : (st + 1) % 3) : 0u;
+              if constexpr (NW == 2) {
+                if (lane == 0) smask[(st + 1) % 3][wv] = unext;
+              }
               if (st >= 0) {
-                if (a.counters) {
+                if (a.counters && wv == 0) {
                   // outer-product FMAs of the sparse rows: 2 per (x, y) of nonzero R bins,
                   // counted per row over the x and y ranges
                   // (a diagonal pass with ymin > 0 counts the pairs reaching block ymin:
@@ -591,7 +675,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
                 for (int b = 0; b < SB; ++b) op[b] *= sq;
                 tile_steps(ucur, P.diag, P.ymin, op, op);
               }
-              ucur = unext;
+              if constexpr (NW == 1) ucur = unext;
+            }
+            if constexpr (NW == 2) {
+              // the last step's buffer, once both waves have read it
+              if (nsteps > 0) {
+                __syncthreads();
+                const int bl = (nsteps - 1) % 3;
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                  if ((b & 1) == wv) buf[bl][lk][16 * b + lm] = 0.0;
+              }
             }
 
           }
@@ -614,16 +708,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
           T hq[SB];
 #pragma unroll
           for (int b = 0; b < SB; ++b) hq[b] = b >= P.ymin ? h0[b] : (T)0;
-          static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
-            constexpr int by = decltype(BY)::value;
-            static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
-              constexpr int bx = decltype(BX)::value;
-              constexpr int j = by * (by + 1) / 2 + bx;
-              constexpr bool in_rect = bx < NX && by >= NX;
-              if (in_rect || P.diag) acc[j] = Form::step(h1[bx], hq[by], acc[j]);
+          if constexpr (NW == 1) {
+            static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+              constexpr int by = decltype(BY)::value;
+              static_for<0, by + 1>([&](auto BX) __attribute__((always_inline)) {
+                constexpr int bx = decltype(BX)::value;
+                constexpr int j = by * (by + 1) / 2 + bx;
+                constexpr bool in_rect = bx < NX && by >= NX;
+                if (in_rect || P.diag) acc[j] = Form::step(h1[bx], hq[by], acc[j]);
+              });
             });
-          });
-          if (a.counters) {
+          } else {
+            T hw[(NB + 1) / 2];
+#pragma unroll
+            for (int t = 0; t < (NB + 1) / 2; ++t) hw[t] = (2 * t + 1 < NB && wv) ? h1[2 * t + 1] : h1[2 * t];
+            static_for<0, NB>([&](auto BY) __attribute__((always_inline)) {
+              constexpr int by = decltype(BY)::value;
+              static_for<0, by / 2 + 1>([&](auto TT) __attribute__((always_inline)) {
+                constexpr int t = decltype(TT)::value;
+                constexpr int sl = wrow_base(by) + t;
+                const int bx = 2 * t + wv;
+                const bool in_rect = bx < NX && by >= NX;
+                if (bx <= by && (in_rect || P.diag)) acc[sl] = Form::step(hw[t], hq[by], acc[sl]);
+              });
+            });
+          }
+          if (a.counters && wv == 0) {
             int hx = 0, qy = 0, hl = 0, ql = 0;
 #pragma unroll
             for (int b = 0; b < SB; ++b) {
@@ -641,7 +751,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
             nalg += 4ull * (unsigned long long)(hx * qy - hl * ql);
           }
           // w_A and the Kronecker term, from H^00 (lanes 0..15)
-          if (P.diag && lk == 0) {
+          if (P.diag && lk == 0 && wv == 0) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
               if (((u_h >> b) & 1u) && b >= P.ymin) wdacc[16 * b + lm] += (double)h0[b];
@@ -652,23 +762,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
         // blocks go through an LDS stage GB at a time, so the atomics are one
         // loop; off-diagonal blocks (bx < by, every block of a rectangle pass)
         // also go to (y, x).
-        static_for<0, (MB + GB - 1) / GB>([&](auto G) __attribute__((always_inline)) {
+        // (with two waves, each flushes its own slots)
+        static_for<0, (MBW + GB - 1) / GB>([&](auto G) __attribute__((always_inline)) {
           constexpr int g = decltype(G)::value;
           __syncthreads();  // the previous group's stage has been read
           static_for<0, GB>([&](auto I) __attribute__((always_inline)) {
             constexpr int jj = g * GB + decltype(I)::value;
-            if constexpr (jj < MB) {
+            if constexpr (jj < MBW) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) stg[(decltype(I)::value * 16 + Form::row(lk, r)) * 16 + lm] = acc[jj][r];
+              for (int r = 0; r < 4; ++r) stg[wv][(decltype(I)::value * 16 + Form::row(lk, r)) * 16 + lm] = acc[jj][r];
               acc[jj] = Acc{0, 0, 0, 0};
             }
           });
           __syncthreads();
           for (int e = lane; e < GB * 256; e += 64) {
             const int jj = g * GB + (e >> 8);
-            if (jj >= MB) break;
-            const double v = -(double)stg[e];
-            const int by = slot_by[jj], bx = jj - by * (by + 1) / 2;
+            if (jj >= MBW) break;
+            const double v = -(double)stg[wv][e];
+            int by, bx;
+            if constexpr (NW == 1) {
+              by = slot_by[jj];
+              bx = jj - by * (by + 1) / 2;
+            } else {
+              by = slot_by[jj];
+              bx = 2 * slot_t[jj] + wv;
+              if (bx > by) continue;  // wave 1's unused slot of an even row (zeros)
+            }
             const int ox = otab[16 * bx + ((e >> 4) & 15)], oy = otab[16 * by + (e & 15)];
             if (v != 0.0 && ox >= 0 && oy >= 0) {
               atomicAdd(&a.dnum[(obase + ox) * nb + oy], v);
@@ -677,7 +796,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
           }
         });
         if (P.diag) {
-          for (int x = lane; x < 16 * P.nx; x += 64) {
+          for (int x = threadIdx.x; x < 16 * P.nx; x += 64 * NW) {
             const double v = wdacc[x];
             const int ox = otab[x];
             if (v != 0.0 && ox >= 0) {
@@ -706,28 +825,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) 
   }
 }
 
-template <typename T, int NB, int PMAX, int WPE>
+template <typename T, int NB, int PMAX, int WPE, int NW>
 hipError_t launch_wave(const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.g.zero_lo_par && a.g.zero_lo_perp)
-    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, true>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, true, NW>), dim3(blocks), dim3(64 * NW), 0, st, a);
   else
-    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, false>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((dmat_wave_kernel<T, NB, PMAX, WPE, false, NW>), dim3(blocks), dim3(64 * NW), 0, st, a);
   return hipGetLastError();
 }
 
-template <typename T, int NB, int PMAX, int WPE>
+template <typename T, int NB, int PMAX, int WPE, int NW>
 int wave_occupancy() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_wave_kernel<T, NB, PMAX, WPE, true>, 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, dmat_wave_kernel<T, NB, PMAX, WPE, true, NW>, 64 * NW, 0) !=
+      hipSuccess)
     return 4;
   return n > 0 ? n : 1;
 }
 
-// tile shapes (blocks per side) of the two variants per form: the larger tile
-// runs one wave per SIMD with its accumulators in AGPRs (FP32: 160-bin
-// windows, three k_perp rows of 50 bins, in one pass), the smaller two waves
-// per SIMD with VGPR accumulators; both are the largest that compile without
-// register spills
+// The two variants per form.  FP32: the larger tile (160-bin windows, three
+// k_perp rows of 50 bins, in one pass) is split between the two waves of a
+// workgroup, each holding half of its accumulator blocks and binning one of
+// the two rows of a step, so that two waves fit on a SIMD (one wave holding
+// the whole tile in AGPRs, one wave per SIMD, took 6 % longer); the smaller
+// tile runs one wave per workgroup, two per SIMD.  FP64: the larger tile runs
+// one wave per SIMD (split between two waves it spills registers and took 5 %
+// longer), the smaller two.  All are the largest that compile without (or
+// with a few bytes of) register spills.
 constexpr int kNB32[2] = {10, 8};
 constexpr int kNB64[2] = {7, 5};
 constexpr int kPMax = 4;    // FP32: 256 pixels of the other forest in registers at a time
@@ -740,22 +864,23 @@ int dmat_wave_num_variants() { return 2; }
 int dmat_wave_tile_blocks(int v, int precision) { return precision == LYA_FP64 ? kNB64[v] : kNB32[v]; }
 
 const char* dmat_wave_variant_name(int v) {
-  static const char* const names[2] = {"w64-sym-big", "w64-sym-small"};
+  static const char* const names[2] = {"sym-big", "sym-small"};
   return (v >= 0 && v < 2) ? names[v] : "?";
 }
 
 hipError_t launch_dmat_wave(int v, int precision, const DmatArgs& a, int blocks, hipStream_t st) {
   if (a.n_items == 0) return hipSuccess;
   if (precision == LYA_FP64)
-    return v == 0 ? launch_wave<double, kNB64[0], kPMax64, 1>(a, blocks, st)
-                  : launch_wave<double, kNB64[1], kPMax64, 2>(a, blocks, st);
-  return v == 0 ? launch_wave<float, kNB32[0], kPMax, 1>(a, blocks, st) : launch_wave<float, kNB32[1], kPMax, 2>(a, blocks, st);
+    return v == 0 ? launch_wave<double, kNB64[0], kPMax64, 1, 1>(a, blocks, st)
+                  : launch_wave<double, kNB64[1], kPMax64, 2, 1>(a, blocks, st);
+  return v == 0 ? launch_wave<float, kNB32[0], kPMax, 2, 2>(a, blocks, st)
+                : launch_wave<float, kNB32[1], kPMax, 2, 1>(a, blocks, st);
 }
 
 int dmat_wave_blocks_per_cu(int v, int precision) {
   if (precision == LYA_FP64)
-    return v == 0 ? wave_occupancy<double, kNB64[0], kPMax64, 1>() : wave_occupancy<double, kNB64[1], kPMax64, 2>();
-  return v == 0 ? wave_occupancy<float, kNB32[0], kPMax, 1>() : wave_occupancy<float, kNB32[1], kPMax, 2>();
+    return v == 0 ? wave_occupancy<double, kNB64[0], kPMax64, 1, 1>() : wave_occupancy<double, kNB64[1], kPMax64, 2, 1>();
+  return v == 0 ? wave_occupancy<float, kNB32[0], kPMax, 2, 2>() : wave_occupancy<float, kNB32[1], kPMax, 2, 1>();
 }
 
 }  // namespace lya

@@ -731,7 +731,7 @@ lya_status lya_xi_noalloc(lya_context* ctx, const lya_forests* F, const lya_grid
 const char* lya_variant_name(int32_t kernel, int32_t variant) {
   if (kernel == 0) return (variant >= 0 && variant < xi_num_variants()) ? xi_variant_name(variant) : nullptr;
   if (kernel == 1) {
-    if (variant == dmat_num_variants()) return "hybrid: w64-sym-small for one-tile windows, w64-sym-big for wider ones";
+    if (variant == dmat_num_variants()) return "hybrid: sym-small for one-tile windows, sym-big for wider ones";
     return (variant >= 0 && variant < dmat_num_variants()) ? dmat_variant_name(variant) : nullptr;
   }
   return nullptr;
