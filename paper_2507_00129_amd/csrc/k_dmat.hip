@@ -681,7 +681,7 @@ __global__ void finalize_dmat_kernel(double* d, const double* wd, int64_t n_rows
 
 }  // namespace
 
-// variants: this file's kernel, then the single-wave kernels (k_dmat_wave.hip)
+// variants: this file's kernel, then the one- and two-wave kernels (k_dmat_wave.hip)
 int dmat_num_variants() { return kNumVariants + dmat_wave_num_variants(); }
 const char* dmat_variant_name(int v) {
   if (v >= kNumVariants) return dmat_wave_variant_name(v - kNumVariants);

@@ -1,4 +1,4 @@
-// Distortion matrix, single-wave form (Sec. 2.2, eq. distortion).
+// Distortion matrix, one- and two-wave form (Sec. 2.2, eq. distortion).
 //
 // With eta_ii' = delta_ii' - p_i . q_i', p = (1, a), q = w p (1/W, 1/S) per
 // forest (a = L - Lbar), the numerator of one kept forest pair (f, g) is
@@ -14,8 +14,9 @@
 // squares too: num is symmetric.  Only the blocks on and above the diagonal
 // of a tile are accumulated; the flush writes each off-diagonal block twice.
 //
-// One wavefront is one workgroup: it owns its accumulator tile in registers,
-// a small LDS area, and needs no barrier with other waves.  It takes work
+// A workgroup of one wave (or two, below) owns its accumulator tile in
+// registers and a small LDS area, and shares nothing with other workgroups.
+// It takes work
 // items (chunks of the window-sorted pair list) from an atomic counter; the
 // pairs of a chunk that share a window (the k_perp rows their r_perp range
 // spans) add into one tile, flushed to the global FP64 numerator once per
@@ -25,11 +26,16 @@
 // to the rows' histograms in LDS; the wave then reads the histograms back in
 // MFMA operand layout, scaled by sqrt(w_row c_l), and issues one step for
 // every tile block (bx <= by) that the union of the two rows' block masks
-// covers.  Two LDS buffers alternate, so the binning of the next two rows is
-// issued while the matrix core works on the current ones.  The pair
+// covers.  Two LDS buffers alternate (three rotate with two waves), so the
+// binning of the next two rows is issued while the matrix core works on the
+// current ones.  The pair
 // histograms H are summed in registers from the operands of the f rows; after
 // them, one more step per block adds the H term (K = 4 is kl) and the
 // Kronecker term w_A goes to an FP64 LDS accumulator.
+//
+// Two waves per workgroup (NW = 2) split the tile and the binning: wave w
+// keeps the blocks (bx, by) with bx & 1 = w and bins row r + w of each step;
+// the two rows' block masks meet in LDS after the step's barrier.
 //
 // Tiles: NB x NB blocks of 16 window bins (the upper triangle, NB (NB+1)/2
 // accumulators).  Windows wider than NB blocks take several passes over the

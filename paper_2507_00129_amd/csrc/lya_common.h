@@ -331,9 +331,9 @@ int peak_block();
 int peak_unroll_lds();
 int peak_unroll_valu();
 
-// the single-wave symmetric-tile D kernel (two tile shapes per form)
+// the symmetric-tile D kernels of one or two waves (two tile shapes per form)
 int dmat_wave_num_variants();
-int dmat_wave_tile_blocks(int v, int precision);  // tile blocks per side of a single-wave variant
+int dmat_wave_tile_blocks(int v, int precision);  // tile blocks per side of a symmetric-tile variant
 const char* dmat_wave_variant_name(int v);
 hipError_t launch_dmat_wave(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
 int dmat_wave_blocks_per_cu(int variant, int precision);

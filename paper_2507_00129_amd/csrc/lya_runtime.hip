@@ -1081,7 +1081,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     a.dnum = dmat;
     a.wd = wsum_d;
     // variants: the kernels of dmat_num_variants(), then the hybrid launch:
-    // the pairs whose window fits the small single-wave tile in one pass (the
+    // the pairs whose window fits the small tile in one pass (the
     // sorted list puts them last) go to that kernel, two waves per SIMD, and
     // the wider windows to the large-tile kernel
     const int kHybrid = dmat_num_variants();
@@ -1092,7 +1092,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
         HIP_TRY(launch_dmat(v, o->precision, args, dmat_blocks_per_cu(v, o->precision) * ctx->n_cu, st));
         return LYA_OK;
       }
-      constexpr int kSmall = 2, kBig = 1;  // dmat variants of the small and the large single-wave tile
+      constexpr int kSmall = 2, kBig = 1;  // dmat variants of the small and the large symmetric tile
       if (n_wide < 0) {
         const int max_span = 16 * dmat_wave_tile_blocks(kSmall - 1, o->precision) / gd.n_par;
         int64_t* dn;
