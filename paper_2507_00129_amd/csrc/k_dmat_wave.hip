@@ -216,6 +216,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
   constexpr int MBW = NW == 1 ? MB : wrow_base(NB);  // accumulator slots of one wave
   constexpr int NBUF = NW == 1 ? 2 : 3;    // row-histogram buffers
   constexpr int NH = 2 / NW;               // rows of a step binned by one wave
+  constexpr bool kTrim = NW == 2 || !kF32;  // per-pass pixel ranges (below)
   constexpr int NX = NB / 2, NY = NB - NX;  // rectangle passes: NX x NY blocks
   constexpr int SB = NB;                 // storage blocks per row and component
   constexpr int SW = 16 * SB + 16;       // storage stride (padded against bank conflicts)
@@ -373,33 +374,76 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
           // pixels within r_par reach of the other forest's extent: the first and
           // last such pixel of each forest bound the rows and the lanes' pixels
           const double reach = a.g.emax_par / pr.c * (1.0 + 1e-12) + 1e-9;
-          int rng[4];
+          // A window of several passes (two-wave kernel; in the one-wave kernels the
+          // extra registers cost more than the trimming saves): pixels are kept
+          // only where they can reach
+          // the pass's blocks.  A pixel at distance D against the other forest's
+          // extent [Omin, Omax] has r_perp in [(D + Omin) s, (D + Omax) s]; window
+          // blocks B0 .. B1 hold k_perp rows kt0 + floor(16 B0 / NP) .. kt0 +
+          // floor((16 B1 + 15) / NP), r_perp in [e(B0), e(B1)) of the FP64 edges,
+          // and every bin decision agrees with the FP64 edge comparison.  Both
+          // forests' pixels are kept where they reach any block of the pass (the
+          // f rows also feed H, which every block needs); the g rows of the second
+          // sweep only where they reach both ranges of a rectangle pass (a row's
+          // outer product there pairs a bin of each range), or the blocks from
+          // ymin on of a diagonal pass.  Widened by a relative 1e-9.  Not in the
+          // first pass of a counted launch, which counts the in-window pairs.
+          double ulo[2] = {-INFINITY, -INFINITY}, uhi[2] = {INFINITY, INFINITY};
+          double rlo = -INFINITY, rhi = INFINITY;
+          if (kTrim && npass > 1 && !(a.counters && ps == 0) && pr.s > 0.0) {
+            auto edge_lo = [&](int B) { return K.et[kt0 + min(span - 1, (16 * B) / NP)]; };
+            auto edge_hi = [&](int B) { return K.et[kt0 + min(span - 1, (16 * B + 15) / NP) + 1]; };
+            const int u1 = P.diag ? P.x0 + P.nx - 1 : P.y0 + P.ny - 1;
+            const double el = edge_lo(P.x0) * (1.0 - 1e-9) / pr.s, eh = edge_hi(u1) * (1.0 + 1e-9) / pr.s;
+            ulo[0] = el - pr.gdmax - 1e-6;  // f against g
+            uhi[0] = eh - pr.gdmin + 1e-6;
+            ulo[1] = el - pr.fdmax - 1e-6;  // g against f
+            uhi[1] = eh - pr.fdmin + 1e-6;
+            rlo = edge_lo(P.diag ? P.x0 + P.ymin : P.y0) * (1.0 - 1e-9) / pr.s - pr.fdmax - 1e-6;
+            rhi = edge_hi(P.x0 + P.nx - 1) * (1.0 + 1e-9) / pr.s - pr.fdmin + 1e-6;
+          }
+          int rng[6];
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const int n = side ? pr.ng : pr.nf;
             const int64_t p0 = side ? pr.pg : pr.pf;
             const double lo_d = (side ? pr.fdmin : pr.gdmin) - reach, hi_d = (side ? pr.fdmax : pr.gdmax) + reach;
-            int first = 0x7fffffff, last = -1;
+            const double lo_u = fmax(lo_d, ulo[side]), hi_u = fmin(hi_d, uhi[side]);
+            const double lo_r = fmax(lo_d, rlo), hi_r = fmin(hi_d, rhi);
+            int first = 0x7fffffff, last = -1, rfirst = 0x7fffffff, rlast = -1;
             for (int e0 = 0; e0 < n; e0 += 64) {
               const int e = e0 + lane;
-              bool in = false;
+              bool in = false, inr = false;
               if (e < n) {
                 double D;
                 if constexpr (kF32) D = recs[p0 + e].D; else D = recs[p0 + e].d;
-                in = D > lo_d && D < hi_d;
+                in = D > lo_u && D < hi_u;
+                inr = D > lo_r && D < hi_r;
               }
               const uint64_t m = __ballot(in);
               if (m != 0ull) {
                 first = min(first, e0 + __ffsll((long long)m) - 1);
                 last = e0 + 63 - __clzll((long long)m);
               }
+              if (kTrim && side == 1) {
+                const uint64_t mr = __ballot(inr);
+                if (mr != 0ull) {
+                  rfirst = min(rfirst, e0 + __ffsll((long long)mr) - 1);
+                  rlast = e0 + 63 - __clzll((long long)mr);
+                }
+              }
             }
             rng[2 * side] = first;
             rng[2 * side + 1] = last;
+            if (side == 1) {
+              rng[4] = kTrim ? rfirst : first;
+              rng[5] = kTrim ? rlast : last;
+            }
           }
           const int f_lo = rng[0], f_n = rng[1] + 1 - rng[0];
           const int g_lo = rng[2], g_n = rng[3] + 1 - rng[2];
-          if (f_n <= 0 || g_n <= 0) continue;  // no pixel pair of these forests is in the grid
+          const int gr_lo = rng[4], gr_n = max(0, rng[5] + 1 - rng[4]);  // g rows of the second sweep
+          if (f_n <= 0 || g_n <= 0) continue;  // no pixel pair of these forests is in the grid (or the pass)
           T cf0, cf1, cg0, cg1;  // c of f and g: (1 / W, 1 / S), 0 where the term is off
           {
             const EtaInfo ef = a.einfo[a.sorted[a.pair_p[q]]];
@@ -420,8 +464,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
           for (int b = 0; b < SB; ++b) h0[b] = h1[b] = (T)0;
 #pragma unroll 1
           for (int rs = 0; rs < 2; ++rs) {
-            const int nr = rs ? g_n : f_n, no = rs ? f_n : g_n;
-            const int64_t prow0 = rs ? pr.pg + g_lo : pr.pf + f_lo;
+            const int nr = rs ? gr_n : f_n, no = rs ? f_n : g_n;
+            const int64_t prow0 = rs ? pr.pg + gr_lo : pr.pf + f_lo;
             const int64_t poth0 = rs ? pr.pf + f_lo : pr.pg + g_lo;
             const T co_l = comp ? (rs ? cf1 : cg1) : (rs ? cf0 : cg0);  // c of the other forest, this lane's l
             const int nch = (no + CH - 1) / CH;
