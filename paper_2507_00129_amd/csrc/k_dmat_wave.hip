@@ -374,14 +374,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
           // pixels within r_par reach of the other forest's extent: the first and
           // last such pixel of each forest bound the rows and the lanes' pixels
           const double reach = a.g.emax_par / pr.c * (1.0 + 1e-12) + 1e-9;
-          // A window of several passes (two-wave kernel; in the one-wave kernels the
-          // extra registers cost more than the trimming saves): pixels are kept
-          // only where they can reach
-          // the pass's blocks.  A pixel at distance D against the other forest's
-          // extent [Omin, Omax] has r_perp in [(D + Omin) s, (D + Omax) s]; window
-          // blocks B0 .. B1 hold k_perp rows kt0 + floor(16 B0 / NP) .. kt0 +
-          // floor((16 B1 + 15) / NP), r_perp in [e(B0), e(B1)) of the FP64 edges,
-          // and every bin decision agrees with the FP64 edge comparison.  Both
+          // A window of several passes (two-wave FP32 kernel, FP64 kernels; in the
+          // one-wave FP32 kernels the extra registers spilled): pixels are kept
+          // only where they can reach the pass's blocks.  A pixel at distance D
+          // against the other forest's extent [Omin, Omax] has r_perp in
+          // [(D + Omin) s, (D + Omax) s]; window blocks B0 .. B1 hold k_perp rows
+          // kt0 + floor(16 B0 / NP) .. kt0 + floor((16 B1 + 15) / NP), r_perp in
+          // [e(B0), e(B1)) of the FP64 edges, and every bin decision agrees with
+          // the FP64 edge comparison.  Both
           // forests' pixels are kept where they reach any block of the pass (the
           // f rows also feed H, which every block needs); the g rows of the second
           // sweep only where they reach both ranges of a rectangle pass (a row's
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
                 // within rounding of an edge: the FP64 separations against the edges
 #pragma unroll
                 for (int hi = 0; hi < NH; ++hi) {
-                const int h = NW == 1 ? hi : wv;  // row r + h
+                  const int h = NW == 1 ? hi : wv;  // row r + h
 #pragma unroll
                   for (int k = 0; k < NKE; ++k) {
                     if (need[hi][k]) {
@@ -588,7 +588,6 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
               bool ok[NH][NKE];
 #pragma unroll
               for (int hi = 0; hi < NH; ++hi) {
-                const int h = NW == 1 ? hi : wv;  // row r + h
 #pragma unroll
                 for (int k = 0; k < NKE; ++k) {
                   const int w = L[hi][k] - base_L;
