@@ -17,8 +17,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
 G60 = uniform_grid(15, 60.0)
 # kernel variants: 0 the 8-wave kernel with a full tile; 1 and 2 the
-# single-wave kernel with the upper-triangle tile (large and small tile); 3 the
-# hybrid launch (small tile for one-tile windows, large tile for the rest)
+# upper-triangle tile kernels (large tile: two waves per workgroup in the FP32
+# form, one in FP64; small tile: one wave); 3 the hybrid launch (small tile for
+# one-tile windows, large tile for the rest)
 VARIANTS = [0, 1, 2, 3]
 ETA = {"identity": O.IDENTITY, "mean": O.MEAN, "mean_slope": O.MEAN_SLOPE}
 
@@ -32,21 +33,31 @@ def lib():
 
 
 def run_dmat(lib, F, G, **kw):
+    """A launch with the work counters (the first pass of a window then takes
+    every pixel within r_par reach, and the counters check that every in-grid
+    pixel pair falls inside its forest pair's r_perp window), then the launch
+    as timed, without counters (every pass of a wide window takes only the
+    pixels that can reach its blocks); both outputs are returned."""
     from paper_2507_00129_amd import DeviceForests
     dF = DeviceForests.from_host(F, "cuda:0")
-    out = lib.dmat(dF, G, timing=True, counters=True, **kw)
+    counted = lib.dmat(dF, G, timing=True, counters=True, **kw)
     torch.cuda.synchronize()
     st = lib.last_stats()
-    # every in-grid pixel pair must fall inside its forest pair's r_perp window
     assert st["lost_pairs"] == 0, st
-    return {k: v.cpu().numpy() for k, v in out.items()}
+    out = {k + "_counted": v.cpu().numpy() for k, v in counted.items()}
+    del counted
+    plain = lib.dmat(dF, G, timing=True, **kw)
+    torch.cuda.synchronize()
+    out.update({k: v.cpu().numpy() for k, v in plain.items()})
+    return out
 
 
 def check(out, ref, prec, what):
-    e_d = O.err_rows(out["dmat"], ref.D)
-    e_w = O.err_rel(out["wsum_d"], ref.wd)
-    print(f"[{what} {prec}] rows={int((ref.wd > 0).sum())} e_D={e_d:.3e} e_W={e_w:.3e}", flush=True)
-    assert e_d <= TOL[prec] and e_w <= TOL[prec]
+    for sfx in ("", "_counted"):
+        e_d = O.err_rows(out["dmat" + sfx], ref.D)
+        e_w = O.err_rel(out["wsum_d" + sfx], ref.wd)
+        print(f"[{what}{sfx} {prec}] rows={int((ref.wd > 0).sum())} e_D={e_d:.3e} e_W={e_w:.3e}", flush=True)
+        assert e_d <= TOL[prec] and e_w <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -162,6 +173,22 @@ def test_windows_wider_than_one_tile(lib, prec, n_par):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_windows_nonzero_first_edges(lib, prec):
+    """Windows of one and two k_perp rows of 100 bins (up to 15 passes on the
+    smallest tile) on a grid whose first r_par and r_perp edges are not zero
+    (the kernels' general range tests), against the oracle: the per-pass pixel
+    ranges map window blocks to r_perp through the edges from the window's
+    first k_perp row."""
+    F, _, _ = make_config(1, seed=4, scale=0.02)
+    S = subset_forests(F, nearest_to_centre(F, 40))
+    G = Grid(np.linspace(1.0, 201.0, 101), np.linspace(2.0, 62.0, 16))
+    ref = O.dmat(S, G, O.dmat_pairs(S, G))
+    for v in VARIANTS:
+        out = run_dmat(lib, S, G, precision=prec, variant=v, autotune=False)
+        check(out, ref, prec, f"wide-offset-v{v}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_config0_against_definition(lib, prec, variant):
     """Config 0 against eq. distortion with each forest pair's inner double sum
@@ -202,7 +229,8 @@ def test_config1_subpatch_120(lib, prec, variant):
 def test_full_config1_fp32_vs_fp64(lib):
     """The full eBOSS-like patch (30k forests, all 1.9e7 forest pairs): the
     FP32 form's D against the FP64 form's, row-normwise within 1e-5, w_A
-    within 1e-5, and no in-grid pixel pair outside its window."""
+    within 1e-5 (launches as timed, without counters), and no in-grid pixel
+    pair outside its window (launches with counters)."""
     import time
     from paper_2507_00129_amd import DeviceForests
     F, G, _ = make_config(1, seed=0)
@@ -214,6 +242,9 @@ def test_full_config1_fp32_vs_fp64(lib):
         torch.cuda.synchronize()
         st = lib.last_stats()
         assert st["lost_pairs"] == 0, st
+        del o
+        o = lib.dmat(dF, G, precision=prec, timing=True)
+        torch.cuda.synchronize()
         out[prec] = {k: v.cpu().numpy() for k, v in o.items()}
         print(f"[dmat full {prec}] forest pairs={st['forest_pairs']} in-grid pairs={st['ingrid_pairs']:.4e} "
               f"kernel={st['ms_main']:.0f} ms call={(time.perf_counter() - t) * 1e3:.0f} ms", flush=True)
