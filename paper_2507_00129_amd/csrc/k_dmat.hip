@@ -710,6 +710,10 @@ int dmat_blocks_per_cu(int variant, int precision) {
   return precision == LYA_FP64 ? occupancy<double, 512>() : occupancy<float, 512>();
 }
 
+size_t dmat_hsave_bytes_per_block(int variant, int precision, int run) {
+  return variant >= kNumVariants ? dmat_wave_hsave_bytes_per_block(variant - kNumVariants, precision, run) : 0;
+}
+
 hipError_t launch_finalize_dmat(double* d, const double* wd, int64_t n_rows, int nb, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_dmat_kernel, dim3((unsigned)n_rows), dim3(256), 0, st, d, wd, n_rows, nb);

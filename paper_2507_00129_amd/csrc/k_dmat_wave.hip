@@ -217,6 +217,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
   constexpr int NBUF = NW == 1 ? 2 : 3;    // row-histogram buffers
   constexpr int NH = 2 / NW;               // rows of a step binned by one wave
   constexpr bool kTrim = NW == 2 || !kF32;  // per-pass pixel ranges (below)
+  constexpr bool kReuse = kTrim && NB >= 7;  // pair histograms kept across passes (below)
   constexpr int NX = NB / 2, NY = NB - NX;  // rectangle passes: NX x NY blocks
   constexpr int SB = NB;                 // storage blocks per row and component
   constexpr int SW = 16 * SB + 16;       // storage stride (padded against bank conflicts)
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
         const int64_t mid = (lo + hi) >> 1;
         if (a.wkeys[mid] == key) lo = mid + 1; else hi = mid;
       }
-      const int64_t r1 = lo;
+      int64_t r1 = lo;
       if (key == ~0ull) {
         r0 = r1;
         continue;
@@ -342,6 +343,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
       const int nblk = (nwin + 15) >> 4;
       const int64_t obase = (int64_t)real * nb;
       const int npass = count_passes<NB, NX, NY>(nblk);
+      // Windows of two segments (three or more passes) keep each pair's
+      // histograms H between passes: the first diagonal pass stores H over the
+      // window's first NB blocks, the second over the rest, and the later
+      // passes read them, so that they need only the f rows whose own outer
+      // products reach their blocks.  The store holds hsave_run pairs per wave,
+      // so a run is cut into pieces of at most that many (each its own tile).
+      const bool reuse = kReuse && a.hsave != nullptr && nblk > NB && nblk <= 2 * NB;
+      if (reuse) r1 = min(r1, r0 + (int64_t)a.hsave_run);
+      T* const hsbase =
+          reuse ? (T*)a.hsave + ((int64_t)blockIdx.x * NW + wv) * a.hsave_run * (int64_t)(2 * NB * 64) + lane
+                : nullptr;
 
       for (int ps = 0; ps < npass; ++ps) {
         const WPass P = pass_of<NB, NX, NY>(ps, nblk);
@@ -388,8 +400,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
           // outer product there pairs a bin of each range), or the blocks from
           // ymin on of a diagonal pass.  Widened by a relative 1e-9.  Not in the
           // first pass of a counted launch, which counts the in-window pairs.
+          // (with the histograms kept across passes, the f rows of the later
+          // passes follow the same rule as the g rows)
+          const bool frows = reuse && ps > 0;
           double ulo[2] = {-INFINITY, -INFINITY}, uhi[2] = {INFINITY, INFINITY};
-          double rlo = -INFINITY, rhi = INFINITY;
+          double rlo[2] = {-INFINITY, -INFINITY}, rhi[2] = {INFINITY, INFINITY};
           if (kTrim && npass > 1 && !(a.counters && ps == 0) && pr.s > 0.0) {
             auto edge_lo = [&](int B) { return K.et[kt0 + min(span - 1, (16 * B) / NP)]; };
             auto edge_hi = [&](int B) { return K.et[kt0 + min(span - 1, (16 * B + 15) / NP) + 1]; };
@@ -399,17 +414,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
             uhi[0] = eh - pr.gdmin + 1e-6;
             ulo[1] = el - pr.fdmax - 1e-6;  // g against f
             uhi[1] = eh - pr.fdmin + 1e-6;
-            rlo = edge_lo(P.diag ? P.x0 + P.ymin : P.y0) * (1.0 - 1e-9) / pr.s - pr.fdmax - 1e-6;
-            rhi = edge_hi(P.x0 + P.nx - 1) * (1.0 + 1e-9) / pr.s - pr.fdmin + 1e-6;
+            const double erl = edge_lo(P.diag ? P.x0 + P.ymin : P.y0) * (1.0 - 1e-9) / pr.s;
+            const double erh = edge_hi(P.x0 + P.nx - 1) * (1.0 + 1e-9) / pr.s;
+            rlo[0] = erl - pr.gdmax - 1e-6;
+            rhi[0] = erh - pr.gdmin + 1e-6;
+            rlo[1] = erl - pr.fdmax - 1e-6;
+            rhi[1] = erh - pr.fdmin + 1e-6;
           }
-          int rng[6];
+          int rng[8];
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const int n = side ? pr.ng : pr.nf;
             const int64_t p0 = side ? pr.pg : pr.pf;
             const double lo_d = (side ? pr.fdmin : pr.gdmin) - reach, hi_d = (side ? pr.fdmax : pr.gdmax) + reach;
             const double lo_u = fmax(lo_d, ulo[side]), hi_u = fmin(hi_d, uhi[side]);
-            const double lo_r = fmax(lo_d, rlo), hi_r = fmin(hi_d, rhi);
+            const double lo_r = fmax(lo_d, rlo[side]), hi_r = fmin(hi_d, rhi[side]);
+            const bool rows_own = side == 1 || frows;  // rows on their own rule
             int first = 0x7fffffff, last = -1, rfirst = 0x7fffffff, rlast = -1;
             for (int e0 = 0; e0 < n; e0 += 64) {
               const int e = e0 + lane;
@@ -425,7 +445,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
                 first = min(first, e0 + __ffsll((long long)m) - 1);
                 last = e0 + 63 - __clzll((long long)m);
               }
-              if (kTrim && side == 1) {
+              if (kTrim && rows_own) {
                 const uint64_t mr = __ballot(inr);
                 if (mr != 0ull) {
                   rfirst = min(rfirst, e0 + __ffsll((long long)mr) - 1);
@@ -435,15 +455,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
             }
             rng[2 * side] = first;
             rng[2 * side + 1] = last;
-            if (side == 1) {
-              rng[4] = kTrim ? rfirst : first;
-              rng[5] = kTrim ? rlast : last;
-            }
+            rng[4 + 2 * side] = kTrim && rows_own ? rfirst : first;
+            rng[5 + 2 * side] = kTrim && rows_own ? rlast : last;
           }
           const int f_lo = rng[0], f_n = rng[1] + 1 - rng[0];
           const int g_lo = rng[2], g_n = rng[3] + 1 - rng[2];
-          const int gr_lo = rng[4], gr_n = max(0, rng[5] + 1 - rng[4]);  // g rows of the second sweep
-          if (f_n <= 0 || g_n <= 0) continue;  // no pixel pair of these forests is in the grid (or the pass)
+          const int fr_lo = rng[4], fr_n = max(0, rng[5] + 1 - rng[4]);  // f rows of the first sweep
+          const int gr_lo = rng[6], gr_n = max(0, rng[7] + 1 - rng[6]);  // g rows of the second sweep
+          // no pixel pair of these forests in the grid (or the pass); a pass that
+          // keeps histograms still goes on without rows, to store zeros
+          const bool none = f_n <= 0 || g_n <= 0;
+          if (none && !(reuse && ps < 2)) continue;
           T cf0, cf1, cg0, cg1;  // c of f and g: (1 / W, 1 / S), 0 where the term is off
           {
             const EtaInfo ef = a.einfo[a.sorted[a.pair_p[q]]];
@@ -464,8 +486,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
           for (int b = 0; b < SB; ++b) h0[b] = h1[b] = (T)0;
 #pragma unroll 1
           for (int rs = 0; rs < 2; ++rs) {
-            const int nr = rs ? gr_n : f_n, no = rs ? f_n : g_n;
-            const int64_t prow0 = rs ? pr.pg + gr_lo : pr.pf + f_lo;
+            const int nr = none ? 0 : (rs ? gr_n : fr_n), no = rs ? f_n : g_n;
+            const int64_t prow0 = rs ? pr.pg + gr_lo : pr.pf + fr_lo;
             const int64_t poth0 = rs ? pr.pf + f_lo : pr.pg + g_lo;
             const T co_l = comp ? (rs ? cf1 : cg1) : (rs ? cf0 : cg0);  // c of the other forest, this lane's l
             const int nch = (no + CH - 1) / CH;
@@ -747,6 +769,28 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE, WP
             const T give = lane < 32 ? h1[b] : h0[b];
             h0[b] = mine + xor32(give);
           }
+          if (reuse) {
+            // kept histograms: window block w of this pair at hs[w * 64]; the
+            // first pass stores its blocks, the second its blocks from ymin on
+            // (complete: every pair there has an f row that reaches them) and
+            // reads the ones below, the rectangle passes read both ranges
+            T* const hs = hsbase + (kk - r0) * (int64_t)(2 * NB * 64);
+            if (ps < 2) {
+#pragma unroll
+              for (int b = 0; b < SB; ++b) {
+                if (b < P.ymin) h0[b] = hs[(P.x0 + b) * 64];
+                else if (b < P.nx) hs[(P.x0 + b) * 64] = h0[b];
+              }
+              u_h |= (1u << P.ymin) - 1u;
+            } else {
+#pragma unroll
+              for (int b = 0; b < SB; ++b) {
+                if (b < P.nx) h0[b] = hs[(P.x0 + b) * 64];
+                else if (b >= NX && b - NX < P.ny) h0[b] = hs[(P.y0 + b - NX) * 64];
+              }
+              u_h |= ((1u << P.nx) - 1u) | (((1u << P.ny) - 1u) << NX);
+            }
+          }
           // H term: A = -c_fk c_gl H^kl (k = lane's row slot, l = its component), B = H^kl
           const T s4 = -(rpar ? cf1 : cf0) * (comp ? cg1 : cg0);
 #pragma unroll
@@ -924,6 +968,13 @@ hipError_t launch_dmat_wave(int v, int precision, const DmatArgs& a, int blocks,
                   : launch_wave<double, kNB64[1], kPMax64, 2, 1>(a, blocks, st);
   return v == 0 ? launch_wave<float, kNB32[0], kPMax, 2, 2>(a, blocks, st)
                 : launch_wave<float, kNB32[1], kPMax, 2, 1>(a, blocks, st);
+}
+
+size_t dmat_wave_hsave_bytes_per_block(int v, int precision, int run) {
+  // the large tile keeps them (NB >= 7, per-pass ranges), one copy per wave
+  if (v != 0) return 0;
+  if (precision == LYA_FP64) return (size_t)1 * run * 2 * kNB64[0] * 64 * sizeof(double);
+  return (size_t)2 * run * 2 * kNB32[0] * 64 * sizeof(float);
 }
 
 int dmat_wave_blocks_per_cu(int v, int precision) {

@@ -304,7 +304,12 @@ struct DmatArgs {
   double* dnum;    // [R][nb][nb] numerator of D
   double* wd;      // [R][nb] sum w_i w_j over the kept pairs
   unsigned long long* counters;  // optional [3]: in-grid pixel pairs, outer-product FMAs, out-of-window pairs
+  // optional (nullptr: off): the pair histograms of windows of two segments,
+  // kept between passes, hsave_run pairs per wave (dmat_hsave_bytes_per_block)
+  void* hsave;
+  int32_t hsave_run;
 };
+constexpr int kDmatHsaveRun = 64;
 // window key of every kept pair: (realisation << 40) | (first k_perp << 16) | span;
 // pairs with no possible in-grid pixel pair get ~0
 hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st);
@@ -334,6 +339,9 @@ int peak_unroll_valu();
 // the symmetric-tile D kernels of one or two waves (two tile shapes per form)
 int dmat_wave_num_variants();
 int dmat_wave_tile_blocks(int v, int precision);  // tile blocks per side of a symmetric-tile variant
+// bytes of the kept pair histograms per workgroup of a variant (0: it keeps none)
+size_t dmat_wave_hsave_bytes_per_block(int v, int precision, int run);
+size_t dmat_hsave_bytes_per_block(int variant, int precision, int run);
 const char* dmat_wave_variant_name(int v);
 hipError_t launch_dmat_wave(int variant, int precision, const DmatArgs& a, int blocks, hipStream_t st);
 int dmat_wave_blocks_per_cu(int variant, int precision);

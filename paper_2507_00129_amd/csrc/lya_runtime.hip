@@ -1080,6 +1080,20 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     a.g = gd;
     a.dnum = dmat;
     a.wd = wsum_d;
+    {
+      // the kept pair histograms of two-segment windows: one store sized for
+      // the largest need over the variants (each launch indexes it by workgroup)
+      size_t hs = 0;
+      for (int v = 0; v < dmat_num_variants(); ++v) {
+        const size_t b = dmat_hsave_bytes_per_block(v, o->precision, kDmatHsaveRun) *
+                         (size_t)dmat_blocks_per_cu(v, o->precision) * (size_t)ctx->n_cu;
+        if (b > hs) hs = b;
+      }
+      unsigned char* p = nullptr;
+      if (hs > 0) LYA_TRY(wst(ctx, "dm_hsave", hs, &p));
+      a.hsave = p;
+      a.hsave_run = kDmatHsaveRun;
+    }
     // variants: the kernels of dmat_num_variants(), then the hybrid launch:
     // the pairs whose window fits the small tile in one pass (the
     // sorted list puts them last) go to that kernel, two waves per SIMD, and
