@@ -329,7 +329,10 @@ lya_status lya_xi3_subsamples(lya_context *ctx, const lya_forests *forests, cons
    device:
      dmat[r][A][B] = D_AB of realisation r, [n_realisations * n_bins * n_bins]
      wsum_d[r][A]  = w_A over the kept pairs, [n_realisations * n_bins]
-   Rows with wsum_d == 0 are zero.  delta is not read. */
+   Rows with wsum_d == 0 are zero.  delta is not read.  Besides the work
+   lists, the context's workspace holds the pair histograms that the
+   large-tile kernels keep between passes: ~0.7 GB (FP32 form) or ~0.5 GB
+   (FP64 form) on a 256-CU device, whatever the input size. */
 lya_status lya_dmat(lya_context *ctx, const lya_forests *forests, const lya_grid *grid,
                     const lya_options *opts, void *stream,
                     double *dmat, double *wsum_d);

@@ -39,8 +39,12 @@
 //
 // Tiles: NB x NB blocks of 16 window bins (the upper triangle, NB (NB+1)/2
 // accumulators).  Windows wider than NB blocks take several passes over the
-// run, each re-binning its rows: a diagonal pass per segment of NB blocks,
-// and rectangle passes of NB x NY blocks between segments.
+// run, each re-binning the rows that can reach its blocks: a diagonal pass
+// per segment of NB blocks, and rectangle passes of NX x NY blocks between
+// segments.  In windows of two segments the large-tile kernels keep each
+// pair's H (over the whole window, from the two diagonal passes) in a device
+// store, so the later passes need only the rows whose own outer products
+// reach their blocks.
 #include <type_traits>
 
 #include "lya_bin.h"
