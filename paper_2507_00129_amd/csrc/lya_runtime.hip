@@ -1080,20 +1080,27 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     a.g = gd;
     a.dnum = dmat;
     a.wd = wsum_d;
+    // the kept pair histograms of two-segment windows: one store sized for
+    // the largest need over the variants (a launch indexes it by workgroup;
+    // dmat_launch passes it only to a launch it covers)
+    size_t hs_bytes = 0;
+    for (int v = 0; v < dmat_num_variants(); ++v) {
+      const size_t b = dmat_hsave_bytes_per_block(v, o->precision, kDmatHsaveRun) *
+                       (size_t)dmat_blocks_per_cu(v, o->precision) * (size_t)ctx->n_cu;
+      if (b > hs_bytes) hs_bytes = b;
+    }
     {
-      // the kept pair histograms of two-segment windows: one store sized for
-      // the largest need over the variants (each launch indexes it by workgroup)
-      size_t hs = 0;
-      for (int v = 0; v < dmat_num_variants(); ++v) {
-        const size_t b = dmat_hsave_bytes_per_block(v, o->precision, kDmatHsaveRun) *
-                         (size_t)dmat_blocks_per_cu(v, o->precision) * (size_t)ctx->n_cu;
-        if (b > hs) hs = b;
-      }
       unsigned char* p = nullptr;
-      if (hs > 0) LYA_TRY(wst(ctx, "dm_hsave", hs, &p));
+      if (hs_bytes > 0) LYA_TRY(wst(ctx, "dm_hsave", hs_bytes, &p));
       a.hsave = p;
       a.hsave_run = kDmatHsaveRun;
     }
+    auto dmat_launch = [&](int v, const DmatArgs& args) -> hipError_t {
+      const int blocks = dmat_blocks_per_cu(v, o->precision) * ctx->n_cu;
+      DmatArgs x = args;
+      if (dmat_hsave_bytes_per_block(v, o->precision, x.hsave_run) * (size_t)blocks > hs_bytes) x.hsave = nullptr;
+      return launch_dmat(v, o->precision, x, blocks, st);
+    };
     // variants: the kernels of dmat_num_variants(), then the hybrid launch:
     // the pairs whose window fits the small tile in one pass (the
     // sorted list puts them last) go to that kernel, two waves per SIMD, and
@@ -1103,7 +1110,7 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
     auto launch_variant = [&](int v, const DmatArgs& args) -> lya_status {
       if (v < kHybrid) {
         HIP_TRY(launch_zero(counter, 4, st));
-        HIP_TRY(launch_dmat(v, o->precision, args, dmat_blocks_per_cu(v, o->precision) * ctx->n_cu, st));
+        HIP_TRY(dmat_launch(v, args));
         return LYA_OK;
       }
       constexpr int kSmall = 2, kBig = 1;  // dmat variants of the small and the large symmetric tile
@@ -1126,8 +1133,8 @@ lya_status lya_dmat(lya_context* ctx, const lya_forests* F, const lya_grid* G, c
       narrow.n_items = (narrow.n_pairs + args.chunk - 1) / args.chunk / args.item_stride;
       narrow.counter = counter + 1;
       HIP_TRY(launch_zero(counter, 8, st));
-      HIP_TRY(launch_dmat(kBig, o->precision, wide, dmat_blocks_per_cu(kBig, o->precision) * ctx->n_cu, st));
-      HIP_TRY(launch_dmat(kSmall, o->precision, narrow, dmat_blocks_per_cu(kSmall, o->precision) * ctx->n_cu, st));
+      HIP_TRY(dmat_launch(kBig, wide));
+      HIP_TRY(dmat_launch(kSmall, narrow));
       return LYA_OK;
     };
     int variant = 0;
