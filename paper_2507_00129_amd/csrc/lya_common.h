@@ -310,8 +310,8 @@ struct DmatArgs {
   int32_t hsave_run;
 };
 constexpr int kDmatHsaveRun = 64;
-// window key of every kept pair: (realisation << 40) | (first k_perp << 16) | span;
-// pairs with no possible in-grid pixel pair get ~0
+// window key of every kept pair (dmat_window_key below); pairs with no
+// possible in-grid pixel pair get ~0
 hipError_t launch_dmat_keys(const DmatArgs& a, uint64_t* keys, int32_t* idx, hipStream_t st);
 // Window key of a kept forest pair: (span of k_perp rows, descending;
 // realisation; first k_perp row), so that the sorted list groups pairs by
