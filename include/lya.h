@@ -46,7 +46,9 @@
  * human-readable message for the last failure on a context.
  *
  * Threading.  A context may be used by one host thread at a time.  Two
- * contexts may run concurrently.
+ * contexts may run concurrently.  The calls of one context share its device
+ * workspace: a call enqueued on another stream than the previous one must
+ * not run before the previous call's work has finished.
  */
 #ifndef LYA_H
 #define LYA_H
